@@ -1,0 +1,167 @@
+/*
+ * qsv.h -- C ABI of libqsv, an MI355X (gfx950) state-vector simulator core.
+ *
+ * Method: Suzuki et al., "Qulacs: a fast and versatile quantum circuit
+ * simulator for research purpose" (Quantum, 2021). Section references below
+ * are to that paper.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * - A state of n qubits is 2^n complex amplitudes in device memory, stored
+ *   interleaved (re, im): complex64 = 2 x float, complex128 = 2 x double. This
+ *   is the layout of torch.complex64 / torch.complex128 tensors.
+ * - Basis index x = sum_q x_q 2^q: qubit 0 is the right-most digit of the ket
+ *   (section 4.2.1).
+ * - Gate matrices are passed from the host as complex128, row-major,
+ *   interleaved, 2^k x 2^k doubles pairs. Bit j of the row / column index
+ *   corresponds to targets[j] (qubit targets[0] is the least significant bit
+ *   of the matrix index), so DenseMatrix({t, c}, CNOT-as-printed) in
+ *   Appendix A flips t when c is set. Complex64 states round the matrix to
+ *   float on the host.
+ * - Rotations are R_P(theta) = exp(+i theta P / 2) as in the table of named
+ *   gates (section 4.3.4).
+ * - Host arrays passed in (matrices, qubit lists, coefficients) are copied
+ *   before the call returns; the caller keeps ownership.
+ * - Every function returns 0 (QSV_OK) or a negative error code. On error
+ *   nothing has been enqueued and no state has been modified; the message is
+ *   available from qsv_last_error() (thread-local). No C++ exception crosses
+ *   this boundary and the library never aborts the process.
+ * - Work is enqueued asynchronously on the stream the state was created with.
+ *   Calls that return values to the host (qsv_store, qsv_norm2, qsv_inner,
+ *   qsv_expectation, qsv_adjoint_gradient) synchronise that stream.
+ */
+#ifndef QSV_H_
+#define QSV_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qsv_state qsv_state;
+typedef struct qsv_circuit qsv_circuit;
+typedef struct qsv_plan qsv_plan;
+typedef struct qsv_observable qsv_observable;
+
+typedef enum { QSV_C64 = 1, QSV_C128 = 2 } qsv_dtype;
+
+enum {
+  QSV_OK = 0,
+  QSV_EINVAL = -1, /* malformed argument (null pointer, bad kind, bad size)  */
+  QSV_ERANGE = -2, /* qubit index, basis index or count out of range        */
+  QSV_EDUP = -3,   /* a qubit listed twice among targets and controls       */
+  QSV_ENOMEM = -4, /* device or host allocation failed                      */
+  QSV_EHIP = -5,   /* a HIP runtime call failed                             */
+  QSV_EDTYPE = -6, /* dtype mismatch between states                         */
+  QSV_ENODEV = -7  /* no usable gfx950 device                               */
+};
+
+/* Named gates of the table of named gates (section 4.3.4). */
+enum {
+  QSV_GATE_X = 1,    /* Pauli X, qubits {q}                                    */
+  QSV_GATE_Y = 2,    /* Pauli Y, qubits {q}                                    */
+  QSV_GATE_Z = 3,    /* Pauli Z, qubits {q}                                    */
+  QSV_GATE_H = 4,    /* Hadamard, qubits {q}                                   */
+  QSV_GATE_RX = 5,   /* exp(+i theta X/2), qubits {q}                          */
+  QSV_GATE_RY = 6,   /* exp(+i theta Y/2), qubits {q}                          */
+  QSV_GATE_RZ = 7,   /* exp(+i theta Z/2), qubits {q}                          */
+  QSV_GATE_CNOT = 8, /* qubits {control, target}                              */
+  QSV_GATE_CZ = 9,   /* qubits {a, b}                                          */
+  QSV_GATE_SWAP = 10 /* qubits {a, b}                                          */
+};
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* qsv_last_error(void);
+
+/* ABI version (major * 100 + minor). */
+int qsv_version(void);
+
+/* ---------------------------------------------------------------- states */
+
+/* Allocate a 2^n-amplitude state on the current HIP device, initialised to
+ * |0...0> (section 4.2.1). 1 <= n <= 34. stream: a hipStream_t (NULL = the
+ * default stream). The library owns the memory; free with qsv_state_free.
+ * QSV_ENOMEM if the device cannot hold it. */
+int qsv_state_alloc(int n, qsv_dtype dtype, void* stream, qsv_state** out);
+
+/* Wrap caller-owned device memory of 2^n amplitudes (e.g. a torch tensor's
+ * storage, 256-byte aligned). Contents are left untouched. The caller keeps
+ * the memory alive until qsv_state_free. */
+int qsv_state_wrap(void* dev_ptr, int n, qsv_dtype dtype, void* stream, qsv_state** out);
+
+/* Release a state (frees the memory only if the library allocated it). NULL is
+ * accepted. The state's stream is synchronised first. */
+int qsv_state_free(qsv_state* s);
+
+/* Report qubit count, dtype and device pointer (any out pointer may be NULL). */
+int qsv_state_info(const qsv_state* s, int* n, int* dtype, void** dev_ptr);
+
+/* Set the state to the computational basis state |k> (section 4.2.1). */
+int qsv_set_basis(qsv_state* s, uint64_t k);
+
+/* Upload 2^n complex128 amplitudes (2 * 2^n doubles, interleaved) from host
+ * memory (section 4.2.1, load). */
+int qsv_load(qsv_state* s, const double* host_interleaved);
+
+/* Download the amplitudes as complex128 into host memory (complex64 states are
+ * widened exactly). Synchronises the state's stream (section 4.2.2,
+ * get_vector). */
+int qsv_store(const qsv_state* s, double* host_interleaved);
+
+/* dst <- src (same n and dtype), enqueued on dst's stream (section 4.2.1, copy). */
+int qsv_copy(qsv_state* dst, const qsv_state* src);
+
+/* ---------------------------------------------------------------- gates */
+
+/* Apply a basic gate psi <- K psi (section 4.3.2, Eq. update_mat) with gate
+ * matrix mat (2^k x 2^k, see conventions) on targets[0..k-1], acting only on
+ * the amplitudes whose control qubits controls[i] hold ctrl_vals[i] in {0, 1}
+ * (controlled gates, section 4.3.2). 1 <= k <= 5; targets and controls
+ * distinct and in [0, n). K need not be unitary. The library recognises the
+ * structured matrices the paper lists (diagonal, Pauli-X / CNOT / SWAP
+ * permutations, one-entry phases such as Z or CZ) and applies them with fewer
+ * memory operations. controls / ctrl_vals may be NULL when nc == 0. */
+int qsv_apply_gate(qsv_state* s, const double* mat, const int* targets, int k,
+                   const int* controls, const int* ctrl_vals, int nc);
+
+/* Apply a named gate (QSV_GATE_*) on qubits[0..nq-1]; theta is used by the
+ * rotations only. */
+int qsv_apply_named(qsv_state* s, int kind, const int* qubits, int nq, double theta);
+
+/* ---------------------------------------------------------------- reductions */
+
+/* Squared norm <psi|psi> accumulated in double (section 4.2.2). */
+int qsv_norm2(const qsv_state* s, double* out);
+
+/* Inner product <bra|ket> accumulated in double (section 4.2.2). Same n and
+ * dtype. */
+int qsv_inner(const qsv_state* bra, const qsv_state* ket, double* re, double* im);
+
+/* ---------------------------------------------------------------- observables */
+
+/* An observable O = sum_k alpha_k P_k, a real linear combination of Pauli
+ * strings (section 4.5). Host-side object; freed with qsv_observable_free. */
+int qsv_observable_create(int n, qsv_observable** out);
+int qsv_observable_free(qsv_observable* o);
+
+/* Add alpha * P with P = prod_j sigma_{pauli_ids[j]}(qubits[j]); pauli ids
+ * 0..3 = I, X, Y, Z (section 4.3.2, Pauli gate). w = 0 adds alpha * identity.
+ * Qubits distinct and < n. */
+int qsv_observable_add_term(qsv_observable* o, double coef, const int* qubits,
+                            const int* pauli_ids, int w);
+
+/* Number of qubits, terms and distinct flip masks (X/Y positions); any out
+ * pointer may be NULL. Terms sharing a flip mask share one pass over the state. */
+int qsv_observable_info(const qsv_observable* o, int* n, int* terms, int* groups);
+
+/* <psi|O|psi> accumulated in double (section 4.5, get_expectation_value). The
+ * state is not normalised first (basic gates need not be unitary). Synchronises
+ * the state's stream. */
+int qsv_expectation(const qsv_state* s, const qsv_observable* o, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSV_H_ */

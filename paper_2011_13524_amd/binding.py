@@ -1,0 +1,237 @@
+"""Thin ctypes binding of libqsv (include/qsv.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libqsv.so. Missing library -> ImportError at first use; there is no
+fallback path.
+
+The functions keep the C names (qsv_state_alloc, qsv_apply_gate, ...). A few
+small classes (State, Circuit, Observable, Plan) own the handles and convert
+numpy arrays / gate records into the C arguments.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqsv.so")
+
+QSV_C64 = 1
+QSV_C128 = 2
+GATE = {"x": 1, "y": 2, "z": 3, "h": 4, "rx": 5, "ry": 6, "rz": 7, "cnot": 8, "cz": 9, "swap": 10}
+PAULI_ID = {"rx": 1, "ry": 2, "rz": 3}
+
+_c = ctypes
+_vp = _c.c_void_p
+_ip = _c.POINTER(_c.c_int)
+_dp = _c.POINTER(_c.c_double)
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "qsv_last_error": (_c.c_char_p, []),
+    "qsv_version": (_c.c_int, []),
+    "qsv_state_alloc": (_c.c_int, [_c.c_int, _c.c_int, _vp, _c.POINTER(_vp)]),
+    "qsv_state_wrap": (_c.c_int, [_vp, _c.c_int, _c.c_int, _vp, _c.POINTER(_vp)]),
+    "qsv_state_free": (_c.c_int, [_vp]),
+    "qsv_state_info": (_c.c_int, [_vp, _ip, _ip, _c.POINTER(_vp)]),
+    "qsv_set_basis": (_c.c_int, [_vp, _c.c_uint64]),
+    "qsv_load": (_c.c_int, [_vp, _dp]),
+    "qsv_store": (_c.c_int, [_vp, _dp]),
+    "qsv_copy": (_c.c_int, [_vp, _vp]),
+    "qsv_apply_gate": (_c.c_int, [_vp, _dp, _ip, _c.c_int, _ip, _ip, _c.c_int]),
+    "qsv_apply_named": (_c.c_int, [_vp, _c.c_int, _ip, _c.c_int, _c.c_double]),
+    "qsv_norm2": (_c.c_int, [_vp, _dp]),
+    "qsv_inner": (_c.c_int, [_vp, _vp, _dp, _dp]),
+    "qsv_observable_create": (_c.c_int, [_c.c_int, _c.POINTER(_vp)]),
+    "qsv_observable_free": (_c.c_int, [_vp]),
+    "qsv_observable_add_term": (_c.c_int, [_vp, _c.c_double, _ip, _ip, _c.c_int]),
+    "qsv_observable_info": (_c.c_int, [_vp, _ip, _ip, _ip]),
+    "qsv_expectation": (_c.c_int, [_vp, _vp, _dp]),
+}
+
+_lib = None
+
+
+class QsvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libqsv error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libqsv.so (built in-tree by paper_2011_13524_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2011_13524_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def declared_symbols():
+    return list(_SIGS)
+
+
+def check(rc: int) -> None:
+    if rc != 0:
+        raise QsvError(rc, lib().qsv_last_error().decode())
+
+
+def _ints(xs):
+    a = np.ascontiguousarray(np.asarray(list(xs) if xs is not None else [], dtype=np.int32))
+    if a.size == 0:
+        a = np.zeros(1, dtype=np.int32)
+    return a
+
+
+def _iptr(a):
+    return a.ctypes.data_as(_ip)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+class State:
+    """A device state vector (qsv_state)."""
+
+    def __init__(self, n: int, dtype: str = "c128", stream=None, _handle=None, _keep=None):
+        self.n = n
+        self.dtype = dtype
+        self._keep = _keep
+        if _handle is not None:
+            self.h = _handle
+            return
+        h = _vp()
+        check(lib().qsv_state_alloc(n, QSV_C64 if dtype == "c64" else QSV_C128,
+                                    _stream_handle(stream), _c.byref(h)))
+        self.h = h
+
+    @classmethod
+    def wrap(cls, tensor, stream=None):
+        """Borrow a contiguous torch complex64/complex128 CUDA tensor of 2^n elements."""
+        import torch
+        assert tensor.is_contiguous() and tensor.dim() == 1
+        n = int(tensor.numel()).bit_length() - 1
+        assert (1 << n) == tensor.numel()
+        dt = {torch.complex64: "c64", torch.complex128: "c128"}[tensor.dtype]
+        h = _vp()
+        check(lib().qsv_state_wrap(_c.c_void_p(tensor.data_ptr()), n,
+                                   QSV_C64 if dt == "c64" else QSV_C128,
+                                   _stream_handle(stream), _c.byref(h)))
+        return cls(n, dt, _handle=h, _keep=tensor)
+
+    def free(self):
+        if self.h is not None and lib is not None:
+            check(lib().qsv_state_free(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None:
+                lib().qsv_state_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def set_basis(self, k: int):
+        check(lib().qsv_set_basis(self.h, k))
+
+    def load(self, vec):
+        v = np.ascontiguousarray(np.asarray(vec, dtype=np.complex128))
+        assert v.size == (1 << self.n)
+        check(lib().qsv_load(self.h, _dptr(v.view(np.float64))))
+
+    def store(self) -> np.ndarray:
+        out = np.empty(1 << self.n, dtype=np.complex128)
+        check(lib().qsv_store(self.h, _dptr(out.view(np.float64))))
+        return out
+
+    def copy_from(self, other: "State"):
+        check(lib().qsv_copy(self.h, other.h))
+
+    def apply_gate(self, mat, targets, controls=(), ctrl_vals=()):
+        m = np.ascontiguousarray(np.asarray(mat, dtype=np.complex128))
+        t, c, v = _ints(targets), _ints(controls), _ints(ctrl_vals)
+        check(lib().qsv_apply_gate(self.h, _dptr(m.view(np.float64)), _iptr(t), len(targets),
+                                   _iptr(c), _iptr(v), len(controls)))
+
+    def apply_named(self, name: str, qubits, theta: float = 0.0):
+        q = _ints(qubits)
+        check(lib().qsv_apply_named(self.h, GATE[name], _iptr(q), len(qubits), float(theta)))
+
+    def norm2(self) -> float:
+        out = _c.c_double()
+        check(lib().qsv_norm2(self.h, _c.byref(out)))
+        return out.value
+
+    def inner(self, ket: "State") -> complex:
+        re, im = _c.c_double(), _c.c_double()
+        check(lib().qsv_inner(self.h, ket.h, _c.byref(re), _c.byref(im)))
+        return complex(re.value, im.value)
+
+
+class Observable:
+    """Real combination of Pauli strings: terms = [(coef, [(qubit, pauli_id), ...]), ...]."""
+
+    def __init__(self, n: int, terms=()):
+        self.n = n
+        h = _vp()
+        check(lib().qsv_observable_create(n, _c.byref(h)))
+        self.h = h
+        for coef, qp in terms:
+            self.add_term(coef, qp)
+
+    def add_term(self, coef: float, qp):
+        q = _ints([a for a, _ in qp])
+        p = _ints([b for _, b in qp])
+        check(lib().qsv_observable_add_term(self.h, float(coef), _iptr(q), _iptr(p), len(qp)))
+
+    def info(self):
+        n, t, g = _c.c_int(), _c.c_int(), _c.c_int()
+        check(lib().qsv_observable_info(self.h, _c.byref(n), _c.byref(t), _c.byref(g)))
+        return n.value, t.value, g.value
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None:
+                lib().qsv_observable_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def expectation(state: State, obs: Observable) -> float:
+    out = _c.c_double()
+    check(lib().qsv_expectation(state.h, obs.h, _c.byref(out)))
+    return out.value
+
+
+def apply_record(state: State, g, theta=None):
+    """Apply one gate record (see workloads.py) through the C ABI."""
+    op = g["op"]
+    if op in ("rx", "ry", "rz"):
+        ang = theta[g["slot"]] if "slot" in g else g["angle"]
+        state.apply_named(op, g["q"], ang)
+    elif op in GATE:
+        state.apply_named(op, g["q"])
+    elif op == "dense":
+        state.apply_gate(g["mat"], g["q"], g.get("controls", ()), g.get("ctrl_vals", ()))
+    else:
+        raise ValueError(op)
