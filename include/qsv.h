@@ -138,6 +138,75 @@ int qsv_norm2(const qsv_state* s, double* out);
  * dtype. */
 int qsv_inner(const qsv_state* bra, const qsv_state* ket, double* re, double* im);
 
+/* ---------------------------------------------------------------- circuits */
+
+/* A circuit is an ordered host-side list of basic gates (section 4.4,
+ * QuantumCircuit), some of them parametric rotations whose angles are read
+ * from a parameter vector at apply time (ParametricQuantumCircuit). */
+int qsv_circuit_create(int n, qsv_circuit** out);
+int qsv_circuit_free(qsv_circuit* c);
+
+/* Append a basic gate: same arguments and limits as qsv_apply_gate. */
+int qsv_circuit_add_gate(qsv_circuit* c, const double* mat, const int* targets, int k,
+                         const int* controls, const int* ctrl_vals, int nc);
+
+/* Append a named gate (QSV_GATE_*); RX/RY/RZ with the fixed angle theta. */
+int qsv_circuit_add_named(qsv_circuit* c, int kind, const int* qubits, int nq, double theta);
+
+/* Append a parametric rotation exp(+i theta[param_slot] P / 2) on one qubit,
+ * P = X, Y, Z for pauli_id = 1, 2, 3 (ParametricRX/RY/RZ, section 4.4). The
+ * circuit's parameter count becomes at least param_slot + 1. */
+int qsv_circuit_add_rotation(qsv_circuit* c, int pauli_id, int qubit, int param_slot);
+
+/* Qubit count, gate count and parameter count (any out pointer may be NULL). */
+int qsv_circuit_info(const qsv_circuit* c, int* n, int* gates, int* nparams);
+
+/* Apply every gate in order, one kernel launch per gate (section 4.4,
+ * update_quantum_state). theta: the parameter vector (may be NULL when the
+ * circuit has no parameters). */
+int qsv_apply_circuit(qsv_state* s, const qsv_circuit* c, const double* theta);
+
+/* ---------------------------------------------------------------- fusion */
+
+/* Plan the fused execution of a circuit (section 5.4, circuit optimization)
+ * for states of dtype `dtype`:
+ *  - gates are merged into dense blocks of at most max_k qubits (1..5) where a
+ *    gate depends on a single earlier block (merge of two successive gates);
+ *    diagonal gates only merge with blocks whose qubits they do not widen;
+ *  - blocks are grouped into tile passes: each pass keeps tile_qubits qubits
+ *    local (0 = default: 13 for complex64, 12 for complex128), always including
+ *    the low_qubits lowest qubits (0 = default: 6 / 5) so that HBM runs are
+ *    contiguous, and applies every block whose non-diagonal targets are local.
+ *    One pass reads and writes the state once.
+ * The plan copies the circuit's structure; later edits of the circuit do not
+ * affect it. Parameters are read at apply time. */
+int qsv_plan_fused(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qubits,
+                   int low_qubits, qsv_plan** out);
+
+/* Number of passes, fused blocks and original gates (any out pointer may be NULL). */
+int qsv_plan_info(const qsv_plan* p, int* passes, int* blocks, int* gates);
+int qsv_plan_free(qsv_plan* p);
+
+/* Apply a plan to a state of the plan's qubit count and dtype: block matrices
+ * are formed on the host in double precision for theta (products of the gate
+ * matrices, later gate on the left), uploaded, and one tile kernel per pass is
+ * enqueued on the state's stream. A plan must not be applied concurrently from
+ * two streams. */
+int qsv_apply_fused(qsv_state* s, qsv_plan* p, const double* theta);
+
+/* ---------------------------------------------------------------- profiling */
+
+/* Opt-in per-kernel timing with HIP events recorded on the launching stream
+ * around every kernel launch, and the algorithmic bytes each launch must move
+ * (the cost model of section 4.3.2: every amplitude a gate touches is read and
+ * written once). qsv_prof_enable(1) clears the records and starts recording;
+ * qsv_prof_enable(0) stops. qsv_prof_read synchronises the recorded events and
+ * reports, for kernel family `name` (e.g. "pair", "tile"), the number of
+ * launches, their summed duration in milliseconds and summed algorithmic
+ * bytes. Not thread-safe; meant for benchmarks. */
+int qsv_prof_enable(int on);
+int qsv_prof_read(const char* name, int* launches, double* total_ms, double* bytes);
+
 /* ---------------------------------------------------------------- observables */
 
 /* An observable O = sum_k alpha_k P_k, a real linear combination of Pauli

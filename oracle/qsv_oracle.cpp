@@ -18,6 +18,9 @@
 #include <cstdint>
 #include <cstring>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef std::complex<double> cplx;
 
@@ -29,6 +32,15 @@ inline const cplx* as_c(const double* p) { return reinterpret_cast<const cplx*>(
 }  // namespace
 
 extern "C" {
+
+// Threads the parallel B0 loop uses (for reporting CPU timings).
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 // |k> : all amplitudes zero except amplitude k, which is one (section 4.2.1).
 void orc_set_basis(double* psi, int n, uint64_t k) {

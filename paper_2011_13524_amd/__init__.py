@@ -1,5 +1,6 @@
 """MI355X (gfx950) state-vector simulation core for the method of Qulacs
 (Suzuki et al., 2021): HIP kernels behind a C ABI (include/qsv.h), with this
 package as a thin ctypes binding."""
-from .binding import (LIB_PATH, Observable, QsvError, State, apply_record, expectation,  # noqa: F401
-                      lib)
+from .binding import (LIB_PATH, Circuit, Observable, Plan, QsvError, State,  # noqa: F401
+                      apply_circuit, apply_fused, apply_record, expectation, lib, prof_enable,
+                      prof_read)

@@ -49,6 +49,19 @@ _SIGS = {
     "qsv_observable_add_term": (_c.c_int, [_vp, _c.c_double, _ip, _ip, _c.c_int]),
     "qsv_observable_info": (_c.c_int, [_vp, _ip, _ip, _ip]),
     "qsv_expectation": (_c.c_int, [_vp, _vp, _dp]),
+    "qsv_circuit_create": (_c.c_int, [_c.c_int, _c.POINTER(_vp)]),
+    "qsv_circuit_free": (_c.c_int, [_vp]),
+    "qsv_circuit_add_gate": (_c.c_int, [_vp, _dp, _ip, _c.c_int, _ip, _ip, _c.c_int]),
+    "qsv_circuit_add_named": (_c.c_int, [_vp, _c.c_int, _ip, _c.c_int, _c.c_double]),
+    "qsv_circuit_add_rotation": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int]),
+    "qsv_circuit_info": (_c.c_int, [_vp, _ip, _ip, _ip]),
+    "qsv_apply_circuit": (_c.c_int, [_vp, _vp, _dp]),
+    "qsv_plan_fused": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.POINTER(_vp)]),
+    "qsv_plan_info": (_c.c_int, [_vp, _ip, _ip, _ip]),
+    "qsv_plan_free": (_c.c_int, [_vp]),
+    "qsv_apply_fused": (_c.c_int, [_vp, _vp, _dp]),
+    "qsv_prof_enable": (_c.c_int, [_c.c_int]),
+    "qsv_prof_read": (_c.c_int, [_c.c_char_p, _ip, _dp, _dp]),
 }
 
 _lib = None
@@ -221,6 +234,111 @@ def expectation(state: State, obs: Observable) -> float:
     out = _c.c_double()
     check(lib().qsv_expectation(state.h, obs.h, _c.byref(out)))
     return out.value
+
+
+class Circuit:
+    """Host-side gate list (qsv_circuit). Build from gate records with
+    Circuit.from_records(n, gates)."""
+
+    def __init__(self, n: int):
+        self.n = n
+        h = _vp()
+        check(lib().qsv_circuit_create(n, _c.byref(h)))
+        self.h = h
+
+    @classmethod
+    def from_records(cls, n: int, gates):
+        c = cls(n)
+        for g in gates:
+            c.add_record(g)
+        return c
+
+    def add_record(self, g):
+        op = g["op"]
+        if op in ("rx", "ry", "rz") and "slot" in g:
+            check(lib().qsv_circuit_add_rotation(self.h, PAULI_ID[op], int(g["q"][0]), int(g["slot"])))
+        elif op in GATE:
+            q = _ints(g["q"])
+            check(lib().qsv_circuit_add_named(self.h, GATE[op], _iptr(q), len(g["q"]),
+                                              float(g.get("angle", 0.0))))
+        elif op == "dense":
+            m = np.ascontiguousarray(np.asarray(g["mat"], dtype=np.complex128))
+            t = _ints(g["q"])
+            ctrl = list(g.get("controls", ()))
+            vals = list(g.get("ctrl_vals", ()))
+            c, v = _ints(ctrl), _ints(vals)
+            check(lib().qsv_circuit_add_gate(self.h, _dptr(m.view(np.float64)), _iptr(t),
+                                             len(g["q"]), _iptr(c), _iptr(v), len(ctrl)))
+        else:
+            raise ValueError(op)
+
+    def info(self):
+        n, g, p = _c.c_int(), _c.c_int(), _c.c_int()
+        check(lib().qsv_circuit_info(self.h, _c.byref(n), _c.byref(g), _c.byref(p)))
+        return n.value, g.value, p.value
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None:
+                lib().qsv_circuit_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def _theta_ptr(theta):
+    if theta is None:
+        return None, None
+    t = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+    if t.size == 0:
+        t = np.zeros(1)
+    return t, _dptr(t)
+
+
+def apply_circuit(state: State, circ: Circuit, theta=None):
+    keep, tp = _theta_ptr(theta)
+    check(lib().qsv_apply_circuit(state.h, circ.h, tp))
+
+
+class Plan:
+    """Fused execution plan (qsv_plan) of a circuit for one dtype."""
+
+    def __init__(self, circ: Circuit, dtype: str = "c128", max_k: int = 2, tile_qubits: int = 0,
+                 low_qubits: int = 0):
+        h = _vp()
+        check(lib().qsv_plan_fused(circ.h, QSV_C64 if dtype == "c64" else QSV_C128, max_k,
+                                   tile_qubits, low_qubits, _c.byref(h)))
+        self.h = h
+        self.dtype = dtype
+
+    def info(self):
+        p, b, g = _c.c_int(), _c.c_int(), _c.c_int()
+        check(lib().qsv_plan_info(self.h, _c.byref(p), _c.byref(b), _c.byref(g)))
+        return {"passes": p.value, "blocks": b.value, "gates": g.value}
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None:
+                lib().qsv_plan_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def apply_fused(state: State, plan: Plan, theta=None):
+    keep, tp = _theta_ptr(theta)
+    check(lib().qsv_apply_fused(state.h, plan.h, tp))
+
+
+def prof_enable(on: bool):
+    check(lib().qsv_prof_enable(1 if on else 0))
+
+
+def prof_read(name: str):
+    """(launches, total_ms, algorithmic bytes) for a kernel family."""
+    n, ms, by = _c.c_int(), _c.c_double(), _c.c_double()
+    check(lib().qsv_prof_read(name.encode(), _c.byref(n), _c.byref(ms), _c.byref(by)))
+    return n.value, ms.value, by.value
 
 
 def apply_record(state: State, g, theta=None):

@@ -44,23 +44,37 @@ __device__ __forceinline__ uint64_t insert_zeros(uint64_t i, const int* pos, int
   return i;
 }
 
+// Clang vector types, usable with the non-temporal load/store builtins. State
+// amplitudes are streamed once per pass, so HBM traffic uses non-temporal
+// accesses (measured on MI355X: ~10% more in-place bandwidth than plain ones).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ f32x4 nt_load(const f32x4* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ f32x2 nt_load(const f32x2* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ f64x2 nt_load(const f64x2* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void nt_store(f32x4 v, f32x4* p) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void nt_store(f32x2 v, f32x2* p) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void nt_store(f64x2 v, f64x2* p) { __builtin_nontemporal_store(v, p); }
+
 // Vector access to VEC consecutive amplitudes starting at amplitude index x
 // (x must be VEC-aligned in amplitudes when 16-byte vectors are used).
 template <typename R, int VEC>
 struct AmpIO;
 
-// complex64: a float4 holds two amplitudes.
+// complex64: a 16-byte vector holds two amplitudes.
 template <int VEC>
 struct AmpIO<float, VEC> {
   static_assert(VEC == 1 || VEC % 2 == 0, "VEC");
   __device__ __forceinline__ static void load(const float* base, uint64_t x, cx<float>* v) {
     if constexpr (VEC == 1) {
-      const float2 a = *reinterpret_cast<const float2*>(base + 2 * x);
+      const f32x2 a = nt_load(reinterpret_cast<const f32x2*>(base + 2 * x));
       v[0] = {a.x, a.y};
     } else {
 #pragma unroll
       for (int j = 0; j < VEC / 2; ++j) {
-        const float4 a = *reinterpret_cast<const float4*>(base + 2 * (x + 2 * j));
+        const f32x4 a = nt_load(reinterpret_cast<const f32x4*>(base + 2 * (x + 2 * j)));
         v[2 * j] = {a.x, a.y};
         v[2 * j + 1] = {a.z, a.w};
       }
@@ -68,30 +82,30 @@ struct AmpIO<float, VEC> {
   }
   __device__ __forceinline__ static void store(float* base, uint64_t x, const cx<float>* v) {
     if constexpr (VEC == 1) {
-      *reinterpret_cast<float2*>(base + 2 * x) = make_float2(v[0].re, v[0].im);
+      nt_store(f32x2{v[0].re, v[0].im}, reinterpret_cast<f32x2*>(base + 2 * x));
     } else {
 #pragma unroll
       for (int j = 0; j < VEC / 2; ++j)
-        *reinterpret_cast<float4*>(base + 2 * (x + 2 * j)) =
-            make_float4(v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im);
+        nt_store(f32x4{v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im},
+                 reinterpret_cast<f32x4*>(base + 2 * (x + 2 * j)));
     }
   }
 };
 
-// complex128: a double2 holds one amplitude.
+// complex128: a 16-byte vector holds one amplitude.
 template <int VEC>
 struct AmpIO<double, VEC> {
   __device__ __forceinline__ static void load(const double* base, uint64_t x, cx<double>* v) {
 #pragma unroll
     for (int j = 0; j < VEC; ++j) {
-      const double2 a = *reinterpret_cast<const double2*>(base + 2 * (x + j));
+      const f64x2 a = nt_load(reinterpret_cast<const f64x2*>(base + 2 * (x + j)));
       v[j] = {a.x, a.y};
     }
   }
   __device__ __forceinline__ static void store(double* base, uint64_t x, const cx<double>* v) {
 #pragma unroll
     for (int j = 0; j < VEC; ++j)
-      *reinterpret_cast<double2*>(base + 2 * (x + j)) = make_double2(v[j].re, v[j].im);
+      nt_store(f64x2{v[j].re, v[j].im}, reinterpret_cast<f64x2*>(base + 2 * (x + j)));
   }
 };
 

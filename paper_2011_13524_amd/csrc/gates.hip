@@ -18,6 +18,7 @@
 #include <algorithm>
 
 #include "dev_common.h"
+#include "prof.h"
 #include "qsv_internal.h"
 
 namespace qsv {
@@ -221,6 +222,7 @@ int launch_pair_t(qsv_state* s, uint64_t ins_mask, uint64_t or_mask, uint64_t of
     if (offA == 0 && offB == 1) {
       a.nthreads = uint64_t(1) << free_bits;
       if ((rc = launch_grid(a.nthreads, &grid))) return rc;
+      ProfScope ps("pair", 4.0 * sizeof(R) * 2 * double(a.nthreads), s->stream);
       if (kind == PK_DENSE)
         hipLaunchKernelGGL(k_pair_adj<PK_DENSE>, grid, dim3(256), 0, s->stream, psi, a);
       else if (kind == PK_DIAG)
@@ -234,6 +236,7 @@ int launch_pair_t(qsv_state* s, uint64_t ins_mask, uint64_t or_mask, uint64_t of
   const int vec = pick_vec(s->dtype, lowest_bit(ins_mask), free_bits);
   a.nthreads = (uint64_t(1) << free_bits) / vec;
   if ((rc = launch_grid(a.nthreads, &grid))) return rc;
+  ProfScope ps("pair", 4.0 * sizeof(R) * 2 * double(uint64_t(1) << free_bits), s->stream);
 #define QSV_PAIR_LAUNCH(V)                                                                   \
   do {                                                                                       \
     if (kind == PK_DENSE)                                                                    \
@@ -277,6 +280,7 @@ int launch_scale_t(qsv_state* s, uint64_t mask, uint64_t pattern, cd c) {
   int rc;
   if ((rc = launch_grid(a.nthreads, &grid))) return rc;
   R* psi = static_cast<R*>(s->ptr);
+  ProfScope ps("scale", 2.0 * sizeof(R) * 2 * double(uint64_t(1) << free_bits), s->stream);
   if (vec == 4) {
     if constexpr (sizeof(R) == 4)
       hipLaunchKernelGGL((k_scale<R, 4>), grid, dim3(256), 0, s->stream, psi, a);
@@ -308,6 +312,7 @@ int launch_diag_t(qsv_state* s, const cd* d, const int* targets, int k, uint64_t
   int rc;
   if ((rc = launch_grid(a.nthreads, &grid))) return rc;
   R* psi = static_cast<R*>(s->ptr);
+  ProfScope ps("diag", 2.0 * sizeof(R) * 2 * double(uint64_t(1) << free_bits), s->stream);
   if (vec == 4) {
     if constexpr (sizeof(R) == 4)
       hipLaunchKernelGGL((k_diag<R, 4>), grid, dim3(256), 0, s->stream, psi, a);
@@ -346,6 +351,7 @@ int launch_dense_k(qsv_state* s, const cd* mat, const int* targets, uint64_t cma
   if (rc) return rc;
   dim3 grid;
   if ((rc = launch_grid(a.nthreads, &grid))) return rc;
+  ProfScope ps("dense", 2.0 * sizeof(R) * 2 * D * double(a.nthreads), s->stream);
   hipLaunchKernelGGL((k_dense<R, K>), grid, dim3(256), 0, s->stream, static_cast<R*>(s->ptr),
                      static_cast<const cx<R>*>(dmat), a);
   QSV_HIP_CHECK(hipGetLastError());
@@ -363,6 +369,8 @@ int launch_dense(qsv_state* s, const cd* mat, const int* targets, int k, uint64_
     default: return fail(QSV_EINVAL, "dense gate on %d qubits not supported", k);
   }
 }
+
+}  // namespace
 
 // Controlled structure of section 4.3.2: if target bit j acts as a control
 // with value v -- the gate matrix is the identity on (and does not couple to)
@@ -405,8 +413,6 @@ void extract_controls(std::vector<cd>& mat, std::vector<int>& tq, uint64_t& cmas
     }
   }
 }
-
-}  // namespace
 
 int launch_scale_subspace(qsv_state* s, uint64_t mask, uint64_t pattern, cd c) {
   return s->dtype == QSV_C64 ? launch_scale_t<float>(s, mask, pattern, c)

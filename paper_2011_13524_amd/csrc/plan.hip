@@ -1,0 +1,625 @@
+// Circuit fusion (section 5.4) and tile passes.
+//
+// Planning, on the host, in three stages:
+//  1. Structure: every gate is reduced to its controlled form (section 4.3.2)
+//     and marked diagonal or not.
+//  2. Merge (section 5.4, merge of two successive gates): a gate joins the
+//     block it depends on when that block is the only earlier block sharing
+//     its qubits -- so it commutes with every block created in between -- and
+//     the merged block stays within max_k qubits. Diagonal gates join diagonal
+//     blocks (the product stays diagonal); a diagonal gate joins a dense block
+//     only on a subset of its qubits, and a dense gate absorbs a diagonal block
+//     only on a subset of its own qubits, so merging never forces extra qubits
+//     to be local. Block matrices are products K_later K_earlier on the
+//     ascending union of qubits.
+//  3. Passes: a pass fixes a set of L local qubits (always including the low b
+//     qubits, so that each run of 2^b amplitudes is contiguous in HBM) and
+//     greedily takes, in order, every block whose non-diagonal targets are
+//     local or can still be made local, skipping blocks that share a qubit
+//     with one already deferred. Diagonal blocks and controls may sit on any
+//     qubit: for one tile their non-local bits are constants.
+//
+// Execution: one kernel launch per pass; workgroup g owns tile g, the 2^L
+// amplitudes whose non-local bits spell g. It streams the tile from HBM into
+// LDS (non-temporal 16-byte vectors), applies the pass's blocks in order with a
+// barrier between them, and streams the tile back. Each pass therefore reads
+// and writes the state once however many gates it applies.
+#include <algorithm>
+#include <cmath>
+
+#include "dev_common.h"
+#include "plan.h"
+#include "prof.h"
+
+namespace qsv {
+
+__device__ __forceinline__ uint32_t insert_zeros32(uint32_t i, const int* pos, int m) {
+  for (int j = 0; j < m; ++j) {
+    const uint32_t lo = i & ((1u << pos[j]) - 1);
+    i = ((i >> pos[j]) << (pos[j] + 1)) | lo;
+  }
+  return i;
+}
+
+template <typename R, int K>
+__device__ __forceinline__ void tile_dense(cx<R>* __restrict__ t, const TileOpDev& op,
+                                           const cx<R>* __restrict__ mat, int L) {
+  constexpr int D = 1 << K;
+  const int cnt = 1 << (L - op.m);
+  if constexpr (K == 1) {
+    const cx<R> m00 = mat[0], m01 = mat[1], m10 = mat[2], m11 = mat[3];
+    const uint32_t o1 = op.off[1];
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+      const uint32_t j0 = insert_zeros32(i, op.ins, op.m) | op.lcv;
+      const cx<R> a = t[j0], b = t[j0 + o1];
+      t[j0] = cfma(m00, a, m01 * b);
+      t[j0 + o1] = cfma(m10, a, m11 * b);
+    }
+  } else {
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+      const uint32_t j0 = insert_zeros32(i, op.ins, op.m) | op.lcv;
+      cx<R> v[D];
+#pragma unroll
+      for (int c = 0; c < D; ++c) v[c] = t[j0 + op.off[c]];
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        cx<R> acc = {R(0), R(0)};
+#pragma unroll
+        for (int c = 0; c < D; ++c) acc = cfma(mat[r * D + c], v[c], acc);
+        t[j0 + op.off[r]] = acc;
+      }
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void tile_diag(cx<R>* __restrict__ t, const TileOpDev& op,
+                                          const cx<R>* __restrict__ d, int L, uint64_t base) {
+  int gidx = 0;
+  for (int b = 0; b < op.k; ++b)
+    if (op.gq[b] >= 0) gidx |= int((base >> op.gq[b]) & 1) << b;
+  const int TS = 1 << L;
+  for (int j = threadIdx.x; j < TS; j += blockDim.x) {
+    if ((uint32_t(j) & op.lcm) != op.lcv) continue;
+    int idx = gidx;
+    for (int b = 0; b < op.k; ++b)
+      if (op.lt[b] >= 0) idx |= ((j >> op.lt[b]) & 1) << b;
+    t[j] = d[idx] * t[j];
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+    k_tile(R* __restrict__ psi, const TilePassDev* __restrict__ passes, int pass_idx,
+           const TileOpDev* __restrict__ ops, const cx<R>* __restrict__ pool) {
+  extern __shared__ __align__(16) char smem[];
+  cx<R>* t = reinterpret_cast<cx<R>*>(smem);
+  const TilePassDev& P = passes[pass_idx];
+  const int L = P.L, b = P.b, nh = P.nh, ng = P.ng;
+  const uint64_t g = blockIdx.x;
+  uint64_t base = 0;
+  for (int j = 0; j < ng; ++j) base |= ((g >> j) & 1) << P.gpos[j];
+  constexpr int V = sizeof(R) == 4 ? 2 : 1;
+  const int TS = 1 << L;
+  const uint32_t lowmask = (1u << b) - 1;
+  for (int e = threadIdx.x; e < TS / V; e += blockDim.x) {
+    const uint32_t j = uint32_t(e) * V;
+    const uint32_t h = j >> b;
+    uint64_t x = base + (j & lowmask);
+    for (int i = 0; i < nh; ++i) x |= uint64_t((h >> i) & 1) << P.hq[i];
+    AmpIO<R, V>::load(psi, x, &t[j]);
+  }
+  __syncthreads();
+  for (int o = 0; o < P.op_count; ++o) {
+    const TileOpDev& op = ops[P.op_begin + o];
+    if ((base & op.gcm) != op.gcv) continue;  // non-local controls not met: skip for this tile
+    const cx<R>* mat = pool + op.moff;
+    if (op.kind == 1) {
+      tile_diag<R>(t, op, mat, L, base);
+    } else {
+      switch (op.k) {
+        case 1: tile_dense<R, 1>(t, op, mat, L); break;
+        case 2: tile_dense<R, 2>(t, op, mat, L); break;
+        case 3: tile_dense<R, 3>(t, op, mat, L); break;
+        case 4: tile_dense<R, 4>(t, op, mat, L); break;
+        default: tile_dense<R, 5>(t, op, mat, L); break;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < TS / V; e += blockDim.x) {
+    const uint32_t j = uint32_t(e) * V;
+    const uint32_t h = j >> b;
+    uint64_t x = base + (j & lowmask);
+    for (int i = 0; i < nh; ++i) x |= uint64_t((h >> i) & 1) << P.hq[i];
+    AmpIO<R, V>::store(psi, x, &t[j]);
+  }
+}
+
+// ------------------------------------------------------------------ host: matrices
+
+namespace {
+
+uint64_t qmask(const std::vector<int>& qs) {
+  uint64_t m = 0;
+  for (int q : qs) m |= uint64_t(1) << q;
+  return m;
+}
+
+std::vector<int> mask_list(uint64_t m) {
+  std::vector<int> v;
+  for (int q = 0; q < 64; ++q)
+    if (m >> q & 1) v.push_back(q);
+  return v;
+}
+
+// Structure of one gate: targets/controls after control extraction and
+// whether the remaining target matrix is diagonal (value-independent for
+// rotations: Z rotations are diagonal for every angle).
+struct GateInfo {
+  std::vector<int> targets, controls, ctrl_vals;
+  std::vector<cd> mat;  // extracted matrix (MATRIX gates only)
+  bool diagonal = false;
+  uint64_t qubits = 0;
+};
+
+GateInfo analyse(const Gate& g) {
+  GateInfo gi;
+  if (g.kind == Gate::ROTATION) {
+    gi.targets = g.targets;
+    gi.diagonal = (g.pauli == 3);
+  } else {
+    std::vector<cd> m = g.mat;
+    std::vector<int> tq = g.targets;
+    uint64_t cm = 0, cv = 0;
+    for (size_t j = 0; j < g.controls.size(); ++j) {
+      cm |= uint64_t(1) << g.controls[j];
+      if (g.ctrl_vals[j]) cv |= uint64_t(1) << g.controls[j];
+    }
+    extract_controls(m, tq, cm, cv);
+    gi.targets = tq;
+    for (int q : mask_list(cm)) {
+      gi.controls.push_back(q);
+      gi.ctrl_vals.push_back(int(cv >> q & 1));
+    }
+    const int D = 1 << tq.size();
+    bool dg = true;
+    for (int r = 0; r < D && dg; ++r)
+      for (int c = 0; c < D && dg; ++c)
+        if (r != c && !(m[r * D + c].re == 0.0 && m[r * D + c].im == 0.0)) dg = false;
+    gi.diagonal = dg;
+    gi.mat = m;
+  }
+  gi.qubits = qmask(gi.targets) | qmask(gi.controls);
+  return gi;
+}
+
+// Target matrix of a gate in its extracted form, for the given parameters.
+void extracted_matrix(const Gate& g, const GateInfo& gi, const double* theta, std::vector<cd>& m) {
+  if (g.kind == Gate::ROTATION) {
+    gate_matrix(g, theta, m);
+  } else {
+    m = gi.mat;
+  }
+}
+
+// Full matrix of a gate (targets + controls) embedded in the index space of
+// `qs` (bit j <-> qs[j]); result is 2^|qs| square, row-major.
+void embed(const std::vector<cd>& gm, const GateInfo& gi, const std::vector<int>& qs,
+           std::vector<cd>& out) {
+  const int k = int(qs.size());
+  const int D = 1 << k;
+  out.assign(size_t(D) * D, cd{0, 0});
+  std::vector<int> tpos(gi.targets.size()), cpos(gi.controls.size());
+  for (size_t j = 0; j < gi.targets.size(); ++j)
+    tpos[j] = int(std::find(qs.begin(), qs.end(), gi.targets[j]) - qs.begin());
+  for (size_t j = 0; j < gi.controls.size(); ++j)
+    cpos[j] = int(std::find(qs.begin(), qs.end(), gi.controls[j]) - qs.begin());
+  const int kt = int(tpos.size());
+  const int Dt = 1 << kt;
+  for (int c = 0; c < D; ++c) {
+    bool on = true;
+    for (size_t j = 0; j < cpos.size(); ++j)
+      if (((c >> cpos[j]) & 1) != gi.ctrl_vals[j]) on = false;
+    if (!on) {
+      out[size_t(c) * D + c] = {1, 0};
+      continue;
+    }
+    int cc = 0, rest = c;
+    for (int j = 0; j < kt; ++j) {
+      cc |= ((c >> tpos[j]) & 1) << j;
+      rest &= ~(1 << tpos[j]);
+    }
+    for (int rr = 0; rr < Dt; ++rr) {
+      int r = rest;
+      for (int j = 0; j < kt; ++j) r |= ((rr >> j) & 1) << tpos[j];
+      out[size_t(r) * D + c] = gm[size_t(rr) * Dt + cc];
+    }
+  }
+}
+
+void matmul(const std::vector<cd>& a, const std::vector<cd>& b, int D, std::vector<cd>& out) {
+  out.assign(size_t(D) * D, cd{0, 0});
+  for (int r = 0; r < D; ++r)
+    for (int k = 0; k < D; ++k) {
+      const cd x = a[size_t(r) * D + k];
+      if (x.re == 0.0 && x.im == 0.0) continue;
+      for (int c = 0; c < D; ++c) out[size_t(r) * D + c] = cadd(out[size_t(r) * D + c], cmul(x, b[size_t(k) * D + c]));
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host: planning
+
+static int build_plan(qsv_plan* p) {
+  const qsv_circuit& C = p->circ_copy;
+  const int n = C.n;
+  std::vector<GateInfo> info(C.gates.size());
+  for (size_t i = 0; i < C.gates.size(); ++i) info[i] = analyse(C.gates[i]);
+
+  // stage 2: merge
+  std::vector<Block>& blocks = p->blocks;
+  blocks.clear();
+  std::vector<uint64_t> bq;  // qubit masks of blocks
+  std::vector<int> last(n, -1);
+  for (size_t gi = 0; gi < C.gates.size(); ++gi) {
+    const GateInfo& I = info[gi];
+    int cand = -2;
+    for (int q : mask_list(I.qubits)) {
+      if (last[q] < 0) continue;
+      if (cand == -2) cand = last[q];
+      else if (cand != last[q]) cand = -1;
+    }
+    bool merged = false;
+    if (cand >= 0) {
+      Block& B = blocks[cand];
+      const uint64_t uni = bq[cand] | I.qubits;
+      const int ku = __builtin_popcountll(uni);
+      bool ok = false;
+      if (B.diagonal && I.diagonal) ok = ku <= 5;
+      else if (!B.diagonal && I.diagonal) ok = (I.qubits & ~bq[cand]) == 0;
+      else if (B.diagonal && !I.diagonal) ok = (bq[cand] & ~I.qubits) == 0 && ku <= std::max(p->max_k, 1);
+      else ok = ku <= p->max_k;
+      if (ok) {
+        B.gates.push_back(int(gi));
+        bq[cand] = uni;
+        B.diagonal = B.diagonal && I.diagonal;
+        merged = true;
+        for (int q : mask_list(I.qubits)) last[q] = cand;
+      }
+    }
+    if (!merged) {
+      Block B;
+      B.gates = {int(gi)};
+      B.diagonal = I.diagonal;
+      blocks.push_back(B);
+      bq.push_back(I.qubits);
+      for (int q : mask_list(I.qubits)) last[q] = int(blocks.size()) - 1;
+    }
+  }
+  for (size_t i = 0; i < blocks.size(); ++i) {
+    Block& B = blocks[i];
+    B.qubits = mask_list(bq[i]);
+    if (B.gates.size() == 1) {
+      const GateInfo& I = info[B.gates[0]];
+      B.targets = I.targets;
+      B.controls = I.controls;
+      B.ctrl_vals = I.ctrl_vals;
+    } else {
+      B.targets = B.qubits;
+      B.controls.clear();
+      B.ctrl_vals.clear();
+    }
+    if (!B.diagonal && B.targets.size() > size_t(5)) return fail(QSV_EINVAL, "block wider than 5 qubits");
+  }
+
+  // stage 3: passes
+  const int L = p->L, b = p->b;
+  p->passes.clear();
+  std::vector<int> rem(blocks.size());
+  for (size_t i = 0; i < blocks.size(); ++i) rem[i] = int(i);
+  const uint64_t low = (b >= 64) ? ~0ull : ((uint64_t(1) << b) - 1);
+  while (!rem.empty()) {
+    qsv_plan::Pass P;
+    uint64_t local = low;
+    uint64_t blocked = 0;
+    std::vector<int> deferred;
+    for (int bi : rem) {
+      const Block& B = blocks[bi];
+      const uint64_t all = bq[bi];
+      if (all & blocked) {
+        deferred.push_back(bi);
+        blocked |= all;
+        continue;
+      }
+      const uint64_t dense = B.diagonal ? 0 : qmask(B.targets);
+      const uint64_t need = dense & ~local;
+      if (__builtin_popcountll(local | need) <= L) {
+        local |= need;
+        P.blocks.push_back(bi);
+      } else {
+        deferred.push_back(bi);
+        blocked |= all;
+      }
+    }
+    if (P.blocks.empty()) return fail(QSV_EINVAL, "planner made no progress (tile too small)");
+    // fill the local set up to L qubits with the lowest unused qubits
+    for (int q = 0; q < n && __builtin_popcountll(local) < L; ++q) local |= uint64_t(1) << q;
+    P.local = mask_list(local);
+    p->passes.push_back(P);
+    rem.swap(deferred);
+  }
+  return QSV_OK;
+}
+
+// Device tables for the passes and ops (matrix offsets fixed here; matrix
+// values are uploaded at apply time).
+static int upload_tables(qsv_plan* p, std::vector<int>& moffs, size_t& pool_elems) {
+  const int n = p->n;
+  std::vector<TilePassDev> hp;
+  std::vector<TileOpDev> ho;
+  moffs.assign(p->blocks.size(), 0);
+  pool_elems = 0;
+  for (size_t bi = 0; bi < p->blocks.size(); ++bi) {
+    const Block& B = p->blocks[bi];
+    moffs[bi] = int(pool_elems);
+    const size_t k = B.targets.size();
+    pool_elems += B.diagonal ? (size_t(1) << k) : (size_t(1) << (2 * k));
+  }
+  for (const auto& P : p->passes) {
+    TilePassDev d{};
+    d.L = int(P.local.size());
+    d.b = std::min(p->b, d.L);
+    d.nh = d.L - d.b;
+    if (d.nh > kTileMaxHigh) return fail(QSV_EINVAL, "too many high local qubits");
+    for (int i = 0; i < d.nh; ++i) d.hq[i] = P.local[d.b + i];
+    uint64_t lm = qmask(P.local);
+    d.ng = 0;
+    for (int q = 0; q < n; ++q)
+      if (!(lm >> q & 1)) d.gpos[d.ng++] = q;
+    d.op_begin = int(ho.size());
+    d.op_count = int(P.blocks.size());
+    std::vector<int> lpos(64, -1);
+    for (size_t i = 0; i < P.local.size(); ++i) lpos[P.local[i]] = int(i);
+    for (int bi : P.blocks) {
+      const Block& B = p->blocks[bi];
+      TileOpDev o{};
+      o.kind = B.diagonal ? 1 : 0;
+      o.k = int(B.targets.size());
+      o.moff = moffs[bi];
+      for (size_t j = 0; j < B.controls.size(); ++j) {
+        const int q = B.controls[j];
+        if (lpos[q] >= 0) {
+          o.lcm |= 1u << lpos[q];
+          if (B.ctrl_vals[j]) o.lcv |= 1u << lpos[q];
+        } else {
+          o.gcm |= uint64_t(1) << q;
+          if (B.ctrl_vals[j]) o.gcv |= uint64_t(1) << q;
+        }
+      }
+      for (int j = 0; j < 5; ++j) {
+        o.lt[j] = -1;
+        o.gq[j] = -1;
+      }
+      for (int j = 0; j < o.k; ++j) {
+        const int q = B.targets[j];
+        if (lpos[q] >= 0) o.lt[j] = lpos[q];
+        else o.gq[j] = q;
+      }
+      if (o.kind == 0) {
+        uint32_t ins = o.lcm;
+        for (int j = 0; j < o.k; ++j) {
+          if (o.lt[j] < 0) return fail(QSV_EINVAL, "internal: dense target not local");
+          ins |= 1u << o.lt[j];
+        }
+        if (__builtin_popcount(ins) > 10) return fail(QSV_EINVAL, "too many local controls on one gate");
+        o.m = 0;
+        for (int q = 0; q < 32; ++q)
+          if (ins >> q & 1) o.ins[o.m++] = q;
+        for (int i = 0; i < (1 << o.k); ++i) {
+          uint32_t off = 0;
+          for (int j = 0; j < o.k; ++j)
+            if (i >> j & 1) off |= 1u << o.lt[j];
+          o.off[i] = off;
+        }
+      }
+      ho.push_back(o);
+    }
+    hp.push_back(d);
+  }
+  p->h_pass.swap(hp);
+  p->h_ops.swap(ho);
+  return QSV_OK;
+}
+
+// Device copies of the pass and op tables, made on the first apply so that
+// planning itself needs no device.
+static int ensure_tables(qsv_plan* p, hipStream_t stream) {
+  if (p->d_pass) return QSV_OK;
+  if (hipMalloc(reinterpret_cast<void**>(&p->d_pass), p->h_pass.size() * sizeof(TilePassDev)) != hipSuccess)
+    return fail(QSV_ENOMEM, "plan table allocation failed");
+  if (hipMalloc(reinterpret_cast<void**>(&p->d_ops),
+                std::max<size_t>(1, p->h_ops.size()) * sizeof(TileOpDev)) != hipSuccess) {
+    (void)hipFree(p->d_pass);
+    p->d_pass = nullptr;
+    return fail(QSV_ENOMEM, "plan table allocation failed");
+  }
+  QSV_HIP_CHECK(hipMemcpyAsync(p->d_pass, p->h_pass.data(), p->h_pass.size() * sizeof(TilePassDev),
+                               hipMemcpyHostToDevice, stream));
+  if (!p->h_ops.empty())
+    QSV_HIP_CHECK(hipMemcpyAsync(p->d_ops, p->h_ops.data(), p->h_ops.size() * sizeof(TileOpDev),
+                                 hipMemcpyHostToDevice, stream));
+  QSV_HIP_CHECK(hipStreamSynchronize(stream));
+  return QSV_OK;
+}
+
+// Block matrices (or diagonals) for parameters theta, written as complex
+// doubles in block order.
+static void block_values(const qsv_plan* p, const double* theta, std::vector<cd>& pool) {
+  const qsv_circuit& C = p->circ_copy;
+  pool.clear();
+  std::vector<cd> gm, full, acc, tmp;
+  for (const Block& B : p->blocks) {
+    const int k = int(B.targets.size());
+    const int D = 1 << k;
+    if (B.gates.size() == 1) {
+      const Gate& g = C.gates[B.gates[0]];
+      GateInfo gi = analyse(g);
+      extracted_matrix(g, gi, theta, gm);
+      if (B.diagonal) {
+        for (int i = 0; i < D; ++i) pool.push_back(gm[size_t(i) * D + i]);
+      } else {
+        pool.insert(pool.end(), gm.begin(), gm.end());
+      }
+      continue;
+    }
+    acc.assign(size_t(D) * D, cd{0, 0});
+    for (int i = 0; i < D; ++i) acc[size_t(i) * D + i] = {1, 0};
+    for (int gidx : B.gates) {
+      const Gate& g = C.gates[gidx];
+      GateInfo gi = analyse(g);
+      extracted_matrix(g, gi, theta, gm);
+      embed(gm, gi, B.targets, full);
+      matmul(full, acc, D, tmp);  // later gate on the left
+      acc.swap(tmp);
+    }
+    if (B.diagonal) {
+      for (int i = 0; i < D; ++i) pool.push_back(acc[size_t(i) * D + i]);
+    } else {
+      pool.insert(pool.end(), acc.begin(), acc.end());
+    }
+  }
+}
+
+template <typename R>
+static int apply_fused_t(qsv_state* s, qsv_plan* p, const double* theta) {
+  int trc = ensure_tables(p, s->stream);
+  if (trc) return trc;
+  std::vector<cd> vals;
+  block_values(p, theta, vals);
+  const size_t bytes = vals.size() * sizeof(cx<R>);
+  if (p->pool_cap < vals.size()) {
+    if (p->d_pool) {
+      QSV_HIP_CHECK(hipStreamSynchronize(s->stream));
+      (void)hipFree(p->d_pool);
+      p->d_pool = nullptr;
+    }
+    if (hipMalloc(&p->d_pool, std::max<size_t>(bytes, 16)) != hipSuccess)
+      return fail(QSV_ENOMEM, "plan pool allocation failed");
+    p->pool_cap = vals.size();
+  }
+  if (p->stage_bytes < bytes) {
+    if (p->h_stage) {
+      if (p->stage_used) QSV_HIP_CHECK(hipEventSynchronize(p->stage_ev));
+      (void)hipHostFree(p->h_stage);
+      p->h_stage = nullptr;
+    }
+    if (hipHostMalloc(&p->h_stage, std::max<size_t>(bytes, 16), hipHostMallocDefault) != hipSuccess)
+      return fail(QSV_ENOMEM, "plan staging allocation failed");
+    p->stage_bytes = bytes;
+  }
+  if (!p->stage_ev) QSV_HIP_CHECK(hipEventCreateWithFlags(&p->stage_ev, hipEventDisableTiming));
+  if (p->stage_used) QSV_HIP_CHECK(hipEventSynchronize(p->stage_ev));
+  cx<R>* st = static_cast<cx<R>*>(p->h_stage);
+  for (size_t i = 0; i < vals.size(); ++i) st[i] = {R(vals[i].re), R(vals[i].im)};
+  if (bytes)
+    QSV_HIP_CHECK(hipMemcpyAsync(p->d_pool, p->h_stage, bytes, hipMemcpyHostToDevice, s->stream));
+  const int n = s->n;
+  for (size_t pi = 0; pi < p->passes.size(); ++pi) {
+    const int L = int(p->passes[pi].local.size());
+    const uint64_t tiles = dim(n - L);
+    const size_t lds = (size_t(1) << L) * sizeof(cx<R>);
+    if (lds > 65536)
+      QSV_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tile<R>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    ProfScope ps("tile", 2.0 * sizeof(cx<R>) * double(dim(n)), s->stream);
+    hipLaunchKernelGGL((k_tile<R>), dim3(unsigned(tiles)), dim3(256), lds, s->stream,
+                       static_cast<R*>(s->ptr), p->d_pass, int(pi), p->d_ops,
+                       static_cast<const cx<R>*>(p->d_pool));
+    QSV_HIP_CHECK(hipGetLastError());
+  }
+  QSV_HIP_CHECK(hipEventRecord(p->stage_ev, s->stream));
+  p->stage_used = true;
+  return QSV_OK;
+}
+
+}  // namespace qsv
+
+using namespace qsv;
+
+extern "C" {
+
+int qsv_plan_fused(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qubits, int low_qubits,
+                   qsv_plan** out) {
+  clear_error();
+  if (!out) return fail(QSV_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!c) return fail(QSV_EINVAL, "null circuit");
+  if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_EDTYPE, "unknown dtype");
+  if (max_k < 1 || max_k > 5) return fail(QSV_EINVAL, "max_k must be in 1..5");
+  const int n = c->n;
+  int L = tile_qubits > 0 ? tile_qubits : (dtype == QSV_C64 ? 13 : 12);
+  int b = low_qubits > 0 ? low_qubits : (dtype == QSV_C64 ? 6 : 5);
+  if (L > 14 || (dtype == QSV_C128 && L > 13)) return fail(QSV_EINVAL, "tile of %d qubits exceeds LDS", L);
+  L = std::min(L, n);
+  b = std::min(b, L);
+  if (dtype == QSV_C64 && b < 1) b = 1;
+  if (L - b < max_k && L < n) return fail(QSV_EINVAL, "tile leaves fewer than max_k free qubits");
+  if (L - b > kTileMaxHigh) return fail(QSV_EINVAL, "too many high local qubits");
+  qsv_plan* p = new (std::nothrow) qsv_plan();
+  if (!p) return fail(QSV_ENOMEM, "host allocation failed");
+  p->n = n;
+  p->dtype = dtype;
+  p->max_k = max_k;
+  p->L = L;
+  p->b = b;
+  p->circ_copy = *c;
+  int rc = build_plan(p);
+  std::vector<int> moffs;
+  size_t pool_elems = 0;
+  if (!rc) rc = upload_tables(p, moffs, pool_elems);
+  if (rc) {
+    if (p->d_pass) (void)hipFree(p->d_pass);
+    if (p->d_ops) (void)hipFree(p->d_ops);
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return QSV_OK;
+}
+
+int qsv_plan_info(const qsv_plan* p, int* passes, int* blocks, int* gates) {
+  clear_error();
+  if (!p) return fail(QSV_EINVAL, "null plan");
+  if (passes) *passes = int(p->passes.size());
+  if (blocks) *blocks = int(p->blocks.size());
+  if (gates) *gates = int(p->circ_copy.gates.size());
+  return QSV_OK;
+}
+
+int qsv_plan_free(qsv_plan* p) {
+  clear_error();
+  if (!p) return QSV_OK;
+  if (p->stage_used) (void)hipEventSynchronize(p->stage_ev);
+  if (p->stage_ev) (void)hipEventDestroy(p->stage_ev);
+  if (p->h_stage) (void)hipHostFree(p->h_stage);
+  if (p->d_pool) (void)hipFree(p->d_pool);
+  if (p->d_pass) (void)hipFree(p->d_pass);
+  if (p->d_ops) (void)hipFree(p->d_ops);
+  delete p;
+  return QSV_OK;
+}
+
+int qsv_apply_fused(qsv_state* s, qsv_plan* p, const double* theta) {
+  clear_error();
+  int rc = check_state(s);
+  if (rc) return rc;
+  if (!p) return fail(QSV_EINVAL, "null plan");
+  if (p->n != s->n) return fail(QSV_ERANGE, "plan has %d qubits, state %d", p->n, s->n);
+  if (p->dtype != s->dtype) return fail(QSV_EDTYPE, "plan and state dtypes differ");
+  if (p->circ_copy.nparams > 0 && !theta) return fail(QSV_EINVAL, "plan has parameters but theta is null");
+  return s->dtype == QSV_C64 ? apply_fused_t<float>(s, p, theta) : apply_fused_t<double>(s, p, theta);
+}
+
+}  // extern "C"

@@ -99,6 +99,12 @@ int apply_gate_impl(qsv_state* s, const cd* mat, const int* targets, int k, cons
                     const int* ctrl_vals, int nc);
 int named_matrix(int kind, double theta, cd* out, int* k);
 
+// Controlled structure of a gate matrix (gates.hip): peel off target bits that
+// act as controls, shrinking the matrix and extending (cmask, cval).
+void extract_controls(std::vector<cd>& mat, std::vector<int>& tq, uint64_t& cmask, uint64_t& cval);
+int validate_gate(int n, const int* targets, int k, const int* controls, const int* ctrl_vals,
+                  int nc, int kmax);
+
 // Launch helpers (gates.hip).
 int launch_scale_subspace(qsv_state* s, uint64_t mask, uint64_t pattern, cd c);
 

@@ -20,6 +20,7 @@
 #include <map>
 
 #include "dev_common.h"
+#include "prof.h"
 #include "qsv_internal.h"
 
 struct qsv_observable {
@@ -190,6 +191,7 @@ int expectation_t(qsv_state* s, const qsv_observable* o, double* out) {
     const int hbit = f ? 63 - __builtin_clzll(f) : 0;
     const uint64_t work = f ? dim(n) / 2 : dim(n);
     double* p = partial + g * B;
+    ProfScope ps("expect", 2.0 * sizeof(R) * double(dim(n)), s->stream);
     hipLaunchKernelGGL((k_expect_group<R>), dim3(B), dim3(kRedThreads), 0, s->stream,
                        static_cast<const R*>(s->ptr), work, f, hbit, dterms + groups[g].begin,
                        groups[g].count, p);

@@ -1,0 +1,133 @@
+"""GPU parity of fused execution (merged blocks applied in LDS tile passes)
+against the unfused CPU oracle. Fusion is an exact rewrite, so only rounding
+differs: bars as for unfused circuits (1e-12 c128, 1e-5 c64 max-abs).
+
+Small tiles (few local qubits) force many passes, non-local controls and
+diagonal gates on non-local qubits at sizes the oracle runs in milliseconds.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2011_13524_amd import Circuit, Plan, State, apply_fused
+from paper_2011_13524_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+AMP_TOL = {"c128": 1e-12, "c64": 1e-5}
+
+
+def mixed_circuit(n, count, seed):
+    """Every gate kind the library recognises, on random qubits."""
+    rng = np.random.default_rng(seed)
+    g = []
+    for _ in range(count):
+        r = rng.integers(0, 10)
+        qs = [int(q) for q in rng.choice(n, size=min(n, 4), replace=False)]
+        if r == 0:
+            g.append({"op": "dense", "q": qs[:1], "mat": W.haar_unitary(rng, 2)})
+        elif r == 1 and n >= 2:
+            g.append({"op": "dense", "q": qs[:2], "mat": W.haar_unitary(rng, 4)})
+        elif r == 2 and n >= 3:
+            g.append({"op": "dense", "q": qs[:3], "mat": W.haar_unitary(rng, 8)})
+        elif r == 3 and n >= 3:
+            g.append({"op": "dense", "q": qs[:1], "mat": W.haar_unitary(rng, 2),
+                      "controls": qs[1:3], "ctrl_vals": [int(v) for v in rng.integers(0, 2, 2)]})
+        elif r == 4 and n >= 2:
+            g.append({"op": "cnot", "q": qs[:2]})
+        elif r == 5 and n >= 2:
+            g.append({"op": "cz", "q": qs[:2]})
+        elif r == 6 and n >= 2:
+            g.append({"op": "swap", "q": qs[:2]})
+        elif r == 7:
+            g.append({"op": ["rx", "ry", "rz"][int(rng.integers(0, 3))], "q": qs[:1],
+                      "angle": float(rng.uniform(0, 6.3))})
+        elif r == 8 and n >= 2:
+            g.append({"op": "dense", "q": qs[:2], "mat": np.diag(np.exp(1j * rng.uniform(0, 6, 4)))})
+        else:
+            g.append({"op": "h", "q": qs[:1]})
+    return g
+
+
+def fused_state(n, gates, dt, theta=None, **plan_kw):
+    c = Circuit.from_records(n, gates)
+    p = Plan(c, dt, **plan_kw)
+    s = State(n, dt)
+    apply_fused(s, p, theta)
+    return s.store(), p.info()
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("kw", [dict(max_k=1), dict(max_k=2), dict(max_k=3),
+                                dict(max_k=2, tile_qubits=6, low_qubits=2),
+                                dict(max_k=3, tile_qubits=7, low_qubits=1),
+                                dict(max_k=5, tile_qubits=8, low_qubits=3)])
+def test_mixed_gates(dt, kw):
+    for n, seed in ((10, 1), (12, 2)):
+        gates = mixed_circuit(n, 150, seed)
+        got, info = fused_state(n, gates, dt, **kw)
+        ref = O.run_circuit(n, gates)
+        err = np.max(np.abs(got - ref))
+        assert err <= AMP_TOL[dt], (err, info)
+
+
+def test_layered_10q_single_pass():
+    n = 10
+    gates = W.layered_rx_rz_cnot(n, 10, seed_key=(0,))
+    got, info = fused_state(n, gates, "c128", max_k=2)
+    assert info["passes"] == 1
+    assert np.max(np.abs(got - O.run_circuit(n, gates))) <= 1e-12
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_layered_many_passes(dt):
+    n = 15
+    gates = W.layered_rx_rz_cnot(n, 10, seed_key=(2, n))
+    got, info = fused_state(n, gates, dt, max_k=2, tile_qubits=9, low_qubits=3)
+    assert info["passes"] > 3
+    assert np.max(np.abs(got - O.run_circuit(n, gates))) <= AMP_TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("max_k", [1, 2, 4])
+def test_random_u_cz_fused(dt, max_k):
+    n = 14
+    gates = W.random_u_cz(n, 20, seed_key=(1, n))
+    got, info = fused_state(n, gates, dt, max_k=max_k, tile_qubits=10, low_qubits=4)
+    assert np.max(np.abs(got - O.run_circuit(n, gates))) <= AMP_TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_parametric_fused_reapply(dt):
+    # the same plan applied with two parameter vectors
+    n = 11
+    gates, npar = W.ry_rz_cnot_ring(n, 4)
+    c = Circuit.from_records(n, gates)
+    p = Plan(c, dt, max_k=2, tile_qubits=8, low_qubits=2)
+    for key in (0, 1):
+        theta = W.uniform_angles(npar, (4, key))
+        s = State(n, dt)
+        apply_fused(s, p, theta)
+        ref = O.run_circuit(n, gates, theta)
+        assert np.max(np.abs(s.store() - ref)) <= AMP_TOL[dt]
+
+
+def test_qft_fused_matches_closed_form():
+    n = 9
+    N = 1 << n
+    g = []
+    for i in range(n - 1, -1, -1):
+        g.append({"op": "h", "q": [i]})
+        for j in range(i - 1, -1, -1):
+            g.append({"op": "dense", "q": [i], "mat": np.diag([1.0, np.exp(2j * np.pi / 2 ** (i - j + 1))]),
+                      "controls": [j], "ctrl_vals": [1]})
+    for q in range(n // 2):
+        g.append({"op": "swap", "q": [q, n - 1 - q]})
+    c = Circuit.from_records(n, g)
+    p = Plan(c, "c128", max_k=3, tile_qubits=6, low_qubits=2)
+    for k in (0, 5, N - 1):
+        s = State(n, "c128")
+        s.set_basis(k)
+        apply_fused(s, p)
+        ref = np.exp(2j * np.pi * np.arange(N) * k / N) / np.sqrt(N)
+        assert np.max(np.abs(s.store() - ref)) <= 1e-12
