@@ -229,6 +229,28 @@ int qsv_observable_info(const qsv_observable* o, int* n, int* terms, int* groups
  * the state's stream. */
 int qsv_expectation(const qsv_state* s, const qsv_observable* o, double* out);
 
+/* out <- O in (out must be a different state of the same n and dtype): the
+ * Pauli-string sum applied to a state, every flip mask in one kernel that reads
+ * in[y ^ F] for each mask F and writes out once. */
+int qsv_apply_observable(const qsv_state* in, const qsv_observable* o, qsv_state* out);
+
+/* ---------------------------------------------------------------- gradients */
+
+/* Energy E = <psi|O|psi> of psi = U(theta)|0...0> and its gradient dE/dtheta
+ * for every parameter slot of the circuit (ParametricRX/RY/RZ of section 4.4,
+ * rotations exp(+i theta P/2)), by one forward pass and one reverse sweep that
+ * uncomputes psi and lambda = O psi gate by gate (adjoint differentiation; the
+ * paper defines the parametric circuits and observables, not this method).
+ * psi, lam: caller-provided workspace states (same n as the circuit, same
+ * dtype, distinct, same stream); on return psi holds |0...0> up to rounding.
+ * forward_plan: optional fused plan of the same circuit and dtype for the
+ * forward pass (NULL = one launch per gate). grad: circuit nparams doubles,
+ * overwritten; a slot used by several gates receives the sum of their
+ * contributions. Gradients accumulate in double. Synchronises the stream. */
+int qsv_adjoint_gradient(const qsv_circuit* c, qsv_plan* forward_plan, const double* theta,
+                         const qsv_observable* o, qsv_state* psi, qsv_state* lam,
+                         double* energy, double* grad);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,5 +2,5 @@
 (Suzuki et al., 2021): HIP kernels behind a C ABI (include/qsv.h), with this
 package as a thin ctypes binding."""
 from .binding import (LIB_PATH, Circuit, Observable, Plan, QsvError, State,  # noqa: F401
-                      apply_circuit, apply_fused, apply_record, expectation, lib, prof_enable,
-                      prof_read)
+                      adjoint_gradient, apply_circuit, apply_fused, apply_observable,
+                      apply_record, expectation, lib, prof_enable, prof_read)

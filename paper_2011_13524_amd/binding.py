@@ -60,6 +60,8 @@ _SIGS = {
     "qsv_plan_info": (_c.c_int, [_vp, _ip, _ip, _ip]),
     "qsv_plan_free": (_c.c_int, [_vp]),
     "qsv_apply_fused": (_c.c_int, [_vp, _vp, _dp]),
+    "qsv_apply_observable": (_c.c_int, [_vp, _vp, _vp]),
+    "qsv_adjoint_gradient": (_c.c_int, [_vp, _vp, _dp, _vp, _vp, _vp, _dp, _dp]),
     "qsv_prof_enable": (_c.c_int, [_c.c_int]),
     "qsv_prof_read": (_c.c_int, [_c.c_char_p, _ip, _dp, _dp]),
 }
@@ -328,6 +330,24 @@ class Plan:
 def apply_fused(state: State, plan: Plan, theta=None):
     keep, tp = _theta_ptr(theta)
     check(lib().qsv_apply_fused(state.h, plan.h, tp))
+
+
+def apply_observable(src: State, obs: Observable, dst: State):
+    check(lib().qsv_apply_observable(src.h, obs.h, dst.h))
+
+
+def adjoint_gradient(circ: Circuit, theta, obs: Observable, psi: State, lam: State,
+                     plan: "Plan | None" = None):
+    """(energy, grad ndarray) through qsv_adjoint_gradient."""
+    _, _, npar = circ.info()
+    t = np.ascontiguousarray(np.asarray(theta if theta is not None else [], dtype=np.float64))
+    if t.size == 0:
+        t = np.zeros(1)
+    grad = np.zeros(max(npar, 1))
+    e = _c.c_double()
+    check(lib().qsv_adjoint_gradient(circ.h, plan.h if plan is not None else None, _dptr(t),
+                                     obs.h, psi.h, lam.h, _c.byref(e), _dptr(grad)))
+    return e.value, grad[:npar]
 
 
 def prof_enable(on: bool):

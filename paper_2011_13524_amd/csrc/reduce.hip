@@ -20,25 +20,11 @@
 #include <map>
 
 #include "dev_common.h"
+#include "observable.h"
 #include "prof.h"
 #include "qsv_internal.h"
 
-struct qsv_observable {
-  int n = 0;
-  struct Term {
-    double coef;
-    uint64_t flip, zmask;
-    int ny;
-  };
-  std::vector<Term> terms;
-};
-
 namespace qsv {
-
-struct GTerm {
-  double re, im;  // alpha_k * i^nY_k
-  uint64_t z;
-};
 
 constexpr int kRedThreads = 256;
 constexpr int kMaxRedBlocks = 2048;
@@ -145,10 +131,7 @@ int red_blocks(uint64_t work) {
   return int(std::max<uint64_t>(1, std::min<uint64_t>(b, kMaxRedBlocks)));
 }
 
-struct Group {
-  uint64_t flip;
-  int begin, count;
-};
+}  // namespace
 
 // Build term groups (by flip mask) as device-ready arrays.
 void build_groups(const qsv_observable* o, std::vector<Group>& groups, std::vector<GTerm>& terms) {
@@ -166,6 +149,8 @@ void build_groups(const qsv_observable* o, std::vector<Group>& groups, std::vect
     terms.insert(terms.end(), kv.second.begin(), kv.second.end());
   }
 }
+
+namespace {
 
 template <typename R>
 int expectation_t(qsv_state* s, const qsv_observable* o, double* out) {
