@@ -43,6 +43,7 @@ typedef struct qsv_state qsv_state;
 typedef struct qsv_circuit qsv_circuit;
 typedef struct qsv_plan qsv_plan;
 typedef struct qsv_observable qsv_observable;
+typedef struct qsv_batch qsv_batch;
 
 typedef enum { QSV_C64 = 1, QSV_C128 = 2 } qsv_dtype;
 
@@ -250,6 +251,35 @@ int qsv_apply_observable(const qsv_state* in, const qsv_observable* o, qsv_state
 int qsv_adjoint_gradient(const qsv_circuit* c, qsv_plan* forward_plan, const double* theta,
                          const qsv_observable* o, qsv_state* psi, qsv_state* lam,
                          double* energy, double* grad);
+
+/* ---------------------------------------------------------------- batches */
+
+/* A batch of independent items (circuit, observable, parameters) whose
+ * energies and adjoint gradients are computed by ONE persistent kernel launch:
+ * each workgroup takes items from a device work queue (largest first) and runs
+ * forward pass, lambda = O psi, energy and reverse sweep for its item with the
+ * item's states in LDS when psi and lambda fit in 64 KiB, else in device
+ * memory. This serves the regime the paper motivates -- small circuits
+ * evaluated many times, where per-call overhead dominates (section 5.1) --
+ * with a design of this library's own. Items take 2..24 qubits; their gates
+ * must be one-qubit gates, rotations, CZ or CNOT (other gates: QSV_EINVAL at
+ * run). The batch copies circuits, observables and parameters when added. */
+int qsv_batch_create(qsv_batch** out);
+int qsv_batch_free(qsv_batch* b);
+int qsv_batch_add(qsv_batch* b, const qsv_circuit* c, const qsv_observable* o, const double* theta);
+
+/* Replace the parameters of item `item` (the circuit's nparams doubles). */
+int qsv_batch_set_theta(qsv_batch* b, int item, const double* theta);
+
+/* Item count and the total parameter count (the length of the grads output). */
+int qsv_batch_info(const qsv_batch* b, int* items, int* total_params);
+
+/* Run every item in dtype `dtype` on `stream` (a hipStream_t, NULL = default).
+ * energies: one double per item (in the order added). grads (nullable): the
+ * items' gradients concatenated in the order added (item i occupies its
+ * circuit's nparams entries). Device buffers are built on the first run for a
+ * dtype and reused. Synchronises the stream. */
+int qsv_batch_run(qsv_batch* b, qsv_dtype dtype, void* stream, double* energies, double* grads);
 
 #ifdef __cplusplus
 }

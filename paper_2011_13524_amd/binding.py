@@ -62,6 +62,12 @@ _SIGS = {
     "qsv_apply_fused": (_c.c_int, [_vp, _vp, _dp]),
     "qsv_apply_observable": (_c.c_int, [_vp, _vp, _vp]),
     "qsv_adjoint_gradient": (_c.c_int, [_vp, _vp, _dp, _vp, _vp, _vp, _dp, _dp]),
+    "qsv_batch_create": (_c.c_int, [_c.POINTER(_vp)]),
+    "qsv_batch_free": (_c.c_int, [_vp]),
+    "qsv_batch_add": (_c.c_int, [_vp, _vp, _vp, _dp]),
+    "qsv_batch_set_theta": (_c.c_int, [_vp, _c.c_int, _dp]),
+    "qsv_batch_info": (_c.c_int, [_vp, _ip, _ip]),
+    "qsv_batch_run": (_c.c_int, [_vp, _c.c_int, _vp, _dp, _dp]),
     "qsv_prof_enable": (_c.c_int, [_c.c_int]),
     "qsv_prof_read": (_c.c_int, [_c.c_char_p, _ip, _dp, _dp]),
 }
@@ -348,6 +354,47 @@ def adjoint_gradient(circ: Circuit, theta, obs: Observable, psi: State, lam: Sta
     check(lib().qsv_adjoint_gradient(circ.h, plan.h if plan is not None else None, _dptr(t),
                                      obs.h, psi.h, lam.h, _c.byref(e), _dptr(grad)))
     return e.value, grad[:npar]
+
+
+class Batch:
+    """Batched energies + adjoint gradients in one persistent launch (qsv_batch)."""
+
+    def __init__(self):
+        h = _vp()
+        check(lib().qsv_batch_create(_c.byref(h)))
+        self.h = h
+        self._nparams = []
+
+    def add(self, circ: Circuit, obs: Observable, theta=None):
+        keep, tp = _theta_ptr(theta)
+        check(lib().qsv_batch_add(self.h, circ.h, obs.h, tp))
+        self._nparams.append(circ.info()[2])
+
+    def set_theta(self, item: int, theta):
+        keep, tp = _theta_ptr(theta)
+        check(lib().qsv_batch_set_theta(self.h, item, tp))
+
+    def run(self, dtype: str = "c64", stream=None):
+        """Returns (energies ndarray, list of per-item gradient ndarrays)."""
+        items, tot = _c.c_int(), _c.c_int()
+        check(lib().qsv_batch_info(self.h, _c.byref(items), _c.byref(tot)))
+        e = np.zeros(max(items.value, 1))
+        g = np.zeros(max(tot.value, 1))
+        check(lib().qsv_batch_run(self.h, QSV_C64 if dtype == "c64" else QSV_C128,
+                                  _stream_handle(stream), _dptr(e), _dptr(g)))
+        out, off = [], 0
+        for p in self._nparams:
+            out.append(g[off:off + p].copy())
+            off += p
+        return e[:items.value], out
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None:
+                lib().qsv_batch_free(self.h)
+                self.h = None
+        except Exception:
+            pass
 
 
 def prof_enable(on: bool):

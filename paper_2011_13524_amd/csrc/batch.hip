@@ -1,0 +1,529 @@
+// Batched energies and adjoint gradients: many independent (circuit, theta,
+// observable) items, possibly of different qubit counts, in ONE persistent
+// kernel launch. The paper motivates this regime -- small circuits simulated
+// many times, where per-call overhead dominates (section 5.1, T_over; the
+// GPU per-call overhead it reports in section 6) -- but does not describe a
+// batched method; this is the library's own design.
+//
+// Each workgroup pulls item indices from a device work queue (items ordered
+// largest first for balance) and runs, for its item, entirely inside the
+// workgroup: psi = |0...0>, the circuit gate by gate, lambda = H psi, E =
+// Re<psi|lambda>, and the reverse sweep of qsv_adjoint_gradient with FP64
+// workgroup reductions. psi and lambda live in LDS when both fit, otherwise in
+// a per-item slice of device memory (served from L2 / Infinity Cache for the
+// sizes this targets). Every workgroup leaves the loop once the queue is
+// exhausted, so the grid always drains.
+#include <algorithm>
+#include <cmath>
+
+#include "circuit.h"
+#include "dev_common.h"
+#include "observable.h"
+#include "prof.h"
+
+namespace qsv {
+
+constexpr int kBatchThreads = 512;
+
+enum BatchOpKind { BO_ROT = 0, BO_CZ = 1, BO_CNOT = 2, BO_DENSE1 = 3 };
+
+struct BatchOp {
+  int kind;
+  int q0, q1;    // ROT/DENSE1: q0 target; CZ: q0, q1; CNOT: q0 control, q1 target
+  int pauli;     // ROT
+  int slot;      // ROT: parameter slot (>= 0) or -1 for a fixed angle
+  int moff;      // DENSE1 / fixed ROT: offset of the 2x2 matrix in the pool
+};
+
+struct BatchItem {
+  int n;
+  int op_begin, op_count;
+  int grp_begin, grp_count;
+  int theta_off, grad_off, nparams;
+  uint64_t psi_off, lam_off;  // amplitude offsets into the state buffer (global items)
+};
+
+struct BatchGroup {
+  uint64_t flip;
+  int begin, count;
+};
+
+struct BatchArgs {
+  const BatchItem* items;
+  const int* order;
+  int nitems;
+  int* queue;
+  const BatchOp* ops;
+  const double* pool;  // complex128 2x2 matrices
+  const BatchGroup* groups;
+  const GTerm* terms;
+  const double* theta;
+  double* energies;
+  double* grads;
+  void* states;
+  size_t lds_state_bytes;  // dynamic LDS available for psi + lambda
+};
+
+__device__ __forceinline__ double wg_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();  // red[] may still be read from the previous reduction
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int i = 0; i < int(blockDim.x >> 6); ++i) r += red[i];  // same order in every thread
+  return r;
+}
+
+template <typename R>
+__device__ __forceinline__ M2<R> rot2(int pauli, double t) {
+  // exp(i t P/2) = cos(t/2) I + i sin(t/2) P
+  double s, c;
+  sincos(0.5 * t, &s, &c);
+  const R cr = R(c), sr = R(s);
+  if (pauli == 1) return {{cr, 0}, {0, sr}, {0, sr}, {cr, 0}};
+  if (pauli == 2) return {{cr, 0}, {sr, 0}, {-sr, 0}, {cr, 0}};
+  return {{cr, sr}, {0, 0}, {0, 0}, {cr, -sr}};
+}
+
+template <typename R>
+__device__ __forceinline__ M2<R> pool2(const double* p, bool dag) {
+  const cx<R> a{R(p[0]), R(p[1])}, b{R(p[2]), R(p[3])}, c{R(p[4]), R(p[5])}, d{R(p[6]), R(p[7])};
+  if (!dag) return {a, b, c, d};
+  return {{a.re, -a.im}, {c.re, -c.im}, {b.re, -b.im}, {d.re, -d.im}};
+}
+
+template <typename R>
+__device__ __forceinline__ void wg_apply_2x2(cx<R>* s, int n, int q, const M2<R>& u) {
+  const uint32_t half = 1u << (n - 1), bit = 1u << q;
+  for (uint32_t i = threadIdx.x; i < half; i += blockDim.x) {
+    const uint32_t x0 = ((i >> q) << (q + 1)) | (i & (bit - 1));
+    const cx<R> a = s[x0], b = s[x0 | bit];
+    s[x0] = cfma(u.m00, a, u.m01 * b);
+    s[x0 | bit] = cfma(u.m10, a, u.m11 * b);
+  }
+}
+
+__device__ __forceinline__ uint32_t ins2(uint32_t i, int lo, int hi) {
+  i = ((i >> lo) << (lo + 1)) | (i & ((1u << lo) - 1));
+  i = ((i >> hi) << (hi + 1)) | (i & ((1u << hi) - 1));
+  return i;
+}
+
+template <typename R>
+__device__ __forceinline__ void wg_apply_op(cx<R>* s, int n, const BatchOp& op, const double* theta,
+                                            const double* pool, bool dag) {
+  if (op.kind == BO_ROT) {
+    const double t = op.slot >= 0 ? theta[op.slot] : 0.0;
+    M2<R> u = op.slot >= 0 ? rot2<R>(op.pauli, dag ? -t : t) : pool2<R>(pool + op.moff, dag);
+    wg_apply_2x2(s, n, op.q0, u);
+  } else if (op.kind == BO_DENSE1) {
+    wg_apply_2x2(s, n, op.q0, pool2<R>(pool + op.moff, dag));
+  } else {
+    const int lo = min(op.q0, op.q1), hi = max(op.q0, op.q1);
+    const uint32_t quarter = 1u << (n - 2);
+    const uint32_t b0 = 1u << op.q0, b1 = 1u << op.q1;
+    for (uint32_t i = threadIdx.x; i < quarter; i += blockDim.x) {
+      const uint32_t x = ins2(i, lo, hi);
+      if (op.kind == BO_CZ) {
+        const cx<R> v = s[x | b0 | b1];
+        s[x | b0 | b1] = {-v.re, -v.im};
+      } else {  // CNOT: swap target within control = 1
+        const cx<R> a = s[x | b0], b = s[x | b0 | b1];
+        s[x | b0] = b;
+        s[x | b0 | b1] = a;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBatchThreads) k_batch(BatchArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double red[kBatchThreads / 64];
+  __shared__ int s_item;
+  while (true) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const int it = s_item;
+    if (it >= a.nitems) break;
+    const BatchItem I = a.items[a.order[it]];
+    const int n = I.n;
+    const uint32_t N = 1u << n;
+    cx<R>* psi;
+    cx<R>* lam;
+    if (size_t(2) * N * sizeof(cx<R>) <= a.lds_state_bytes) {
+      psi = reinterpret_cast<cx<R>*>(smem);
+      lam = psi + N;
+    } else {
+      psi = reinterpret_cast<cx<R>*>(a.states) + I.psi_off;
+      lam = reinterpret_cast<cx<R>*>(a.states) + I.lam_off;
+    }
+    const double* theta = a.theta + I.theta_off;
+    // |0...0>
+    for (uint32_t x = threadIdx.x; x < N; x += blockDim.x) psi[x] = {R(x == 0 ? 1 : 0), R(0)};
+    __syncthreads();
+    // forward
+    for (int o = 0; o < I.op_count; ++o) wg_apply_op<R>(psi, n, a.ops[I.op_begin + o], theta, a.pool, false);
+    // lambda = H psi
+    for (uint32_t y = threadIdx.x; y < N; y += blockDim.x) {
+      double ar = 0.0, ai = 0.0;
+      for (int g = 0; g < I.grp_count; ++g) {
+        const BatchGroup G = a.groups[I.grp_begin + g];
+        const uint32_t x = y ^ uint32_t(G.flip);
+        const cx<R> v = psi[x];
+        double cr = 0.0, ci = 0.0;
+        for (int k = G.begin; k < G.begin + G.count; ++k) {
+          const GTerm t = a.terms[k];
+          const bool neg = __popc(x & uint32_t(t.z)) & 1;
+          cr += neg ? -t.re : t.re;
+          ci += neg ? -t.im : t.im;
+        }
+        ar += cr * double(v.re) - ci * double(v.im);
+        ai += cr * double(v.im) + ci * double(v.re);
+      }
+      lam[y] = {R(ar), R(ai)};
+    }
+    __syncthreads();
+    // E = Re <psi|lambda>
+    double e = 0.0;
+    for (uint32_t x = threadIdx.x; x < N; x += blockDim.x)
+      e += double(psi[x].re) * double(lam[x].re) + double(psi[x].im) * double(lam[x].im);
+    e = wg_sum(e, red);
+    if (threadIdx.x == 0) a.energies[a.order[it]] = e;
+    double* grad = a.grads + I.grad_off;
+    for (int i = threadIdx.x; i < I.nparams; i += blockDim.x) grad[i] = 0.0;
+    __syncthreads();
+    // reverse sweep
+    for (int o = I.op_count - 1; o >= 0; --o) {
+      const BatchOp op = a.ops[I.op_begin + o];
+      if (op.kind == BO_ROT && op.slot >= 0) {
+        const M2<R> ud = rot2<R>(op.pauli, -theta[op.slot]);
+        const uint32_t half = N >> 1, bit = 1u << op.q0;
+        double acc = 0.0;
+        for (uint32_t i = threadIdx.x; i < half; i += blockDim.x) {
+          const uint32_t x0 = ((i >> op.q0) << (op.q0 + 1)) | (i & (bit - 1));
+          const uint32_t x1 = x0 | bit;
+          const cx<R> a0 = psi[x0], a1 = psi[x1], l0 = lam[x0], l1 = lam[x1];
+          const double a0r = a0.re, a0i = a0.im, a1r = a1.re, a1i = a1.im;
+          const double l0r = l0.re, l0i = l0.im, l1r = l1.re, l1i = l1.im;
+          double im;
+          if (op.pauli == 1) im = (l0r * a1i - l0i * a1r) + (l1r * a0i - l1i * a0r);
+          else if (op.pauli == 2) im = -(l0r * a1r + l0i * a1i) + (l1r * a0r + l1i * a0i);
+          else im = (l0r * a0i - l0i * a0r) - (l1r * a1i - l1i * a1r);
+          acc -= im;
+          psi[x0] = cfma(ud.m00, a0, ud.m01 * a1);
+          psi[x1] = cfma(ud.m10, a0, ud.m11 * a1);
+          lam[x0] = cfma(ud.m00, l0, ud.m01 * l1);
+          lam[x1] = cfma(ud.m10, l0, ud.m11 * l1);
+        }
+        acc = wg_sum(acc, red);
+        if (threadIdx.x == 0) grad[op.slot] += acc;
+        __syncthreads();
+      } else {
+        wg_apply_op<R>(psi, n, op, theta, a.pool, true);
+        wg_apply_op<R>(lam, n, op, theta, a.pool, true);
+      }
+    }
+  }
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+}  // namespace qsv
+
+// ------------------------------------------------------------------ host
+
+struct qsv_batch {
+  struct Item {
+    qsv_circuit c;
+    qsv_observable o;
+    std::vector<double> theta;
+  };
+  std::vector<Item> items;
+  // device cache (per dtype)
+  int dev_dtype = 0;
+  size_t state_elems = 0;
+  void* d_states = nullptr;
+  void* d_tables = nullptr;
+  size_t tables_bytes = 0;
+  size_t off_items = 0, off_order = 0, off_queue = 0, off_ops = 0, off_pool = 0, off_groups = 0,
+         off_terms = 0, off_theta = 0, off_energy = 0, off_grads = 0;
+  int total_params = 0;
+  size_t lds_bytes = 0;
+  int grid = 0;
+};
+
+namespace qsv {
+
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int build_device(qsv_batch* b, qsv_dtype dt) {
+  const size_t S = amp_bytes(dt);
+  std::vector<BatchItem> items(b->items.size());
+  std::vector<BatchOp> ops;
+  std::vector<double> pool;
+  std::vector<BatchGroup> groups;
+  std::vector<GTerm> terms;
+  std::vector<double> theta;
+  // LDS for psi + lambda: 64 KiB keeps two workgroups per CU
+  const size_t lds = 65536;
+  size_t state_elems = 0;
+  int grad_off = 0;
+  for (size_t i = 0; i < b->items.size(); ++i) {
+    const auto& it = b->items[i];
+    BatchItem& I = items[i];
+    I.n = it.c.n;
+    I.op_begin = int(ops.size());
+    for (const Gate& g : it.c.gates) {
+      BatchOp op{};
+      if (g.kind == Gate::ROTATION) {
+        op.kind = BO_ROT;
+        op.q0 = g.targets[0];
+        op.pauli = g.pauli;
+        op.slot = g.slot;
+        if (g.slot < 0) {
+          cd m[4];
+          rotation_matrix(g.pauli, g.fixed_angle, m);
+          op.moff = int(pool.size());
+          for (int j = 0; j < 4; ++j) {
+            pool.push_back(m[j].re);
+            pool.push_back(m[j].im);
+          }
+        }
+      } else {
+        std::vector<cd> m = g.mat;
+        std::vector<int> tq = g.targets;
+        uint64_t cm = 0, cv = 0;
+        for (size_t j = 0; j < g.controls.size(); ++j) {
+          cm |= uint64_t(1) << g.controls[j];
+          if (g.ctrl_vals[j]) cv |= uint64_t(1) << g.controls[j];
+        }
+        extract_controls(m, tq, cm, cv);
+        const bool one_ctrl_on = __builtin_popcountll(cm) == 1 && cv == cm;
+        auto is = [&](int r, int c, double re, double im) {
+          return m[r * 2 + c].re == re && m[r * 2 + c].im == im;
+        };
+        if (tq.size() == 1 && cm == 0) {
+          op.kind = BO_DENSE1;
+          op.q0 = tq[0];
+          op.moff = int(pool.size());
+          for (int j = 0; j < 4; ++j) {
+            pool.push_back(m[j].re);
+            pool.push_back(m[j].im);
+          }
+        } else if (tq.size() == 1 && one_ctrl_on && is(0, 0, 1, 0) && is(0, 1, 0, 0) &&
+                   is(1, 0, 0, 0) && is(1, 1, -1, 0)) {
+          op.kind = BO_CZ;
+          op.q0 = __builtin_ctzll(cm);
+          op.q1 = tq[0];
+        } else if (tq.size() == 1 && one_ctrl_on && is(0, 0, 0, 0) && is(0, 1, 1, 0) &&
+                   is(1, 0, 1, 0) && is(1, 1, 0, 0)) {
+          op.kind = BO_CNOT;
+          op.q0 = __builtin_ctzll(cm);
+          op.q1 = tq[0];
+        } else {
+          return fail(QSV_EINVAL, "batched items support one-qubit gates, rotations, CZ and CNOT");
+        }
+      }
+      ops.push_back(op);
+    }
+    I.op_count = int(ops.size()) - I.op_begin;
+    std::vector<Group> gs;
+    std::vector<GTerm> ts;
+    build_groups(&it.o, gs, ts);
+    I.grp_begin = int(groups.size());
+    I.grp_count = int(gs.size());
+    const int tbase = int(terms.size());
+    for (const Group& g : gs) groups.push_back({g.flip, g.begin + tbase, g.count});
+    terms.insert(terms.end(), ts.begin(), ts.end());
+    I.theta_off = int(theta.size());
+    I.nparams = it.c.nparams;
+    theta.insert(theta.end(), it.theta.begin(), it.theta.end());
+    I.grad_off = grad_off;
+    grad_off += it.c.nparams;
+    const uint64_t N = dim(I.n);
+    if (2 * N * S <= lds) {
+      I.psi_off = I.lam_off = 0;
+    } else {
+      I.psi_off = state_elems;
+      I.lam_off = state_elems + N;
+      state_elems += 2 * N;
+    }
+  }
+  // largest items first
+  std::vector<int> order(items.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = int(i);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return items[x].n > items[y].n; });
+
+  size_t off = 0;
+  b->off_items = off; off = align_up(off + items.size() * sizeof(BatchItem), 256);
+  b->off_order = off; off = align_up(off + order.size() * sizeof(int), 256);
+  b->off_queue = off; off = align_up(off + sizeof(int), 256);
+  b->off_ops = off; off = align_up(off + std::max<size_t>(1, ops.size()) * sizeof(BatchOp), 256);
+  b->off_pool = off; off = align_up(off + std::max<size_t>(1, pool.size()) * sizeof(double), 256);
+  b->off_groups = off; off = align_up(off + std::max<size_t>(1, groups.size()) * sizeof(BatchGroup), 256);
+  b->off_terms = off; off = align_up(off + std::max<size_t>(1, terms.size()) * sizeof(GTerm), 256);
+  b->off_theta = off; off = align_up(off + std::max<size_t>(1, theta.size()) * sizeof(double), 256);
+  b->off_energy = off; off = align_up(off + items.size() * sizeof(double), 256);
+  b->off_grads = off; off = align_up(off + std::max<int>(1, grad_off) * sizeof(double), 256);
+  if (hipMalloc(&b->d_tables, off) != hipSuccess) return fail(QSV_ENOMEM, "batch table allocation failed");
+  b->tables_bytes = off;
+  if (state_elems && hipMalloc(&b->d_states, state_elems * S) != hipSuccess)
+    return fail(QSV_ENOMEM, "batch state allocation failed (%zu bytes)", state_elems * S);
+  char* d = static_cast<char*>(b->d_tables);
+  auto put = [&](size_t o, const void* src, size_t bytes) -> int {
+    if (bytes) QSV_HIP_CHECK(hipMemcpy(d + o, src, bytes, hipMemcpyHostToDevice));
+    return QSV_OK;
+  };
+  int rc;
+  if ((rc = put(b->off_items, items.data(), items.size() * sizeof(BatchItem)))) return rc;
+  if ((rc = put(b->off_order, order.data(), order.size() * sizeof(int)))) return rc;
+  if ((rc = put(b->off_ops, ops.data(), ops.size() * sizeof(BatchOp)))) return rc;
+  if ((rc = put(b->off_pool, pool.data(), pool.size() * sizeof(double)))) return rc;
+  if ((rc = put(b->off_groups, groups.data(), groups.size() * sizeof(BatchGroup)))) return rc;
+  if ((rc = put(b->off_terms, terms.data(), terms.size() * sizeof(GTerm)))) return rc;
+  b->state_elems = state_elems;
+  b->total_params = grad_off;
+  b->lds_bytes = lds;
+  b->dev_dtype = int(dt);
+  return QSV_OK;
+}
+
+template <typename R>
+int run_t(qsv_batch* b, hipStream_t st, double* energies, double* grads) {
+  char* d = static_cast<char*>(b->d_tables);
+  std::vector<double> theta;
+  for (const auto& it : b->items) theta.insert(theta.end(), it.theta.begin(), it.theta.end());
+  if (!theta.empty())
+    QSV_HIP_CHECK(hipMemcpyAsync(d + b->off_theta, theta.data(), theta.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, st));
+  if (b->grid == 0) {
+    int dev = 0, cus = 0, per = 0;
+    QSV_HIP_CHECK(hipGetDevice(&dev));
+    QSV_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    QSV_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch<R>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds_bytes)));
+    QSV_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<R>, kBatchThreads,
+                                                               b->lds_bytes));
+    b->grid = std::max(1, cus * std::max(1, per));
+  }
+  BatchArgs a;
+  a.items = reinterpret_cast<const BatchItem*>(d + b->off_items);
+  a.order = reinterpret_cast<const int*>(d + b->off_order);
+  a.nitems = int(b->items.size());
+  a.queue = reinterpret_cast<int*>(d + b->off_queue);
+  a.ops = reinterpret_cast<const BatchOp*>(d + b->off_ops);
+  a.pool = reinterpret_cast<const double*>(d + b->off_pool);
+  a.groups = reinterpret_cast<const BatchGroup*>(d + b->off_groups);
+  a.terms = reinterpret_cast<const GTerm*>(d + b->off_terms);
+  a.theta = reinterpret_cast<const double*>(d + b->off_theta);
+  a.energies = reinterpret_cast<double*>(d + b->off_energy);
+  a.grads = reinterpret_cast<double*>(d + b->off_grads);
+  a.states = b->d_states;
+  a.lds_state_bytes = b->lds_bytes;
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, a.queue);
+  {
+    ProfScope ps("batch", 0.0, st);
+    hipLaunchKernelGGL((k_batch<R>), dim3(b->grid), dim3(kBatchThreads), b->lds_bytes, st, a);
+  }
+  QSV_HIP_CHECK(hipGetLastError());
+  QSV_HIP_CHECK(hipMemcpyAsync(energies, a.energies, b->items.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, st));
+  if (grads && b->total_params)
+    QSV_HIP_CHECK(hipMemcpyAsync(grads, a.grads, size_t(b->total_params) * sizeof(double),
+                                 hipMemcpyDeviceToHost, st));
+  QSV_HIP_CHECK(hipStreamSynchronize(st));
+  return QSV_OK;
+}
+
+void release_device(qsv_batch* b) {
+  if (b->d_tables) (void)hipFree(b->d_tables);
+  if (b->d_states) (void)hipFree(b->d_states);
+  b->d_tables = b->d_states = nullptr;
+  b->dev_dtype = 0;
+  b->grid = 0;
+}
+
+}  // namespace
+
+}  // namespace qsv
+
+using namespace qsv;
+
+extern "C" {
+
+int qsv_batch_create(qsv_batch** out) {
+  clear_error();
+  if (!out) return fail(QSV_EINVAL, "null output handle");
+  *out = new (std::nothrow) qsv_batch();
+  return *out ? QSV_OK : fail(QSV_ENOMEM, "host allocation failed");
+}
+
+int qsv_batch_free(qsv_batch* b) {
+  clear_error();
+  if (!b) return QSV_OK;
+  release_device(b);
+  delete b;
+  return QSV_OK;
+}
+
+int qsv_batch_add(qsv_batch* b, const qsv_circuit* c, const qsv_observable* o, const double* theta) {
+  clear_error();
+  if (!b || !c || !o) return fail(QSV_EINVAL, "null argument");
+  if (c->n != o->n) return fail(QSV_ERANGE, "circuit and observable qubit counts differ");
+  if (c->n < 2 || c->n > 24) return fail(QSV_ERANGE, "batched items take 2..24 qubits");
+  if (c->nparams > 0 && !theta) return fail(QSV_EINVAL, "null theta");
+  qsv_batch::Item it;
+  it.c = *c;
+  it.o = *o;
+  if (c->nparams) it.theta.assign(theta, theta + c->nparams);
+  b->items.push_back(std::move(it));
+  release_device(b);
+  return QSV_OK;
+}
+
+int qsv_batch_set_theta(qsv_batch* b, int item, const double* theta) {
+  clear_error();
+  if (!b) return fail(QSV_EINVAL, "null batch");
+  if (item < 0 || item >= int(b->items.size())) return fail(QSV_ERANGE, "item out of range");
+  auto& it = b->items[item];
+  if (it.c.nparams && !theta) return fail(QSV_EINVAL, "null theta");
+  std::copy(theta, theta + it.c.nparams, it.theta.begin());
+  return QSV_OK;
+}
+
+int qsv_batch_info(const qsv_batch* b, int* items, int* total_params) {
+  clear_error();
+  if (!b) return fail(QSV_EINVAL, "null batch");
+  int tp = 0;
+  for (const auto& it : b->items) tp += it.c.nparams;
+  if (items) *items = int(b->items.size());
+  if (total_params) *total_params = tp;
+  return QSV_OK;
+}
+
+int qsv_batch_run(qsv_batch* b, qsv_dtype dtype, void* stream, double* energies, double* grads) {
+  clear_error();
+  if (!b) return fail(QSV_EINVAL, "null batch");
+  if (!energies) return fail(QSV_EINVAL, "null energies");
+  if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_EDTYPE, "unknown dtype");
+  if (b->items.empty()) return QSV_OK;
+  if (b->dev_dtype != int(dtype)) {
+    release_device(b);
+    int rc = build_device(b, dtype);
+    if (rc) {
+      release_device(b);
+      return rc;
+    }
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return dtype == QSV_C64 ? run_t<float>(b, st, energies, grads) : run_t<double>(b, st, energies, grads);
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+"""CPU-only checks of the C ABI: the library loads and exports every symbol
+include/qsv.h declares, and every host-side validation path returns the
+documented error code without touching a device (no compute is launched).
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2011_13524_amd as Q
+from paper_2011_13524_amd import binding as B
+from paper_2011_13524_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qsv.h")
+
+EINVAL, ERANGE, EDUP, ENOMEM, EHIP, EDTYPE, ENODEV = -1, -2, -3, -4, -5, -6, -7
+
+
+def declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(qsv_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    L = Q.lib()
+    names = declared()
+    assert len(names) >= 30
+    for name in names:
+        assert hasattr(L, name), name
+        assert name in B.declared_symbols(), name
+
+
+def test_version_and_last_error():
+    L = Q.lib()
+    assert L.qsv_version() >= 100
+    h = ctypes.c_void_p()
+    assert L.qsv_circuit_create(0, ctypes.byref(h)) == ERANGE
+    assert b"qubit count" in L.qsv_last_error()
+
+
+def _code(fn, *a):
+    with pytest.raises(Q.QsvError) as ei:
+        fn(*a)
+    return ei.value.code
+
+
+def test_circuit_validation():
+    c = Q.Circuit(4)
+    assert _code(c.add_record, {"op": "dense", "q": [4], "mat": np.eye(2)}) == ERANGE
+    assert _code(c.add_record, {"op": "dense", "q": [1, 1], "mat": np.eye(4)}) == EDUP
+    assert _code(c.add_record, {"op": "dense", "q": [0], "mat": np.eye(2), "controls": [0],
+                                "ctrl_vals": [1]}) == EDUP
+    assert _code(c.add_record, {"op": "dense", "q": [0], "mat": np.eye(2), "controls": [1],
+                                "ctrl_vals": [2]}) == EINVAL
+    assert _code(c.add_record, {"op": "cnot", "q": [3, 3]}) == EDUP
+    L = Q.lib()
+    assert L.qsv_circuit_add_rotation(c.h, 4, 0, 0) == EINVAL
+    assert L.qsv_circuit_add_rotation(c.h, 1, 9, 0) == ERANGE
+    assert L.qsv_circuit_add_rotation(c.h, 1, 0, -1) == ERANGE
+    m = np.eye(64, dtype=np.complex128)
+    t = np.arange(6, dtype=np.int32)
+    assert L.qsv_circuit_add_gate(c.h, m.ctypes.data_as(B._dp), t.ctypes.data_as(B._ip), 6, None,
+                                  None, 0) == EINVAL
+    assert c.info() == (4, 0, 0)
+
+
+def test_observable_validation():
+    o = Q.Observable(3)
+    assert _code(o.add_term, 1.0, [(3, 1)]) == ERANGE
+    assert _code(o.add_term, 1.0, [(0, 4)]) == EINVAL
+    assert _code(o.add_term, 1.0, [(1, 1), (1, 3)]) == EDUP
+    o.add_term(0.5, [(0, 1), (1, 2)])
+    o.add_term(0.5, [(0, 1), (1, 1), (2, 3)])
+    o.add_term(0.1, [])
+    # X0Y1 and X0X1Z2 share the flip mask {0, 1}; the identity has flip mask 0
+    assert o.info() == (3, 3, 2)
+
+
+def test_state_without_device():
+    L = Q.lib()
+    h = ctypes.c_void_p()
+    rc = L.qsv_state_alloc(4, 1, None, ctypes.byref(h))
+    assert rc in (ENODEV, 0)
+    if rc == 0:  # running on a GPU machine: nothing more to check here
+        L.qsv_state_free(h)
+        return
+    assert L.qsv_state_alloc(0, 1, None, ctypes.byref(h)) == ERANGE
+    assert L.qsv_state_alloc(4, 7, None, ctypes.byref(h)) == EDTYPE
+
+
+def test_validation_before_any_launch_on_wrapped_memory():
+    # a wrapped host buffer is never touched: each call fails validation first
+    L = Q.lib()
+    buf = np.zeros(32 + 4, dtype=np.float64)
+    addr = (buf.ctypes.data + 15) // 16 * 16
+    h = ctypes.c_void_p()
+    assert L.qsv_state_wrap(ctypes.c_void_p(addr), 4, 2, None, ctypes.byref(h)) == 0
+    s = Q.State(4, "c128", _handle=h)
+    assert _code(s.apply_gate, np.eye(2), [4]) == ERANGE
+    assert _code(s.apply_gate, np.eye(4), [2, 2]) == EDUP
+    assert _code(s.apply_gate, np.eye(2), [0], [1], [3]) == EINVAL
+    assert _code(s.apply_named, "cnot", [1]) == EINVAL
+    assert _code(s.set_basis, 16) == ERANGE
+    h2 = ctypes.c_void_p()
+    assert L.qsv_state_wrap(ctypes.c_void_p(addr + 8), 4, 2, None, ctypes.byref(h2)) == EINVAL
+    assert h2.value is None
+    c = Q.Circuit(5)
+    assert L.qsv_apply_circuit(s.h, c.h, None) == ERANGE
+    o = Q.Observable(5)
+    out = ctypes.c_double()
+    assert L.qsv_expectation(s.h, o.h, ctypes.byref(out)) == ERANGE
+    np.testing.assert_array_equal(buf, 0.0)
+
+
+def test_planner_on_host():
+    n = 30
+    gates = W.layered_rx_rz_cnot(n, 10, seed_key=(2,))
+    c = Q.Circuit.from_records(n, gates)
+    info = Q.Plan(c, "c64", max_k=2).info()
+    assert info["gates"] == 890
+    assert info["blocks"] == 320  # RX/RZ pairs merged with the ladder CNOT into 2-qubit blocks
+    assert info["passes"] <= 40
+    small = Q.Circuit.from_records(10, W.layered_rx_rz_cnot(10, 10, seed_key=(0,)))
+    assert Q.Plan(small, "c128", max_k=2).info()["passes"] == 1
+    assert _code(Q.Plan, c, "c64", 0) == EINVAL
+    assert _code(Q.Plan, c, "c128", 2, 14) == EINVAL
+    assert _code(Q.Plan, c, "c64", 5, 8, 6) == EINVAL
+
+
+def test_batch_validation():
+    b = Q.Batch()
+    c = Q.Circuit(3)
+    o = Q.Observable(4)
+    assert _code(b.add, c, o) == ERANGE
+    c1 = Q.Circuit(1)
+    assert _code(b.add, c1, Q.Observable(1)) == ERANGE
+    c3 = Q.Circuit.from_records(3, [{"op": "ry", "q": [0], "slot": 1}])
+    L = Q.lib()
+    assert L.qsv_batch_add(b.h, c3.h, Q.Observable(3).h, None) == EINVAL
+    b.add(c3, Q.Observable(3), [0.1, 0.2])
+    items, tot = ctypes.c_int(), ctypes.c_int()
+    assert L.qsv_batch_info(b.h, ctypes.byref(items), ctypes.byref(tot)) == 0
+    assert (items.value, tot.value) == (1, 2)
+    assert L.qsv_batch_set_theta(b.h, 1, None) == ERANGE

@@ -1,0 +1,77 @@
+"""GPU parity of the batched persistent launch: energies and gradients of
+every item against the CPU oracle (small items, exact parameter-shift) and
+against the single-item adjoint path (larger items, which is itself
+oracle-pinned).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2011_13524_amd import Batch, Circuit, Observable, State, adjoint_gradient
+from paper_2011_13524_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-10, "c64": 2e-5}
+
+
+def small_items():
+    items = []
+    for i, n in enumerate((2, 3, 4, 5, 6, 3, 5, 2)):
+        if i % 2 == 0:
+            gates, npar = W.hea_ry_rz_cz(n, 2)
+            obs = W.tfim_chain(n)
+        else:
+            gates, npar = W.ry_rz_cnot_ring(n, 2)
+            obs = W.random_pauli_observable(n, 12, (1, n), seed_key=(7, i)) + [(0.25, [])]
+        gates = gates + [{"op": "h", "q": [0]}, {"op": "rx", "q": [n - 1], "angle": 0.3}]
+        theta = W.uniform_angles(npar, (7, i, 1))
+        items.append((n, gates, theta, obs))
+    return items
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_small_items_vs_oracle(dt):
+    items = small_items()
+    b = Batch()
+    for n, gates, theta, obs in items:
+        b.add(Circuit.from_records(n, gates), Observable(n, obs), theta)
+    e, g = b.run(dt)
+    for i, (n, gates, theta, obs) in enumerate(items):
+        scale = sum(abs(c) for c, _ in obs)
+        assert abs(e[i] - O.energy(n, gates, theta, obs)) <= TOL[dt] * scale, i
+        assert np.max(np.abs(g[i] - O.param_shift_grad(n, gates, theta, obs))) <= TOL[dt] * scale, i
+    # second run with new parameters for one item
+    n, gates, theta, obs = items[3]
+    theta2 = theta + 0.5
+    b.set_theta(3, theta2)
+    e2, g2 = b.run(dt)
+    scale = sum(abs(c) for c, _ in obs)
+    assert abs(e2[3] - O.energy(n, gates, theta2, obs)) <= TOL[dt] * scale
+    assert abs(e2[0] - e[0]) <= 1e-15 * max(1.0, abs(e[0])) * 10
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_hea_items_mixed_sizes(dt):
+    # batched-VQE structure at the sizes of the workload (12..18 qubits),
+    # 24 items, against the single-item adjoint path; one 12-qubit item also
+    # against the oracle's exact shift rule.
+    items = W.batch_items(24, seed=3)
+    b = Batch()
+    for it in items:
+        b.add(Circuit.from_records(it["n"], it["gates"]), Observable(it["n"], it["obs"]), it["theta"])
+    e, g = b.run(dt)
+    for i, it in enumerate(items):
+        n = it["n"]
+        psi, lam = State(n, dt), State(n, dt)
+        e1, g1 = adjoint_gradient(Circuit.from_records(n, it["gates"]), it["theta"],
+                                  Observable(n, it["obs"]), psi, lam)
+        scale = sum(abs(c) for c, _ in it["obs"])
+        assert abs(e[i] - e1) <= TOL[dt] * scale, (i, n)
+        assert np.max(np.abs(g[i] - g1)) <= TOL[dt] * scale, (i, n)
+    twelve = [i for i, it in enumerate(items) if it["n"] == 12]
+    assert twelve
+    it = items[twelve[0]]
+    scale = sum(abs(c) for c, _ in it["obs"])
+    ref = O.param_shift_grad(12, it["gates"], it["theta"], it["obs"], slots=range(0, 192, 17))
+    assert np.max(np.abs(g[twelve[0]][0:192:17] - ref)) <= TOL[dt] * scale
