@@ -1,20 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of the state-vector hot path on one MI355X.
 
-Workload (one "step"): a 30-qubit complex64 state is reset to |0...0>, a
-10-layer circuit of RX(theta) then RZ(phi) on every qubit followed by a CNOT
-ladder (i -> i+1) is applied (890 gates), and <H> is evaluated for H = 200
-random weight-4 Pauli strings with N(0, 1) coefficients, accumulated in FP64.
-Inputs are seeded and synthetic (no dataset exists for this workload).
+Headline workload (one "step"): a 30-qubit complex64 state is reset to
+|0...0>, a 10-layer circuit of RX(theta) then RZ(phi) on every qubit followed
+by a CNOT ladder (i -> i+1) is applied (890 gates, fused into tile passes),
+and <H> is evaluated for H = 200 random weight-4 Pauli strings with N(0, 1)
+coefficients, accumulated in FP64. Inputs are seeded and synthetic.
 
-value = circuit gates per second over whole steps (expectation included);
-extra fields give the HBM bandwidth and the split between the circuit and the
-expectation. `roofline` reports the kernel family that takes the most time in
-the timed steps, timed with HIP events recorded by the library on the stream
-the kernels run on. `cpu_baseline` times the CPU oracle on a bounded sample of
-the same circuit (the first gates of it, complex128).
+value = circuit gates per second over whole steps (expectation included).
+`roofline` reports the kernel family that takes the most time in the timed
+steps, timed with HIP events the library records on the stream its kernels run
+on, against the 8 TB/s HBM peak. `cpu_baseline` times the CPU oracle on a
+bounded sample of the same circuit (its first gates, complex128).
+
+Extra legs (same JSON line):
+  adjoint_24q   24 qubits, 20 layers RY/RZ + CNOT ring (960 parameters),
+                500-term observable: adjoint gradient vs central finite
+                differences on the same kernels (FD timed on a sample of
+                parameters; both reported as gradient components per second)
+  batch_vqe     512 hardware-efficient-ansatz items of 12..18 qubits: one
+                persistent launch vs one adjoint call per item
+  random_26q    26-qubit Haar-1q + random-CZ circuit, fused vs unfused
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode fused|unfused]
+                       [--quick] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -31,6 +40,7 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBPS = 8000.0
 METRIC = "gates/s + HBM GB/s at 30q; adjoint grads/s vs plain finite-diff, 24q c64"
+FAMILIES = ("pair", "scale", "diag", "dense", "expect", "tile", "apply_obs", "adjoint", "batch")
 
 
 def parse():
@@ -43,9 +53,25 @@ def parse():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--low", type=int, default=0)
     ap.add_argument("--n", type=int, default=30)
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--fd-params", type=int, default=6)
+    ap.add_argument("--batch-items", type=int, default=512)
     return ap.parse_args()
+
+
+def sync(Q, state):
+    state.norm2()  # a reduction that synchronises the state's stream
+
+
+def read_families(Q, steps):
+    fams = {}
+    for fam in FAMILIES:
+        cnt, ms, by = Q.prof_read(fam)
+        if cnt:
+            fams[fam] = {"launches": cnt, "ms": ms, "bytes": by}
+    return fams
 
 
 def cpu_baseline(n, gates, budget_s):
@@ -68,6 +94,116 @@ def cpu_baseline(n, gates, budget_s):
                       f"{dt:.1f} s"}
 
 
+def adjoint_leg(Q, W, fd_params):
+    n = 24
+    gates, npar = W.ry_rz_cnot_ring(n, 20)
+    theta = W.uniform_angles(npar, (4, 0))
+    obs_t = W.random_pauli_observable(n, 500, (1, 6), seed_key=(4, 1))
+    circ = Q.Circuit.from_records(n, gates)
+    obs = Q.Observable(n, obs_t)
+    out = {"workload": "24 qubits, 20 layers RY/RZ + CNOT ring (1440 gates, 960 parameters), "
+                       "500 random Pauli strings of weight 1..6", "params": npar}
+    for dt in ("c64", "c128"):
+        plan = Q.Plan(circ, dt, max_k=2)
+        psi, lam, s = Q.State(n, dt), Q.State(n, dt), Q.State(n, dt)
+        Q.adjoint_gradient(circ, theta, obs, psi, lam, plan)  # warm-up
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            e, g = Q.adjoint_gradient(circ, theta, obs, psi, lam, plan)
+        t_adj = (time.perf_counter() - t0) / reps
+
+        def energy(th):
+            s.set_basis(0)
+            Q.apply_fused(s, plan, th)
+            return Q.expectation(s, obs)
+
+        energy(theta)
+        h = 1e-6 if dt == "c128" else 4e-3
+        slots = list(range(0, npar, max(1, npar // fd_params)))[:fd_params]
+        t0 = time.perf_counter()
+        fd = []
+        for sl in slots:
+            tp, tm = theta.copy(), theta.copy()
+            tp[sl] += h
+            tm[sl] -= h
+            fd.append((energy(tp) - energy(tm)) / (2 * h))
+        t_fd = (time.perf_counter() - t0) / len(slots)  # seconds per gradient component
+        scale = sum(abs(c) for c, _ in obs_t)
+        out[dt] = {"adjoint_s": t_adj, "grads_per_s": npar / t_adj,
+                   "fd_grads_per_s": 1.0 / t_fd, "fd_sample_params": len(slots), "fd_h": h,
+                   "speedup_vs_fd": (npar / t_adj) * t_fd,
+                   "max_abs_adjoint_minus_fd_over_sum_abs_alpha":
+                       float(np.max(np.abs(g[slots] - np.array(fd))) / scale),
+                   "energy": e}
+    return out
+
+
+def batch_leg(Q, W, count):
+    items = W.batch_items(count, seed=3)
+    out = {"workload": f"{count} items, HEA 8 layers RY,RZ + CZ ladder, n uniform over "
+                       "{12,14,16,18}, H = sum Z_i Z_i+1 + 0.7 sum X_i",
+           "items": count, "params_total": int(sum(len(it["theta"]) for it in items))}
+    b = Q.Batch()
+    circs = []
+    for it in items:
+        c = Q.Circuit.from_records(it["n"], it["gates"])
+        o = Q.Observable(it["n"], it["obs"])
+        circs.append((c, o))
+        b.add(c, o, it["theta"])
+    for dt in ("c64", "c128"):
+        b.run(dt)  # builds device tables
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            e, g = b.run(dt)
+        t_b = (time.perf_counter() - t0) / reps
+        # plain per-circuit baseline: one adjoint call per item (per-gate launches), sampled
+        sample = list(range(0, count, max(1, count // 32)))
+        states = {}
+        t_pc = 0.0
+        for i in sample:
+            n = items[i]["n"]
+            if n not in states:
+                states[n] = (Q.State(n, dt), Q.State(n, dt))
+            psi, lam = states[n]
+            c, o = circs[i]
+            Q.adjoint_gradient(c, items[i]["theta"], o, psi, lam)
+            t0 = time.perf_counter()
+            e1, g1 = Q.adjoint_gradient(c, items[i]["theta"], o, psi, lam)
+            t_pc += time.perf_counter() - t0
+        per_item = t_pc / len(sample)
+        out[dt] = {"batch_s": t_b, "items_per_s": count / t_b,
+                   "grads_per_s": out["params_total"] / t_b,
+                   "per_circuit_items_per_s": 1.0 / per_item,
+                   "speedup_vs_per_circuit": (count / t_b) * per_item}
+    return out
+
+
+def random_leg(Q, W):
+    n = 26
+    gates = W.random_u_cz(n, 20, seed_key=(1,))
+    circ = Q.Circuit.from_records(n, gates)
+    out = {"workload": "26 qubits, 20 layers of Haar 1q on every qubit + CZ on a random "
+                       "perfect matching (780 gates)"}
+    for dt in ("c64", "c128"):
+        s = Q.State(n, dt)
+        plan = Q.Plan(circ, dt, max_k=2)
+        r = {}
+        for mode in ("unfused", "fused"):
+            f = (lambda: Q.apply_circuit(s, circ)) if mode == "unfused" else (lambda: Q.apply_fused(s, plan))
+            f()
+            sync(Q, s)
+            t0 = time.perf_counter()
+            f()
+            sync(Q, s)
+            t = time.perf_counter() - t0
+            r[mode] = {"s": t, "gates_per_s": len(gates) / t}
+        r["passes"] = plan.info()["passes"]
+        out[dt] = r
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -80,8 +216,6 @@ def main():
 
     n = args.n
     dt = "c64"
-    S = 8
-    N = 1 << n
     gates = W.layered_rx_rz_cnot(n, 10, seed_key=(2,))
     obs_terms = W.random_pauli_observable(n, 200, 4, seed_key=(2, 1))
     circ = Q.Circuit.from_records(n, gates)
@@ -108,34 +242,28 @@ def main():
 
     # split of one step (synchronised between the parts)
     state.set_basis(0)
-    state.norm2()
+    sync(Q, state)
     t0 = time.perf_counter()
     run_circuit()
-    state.norm2()  # forces completion of the circuit
+    sync(Q, state)
     t1 = time.perf_counter()
     Q.expectation(state, obs)
     t2 = time.perf_counter()
-    circuit_ms_incl_norm = (t1 - t0) * 1e3
-    expect_ms = (t2 - t1) * 1e3
 
     # timed region
     Q.prof_enable(True)
-    state.norm2()
-    t0 = time.perf_counter()
+    sync(Q, state)
+    t_start = time.perf_counter()
     energy = None
     for _ in range(args.steps):
         energy = step()
-    state.norm2()
-    t1 = time.perf_counter()
+    sync(Q, state)
+    t_end = time.perf_counter()
     Q.prof_enable(False)
-    total = t1 - t0
+    total = t_end - t_start
     ms_per_step = total * 1e3 / args.steps
 
-    fams = {}
-    for fam in ("pair", "scale", "diag", "dense", "expect", "tile"):
-        cnt, ms, by = Q.prof_read(fam)
-        if cnt:
-            fams[fam] = {"launches": cnt, "ms": ms, "bytes": by}
+    fams = read_families(Q, args.steps)
     dom = max(fams, key=lambda f: fams[f]["ms"])
     d = fams[dom]
     achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
@@ -161,8 +289,8 @@ def main():
                    "plan": plan.info() if plan is not None else None,
                    "observable_terms": nterms, "flip_mask_groups": ngroups},
         "hbm_gbps_step": step_bytes / (ms_per_step * 1e-3) / 1e9,
-        "circuit_ms": circuit_ms_incl_norm,
-        "expectation_ms": expect_ms,
+        "circuit_ms": (t1 - t0) * 1e3,
+        "expectation_ms": (t2 - t1) * 1e3,
         "energy": energy,
         "kernel_families": {f: {"launches": v["launches"] // args.steps,
                                 "ms_per_step": v["ms"] / args.steps,
@@ -174,6 +302,11 @@ def main():
                      "bytes_per_launch": d["bytes"] / d["launches"],
                      "avg_launch_ms": d["ms"] / d["launches"]},
     }
+    del state
+    if not args.quick:
+        out["adjoint_24q"] = adjoint_leg(Q, W, args.fd_params)
+        out["batch_vqe"] = batch_leg(Q, W, args.batch_items)
+        out["random_26q"] = random_leg(Q, W)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, gates, args.cpu_seconds)
     print(json.dumps(out), flush=True)
