@@ -186,6 +186,11 @@ int qsv_plan_fused(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qu
 
 /* Number of passes, fused blocks and original gates (any out pointer may be NULL). */
 int qsv_plan_info(const qsv_plan* p, int* passes, int* blocks, int* gates);
+
+/* Execution shape of a plan: register-resident segments summed over passes
+ * (0 when passes run LDS-resident), blocks applied through LDS inside
+ * register-resident passes, and the widest dense block. */
+int qsv_plan_stats(const qsv_plan* p, int* segments, int* lds_ops, int* kmax);
 int qsv_plan_free(qsv_plan* p);
 
 /* Apply a plan to a state of the plan's qubit count and dtype: block matrices

@@ -59,6 +59,7 @@ _SIGS = {
     "qsv_plan_fused": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.POINTER(_vp)]),
     "qsv_plan_info": (_c.c_int, [_vp, _ip, _ip, _ip]),
     "qsv_plan_free": (_c.c_int, [_vp]),
+    "qsv_plan_stats": (_c.c_int, [_vp, _ip, _ip, _ip]),
     "qsv_apply_fused": (_c.c_int, [_vp, _vp, _dp]),
     "qsv_apply_observable": (_c.c_int, [_vp, _vp, _vp]),
     "qsv_adjoint_gradient": (_c.c_int, [_vp, _vp, _dp, _vp, _vp, _vp, _dp, _dp]),
@@ -322,7 +323,10 @@ class Plan:
     def info(self):
         p, b, g = _c.c_int(), _c.c_int(), _c.c_int()
         check(lib().qsv_plan_info(self.h, _c.byref(p), _c.byref(b), _c.byref(g)))
-        return {"passes": p.value, "blocks": b.value, "gates": g.value}
+        s, lo, km = _c.c_int(), _c.c_int(), _c.c_int()
+        check(lib().qsv_plan_stats(self.h, _c.byref(s), _c.byref(lo), _c.byref(km)))
+        return {"passes": p.value, "blocks": b.value, "gates": g.value, "segments": s.value,
+                "lds_ops": lo.value, "kmax": km.value}
 
     def __del__(self):
         try:

@@ -6,6 +6,11 @@
 
 #include "qsv_internal.h"
 
+namespace qsv {
+struct ExpPlan;
+void free_exp_plan(ExpPlan* p);
+}  // namespace qsv
+
 struct qsv_observable {
   int n = 0;
   struct Term {
@@ -14,6 +19,26 @@ struct qsv_observable {
     int ny;
   };
   std::vector<Term> terms;
+  // tiled evaluation plans per dtype (built on first use, dropped on change)
+  qsv::ExpPlan* exp_plan[3] = {nullptr, nullptr, nullptr};
+
+  qsv_observable() = default;
+  qsv_observable(const qsv_observable& o) : n(o.n), terms(o.terms) {}
+  qsv_observable& operator=(const qsv_observable& o) {
+    if (this != &o) {
+      drop_plans();
+      n = o.n;
+      terms = o.terms;
+    }
+    return *this;
+  }
+  ~qsv_observable() { drop_plans(); }
+  void drop_plans() {
+    for (auto*& p : exp_plan) {
+      if (p) qsv::free_exp_plan(p);
+      p = nullptr;
+    }
+  }
 };
 
 namespace qsv {

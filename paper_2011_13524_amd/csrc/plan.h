@@ -23,6 +23,7 @@ struct TileOpDev {
   int lt[5];       // dense: local target positions; diag: local position or -1
   int gq[5];       // diag: global qubit of a non-local target, or -1
   int ins[10];     // dense: sorted local positions with zero bits (targets + local controls)
+  int xswap;       // 1: the one-qubit matrix is Pauli X (a pure exchange)
   uint32_t lcm, lcv;  // local control mask / values (local index space)
   uint64_t gcm, gcv;  // non-local control mask / values (global index space)
   uint32_t off[32];   // dense: local offset of the i-th element of B1
@@ -31,8 +32,35 @@ struct TileOpDev {
 struct TilePassDev {
   int L, b, nh, ng;
   int op_begin, op_count;
-  int hq[kTileMaxHigh];     // qubits of local bits b..L-1
-  int gpos[kTileMaxGlobal]; // non-local qubits, ascending
+  int seg_begin, seg_count;  // register-resident execution (seg_count > 0)
+  int hq[kTileMaxHigh];      // qubits of local bits b..L-1
+  int gpos[kTileMaxGlobal];  // non-local qubits, ascending
+};
+
+// Register-resident tiles: the 2^L tile is spread over 256 threads holding
+// 2^RB amplitudes each. A segment fixes which local bits index a thread's
+// registers (reg) and which index the thread (thr); ops of the segment whose
+// dense targets are register bits run without touching LDS.
+constexpr int kRegMaxBits = 6;
+constexpr int kRegThreadBits = 8;
+
+struct RegSegDev {
+  int reg[kRegMaxBits];      // local positions of register-index bits, ascending
+  int thr[kRegThreadBits];   // local positions of thread-index bits, ascending
+  int op_begin, op_count;
+};
+
+struct RegOpDev {
+  int kind;             // 0 dense one-qubit, 1 dense two-qubit, 2 diagonal (k <= 2), 3 via LDS,
+                        // 4 Pauli-X exchange on one register bit
+  int p1, p2;           // register bits of matrix index bits 0 and 1
+  int k;
+  int dsrc[2], dbit[2]; // diagonal targets: source 0 register bit, 1 thread bit, 2 global qubit
+  uint32_t ri_cm, ri_cv;  // controls on register bits (register-index space)
+  uint32_t ti_cm, ti_cv;  // controls on thread bits (thread-index space)
+  uint64_t gcm, gcv;      // controls on non-local qubits
+  int moff;
+  int lop;              // index of the equivalent TileOpDev (LDS execution)
 };
 
 // A fused block: gates (indices into the circuit) applied in order, acting on
@@ -41,6 +69,7 @@ struct Block {
   std::vector<int> gates;
   std::vector<int> qubits;  // all qubits the block touches
   bool diagonal = false;
+  bool xswap = false;  // single gate whose extracted matrix is Pauli X (CNOT, X)
   // structure used on the device (targets + controls after extraction)
   std::vector<int> targets;
   std::vector<int> controls, ctrl_vals;
@@ -64,9 +93,15 @@ struct qsv_plan {
   // host copies of the device tables (uploaded on first apply)
   std::vector<qsv::TilePassDev> h_pass;
   std::vector<qsv::TileOpDev> h_ops;
+  std::vector<qsv::RegSegDev> h_segs;
+  std::vector<qsv::RegOpDev> h_rops;
+  int reg_bits = 0;  // > 0: passes run register-resident
+  int kmax_dense = 1;  // widest dense op (selects the kernel instantiation)
   // device buffers
   qsv::TilePassDev* d_pass = nullptr;
   qsv::TileOpDev* d_ops = nullptr;
+  qsv::RegSegDev* d_segs = nullptr;
+  qsv::RegOpDev* d_rops = nullptr;
   void* d_pool = nullptr;
   size_t pool_cap = 0;  // complex elements
   // pinned staging for per-apply uploads

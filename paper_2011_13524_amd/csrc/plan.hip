@@ -30,65 +30,14 @@
 #include "dev_common.h"
 #include "plan.h"
 #include "prof.h"
+#include "tile_reg.h"
 
 namespace qsv {
 
-__device__ __forceinline__ uint32_t insert_zeros32(uint32_t i, const int* pos, int m) {
-  for (int j = 0; j < m; ++j) {
-    const uint32_t lo = i & ((1u << pos[j]) - 1);
-    i = ((i >> pos[j]) << (pos[j] + 1)) | lo;
-  }
-  return i;
-}
-
-template <typename R, int K>
-__device__ __forceinline__ void tile_dense(cx<R>* __restrict__ t, const TileOpDev& op,
-                                           const cx<R>* __restrict__ mat, int L) {
-  constexpr int D = 1 << K;
-  const int cnt = 1 << (L - op.m);
-  if constexpr (K == 1) {
-    const cx<R> m00 = mat[0], m01 = mat[1], m10 = mat[2], m11 = mat[3];
-    const uint32_t o1 = op.off[1];
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-      const uint32_t j0 = insert_zeros32(i, op.ins, op.m) | op.lcv;
-      const cx<R> a = t[j0], b = t[j0 + o1];
-      t[j0] = cfma(m00, a, m01 * b);
-      t[j0 + o1] = cfma(m10, a, m11 * b);
-    }
-  } else {
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-      const uint32_t j0 = insert_zeros32(i, op.ins, op.m) | op.lcv;
-      cx<R> v[D];
-#pragma unroll
-      for (int c = 0; c < D; ++c) v[c] = t[j0 + op.off[c]];
-#pragma unroll
-      for (int r = 0; r < D; ++r) {
-        cx<R> acc = {R(0), R(0)};
-#pragma unroll
-        for (int c = 0; c < D; ++c) acc = cfma(mat[r * D + c], v[c], acc);
-        t[j0 + op.off[r]] = acc;
-      }
-    }
-  }
-}
-
-template <typename R>
-__device__ __forceinline__ void tile_diag(cx<R>* __restrict__ t, const TileOpDev& op,
-                                          const cx<R>* __restrict__ d, int L, uint64_t base) {
-  int gidx = 0;
-  for (int b = 0; b < op.k; ++b)
-    if (op.gq[b] >= 0) gidx |= int((base >> op.gq[b]) & 1) << b;
-  const int TS = 1 << L;
-  for (int j = threadIdx.x; j < TS; j += blockDim.x) {
-    if ((uint32_t(j) & op.lcm) != op.lcv) continue;
-    int idx = gidx;
-    for (int b = 0; b < op.k; ++b)
-      if (op.lt[b] >= 0) idx |= ((j >> op.lt[b]) & 1) << b;
-    t[j] = d[idx] * t[j];
-  }
-}
-
-template <typename R>
+// LDS-resident tile pass: the whole tile in LDS, every block an LDS sweep.
+// Used when the tile does not match the register-resident shape (small
+// states, non-default tile sizes).
+template <typename R, int KMAX>
 __global__ void __launch_bounds__(256)
     k_tile(R* __restrict__ psi, const TilePassDev* __restrict__ passes, int pass_idx,
            const TileOpDev* __restrict__ ops, const cx<R>* __restrict__ pool) {
@@ -113,18 +62,7 @@ __global__ void __launch_bounds__(256)
   for (int o = 0; o < P.op_count; ++o) {
     const TileOpDev& op = ops[P.op_begin + o];
     if ((base & op.gcm) != op.gcv) continue;  // non-local controls not met: skip for this tile
-    const cx<R>* mat = pool + op.moff;
-    if (op.kind == 1) {
-      tile_diag<R>(t, op, mat, L, base);
-    } else {
-      switch (op.k) {
-        case 1: tile_dense<R, 1>(t, op, mat, L); break;
-        case 2: tile_dense<R, 2>(t, op, mat, L); break;
-        case 3: tile_dense<R, 3>(t, op, mat, L); break;
-        case 4: tile_dense<R, 4>(t, op, mat, L); break;
-        default: tile_dense<R, 5>(t, op, mat, L); break;
-      }
-    }
+    lds_op<R, KMAX>(t, op, pool, L, base, NoSwz());
     __syncthreads();
   }
   for (int e = threadIdx.x; e < TS / V; e += blockDim.x) {
@@ -277,7 +215,7 @@ static int build_plan(qsv_plan* p) {
       const uint64_t uni = bq[cand] | I.qubits;
       const int ku = __builtin_popcountll(uni);
       bool ok = false;
-      if (B.diagonal && I.diagonal) ok = ku <= 5;
+      if (B.diagonal && I.diagonal) ok = ku <= 2;  // diagonal blocks stay register-friendly
       else if (!B.diagonal && I.diagonal) ok = (I.qubits & ~bq[cand]) == 0;
       else if (B.diagonal && !I.diagonal) ok = (bq[cand] & ~I.qubits) == 0 && ku <= std::max(p->max_k, 1);
       else ok = ku <= p->max_k;
@@ -306,6 +244,10 @@ static int build_plan(qsv_plan* p) {
       B.targets = I.targets;
       B.controls = I.controls;
       B.ctrl_vals = I.ctrl_vals;
+      const Gate& g0 = C.gates[B.gates[0]];
+      B.xswap = g0.kind == Gate::MATRIX && I.targets.size() == 1 && I.mat.size() == 4 &&
+                I.mat[0].re == 0 && I.mat[0].im == 0 && I.mat[1].re == 1 && I.mat[1].im == 0 &&
+                I.mat[2].re == 1 && I.mat[2].im == 0 && I.mat[3].re == 0 && I.mat[3].im == 0;
     } else {
       B.targets = B.qubits;
       B.controls.clear();
@@ -353,6 +295,130 @@ static int build_plan(qsv_plan* p) {
   return QSV_OK;
 }
 
+// Split a pass's ops into register-resident segments. A segment gathers
+// consecutive ops while the union of their dense targets (one- and two-qubit
+// dense ops; other ops run through LDS) fits in reg_bits register bits; the
+// first and last segments of a complex64 pass also keep local bit 0 in
+// registers so HBM traffic uses 16-byte vectors. Remaining register bits are
+// filled with the highest free local bits, leaving the low local bits to the
+// lanes (contiguous HBM runs, conflict-free LDS rows).
+static int build_segments(qsv_plan* p, const std::vector<TileOpDev>& ho, TilePassDev& d) {
+  const int RB = p->reg_bits, L = d.L;
+  const bool c64 = p->dtype == QSV_C64;
+  struct Seg {
+    uint32_t regs = 0;
+    bool fixed = false;  // layout already complete (the HBM layout)
+    std::vector<int> ops;
+  };
+  // HBM layout: the highest local bits (and bit 0 for complex64, whose pairs
+  // form 16-byte vectors) in registers, the low bits on lanes, so every load /
+  // store instruction of a wavefront covers one contiguous span.
+  uint32_t io = c64 ? 1u : 0u;
+  for (int pos = L - 1; pos >= 0 && __builtin_popcount(io) < RB; --pos) io |= 1u << pos;
+  std::vector<Seg> segs(1);
+  segs[0].regs = io;
+  segs[0].fixed = true;
+  for (int oi = d.op_begin; oi < d.op_begin + d.op_count; ++oi) {
+    const TileOpDev& o = ho[oi];
+    uint32_t need = 0;
+    if (o.kind == 0 && o.k <= 2)
+      for (int j = 0; j < o.k; ++j) need |= 1u << o.lt[j];
+    Seg& cur = segs.back();
+    const bool fits = cur.fixed ? (need & ~cur.regs) == 0 : __builtin_popcount(cur.regs | need) <= RB;
+    if (fits) {
+      cur.regs |= need;
+      cur.ops.push_back(oi);
+    } else {
+      Seg s;
+      s.regs = need;
+      s.ops.push_back(oi);
+      segs.push_back(s);
+    }
+  }
+  // the last segment must store in the HBM layout: extend it to that layout
+  // when its register bits allow, else add an empty re-mapping segment
+  Seg& last = segs.back();
+  if (!last.fixed) {
+    if ((last.regs & ~io) == 0) {
+      last.regs = io;
+      last.fixed = true;
+    } else {
+      Seg s;
+      s.regs = io;
+      s.fixed = true;
+      segs.push_back(s);
+    }
+  }
+  for (Seg& s : segs) {
+    RegSegDev sd{};
+    for (int pos = L - 1; pos >= 0 && __builtin_popcount(s.regs) < RB; --pos) s.regs |= 1u << pos;
+    int nr = 0, nt = 0;
+    int regidx[32], thridx[32];
+    for (int pos = 0; pos < L; ++pos) {
+      if (s.regs >> pos & 1) {
+        regidx[pos] = nr;
+        sd.reg[nr++] = pos;
+        thridx[pos] = -1;
+      } else {
+        thridx[pos] = nt;
+        sd.thr[nt++] = pos;
+        regidx[pos] = -1;
+      }
+    }
+    if (nr != RB || nt != kRegThreadBits) return fail(QSV_EINVAL, "internal: bad segment layout");
+    sd.op_begin = int(p->h_rops.size());
+    sd.op_count = int(s.ops.size());
+    for (int oi : s.ops) {
+      const TileOpDev& o = ho[oi];
+      RegOpDev r{};
+      r.lop = oi;
+      r.moff = o.moff;
+      r.k = o.k;
+      r.gcm = o.gcm;
+      r.gcv = o.gcv;
+      for (int pos = 0; pos < L; ++pos) {
+        if (!(o.lcm >> pos & 1)) continue;
+        const uint32_t val = (o.lcv >> pos) & 1;
+        if (regidx[pos] >= 0) {
+          r.ri_cm |= 1u << regidx[pos];
+          r.ri_cv |= val << regidx[pos];
+        } else {
+          r.ti_cm |= 1u << thridx[pos];
+          r.ti_cv |= val << thridx[pos];
+        }
+      }
+      if (o.kind == 0 && o.k <= 2) {
+        r.kind = o.k == 1 ? (o.xswap ? 4 : 0) : 1;
+        r.p1 = regidx[o.lt[0]];
+        r.p2 = o.k == 2 ? regidx[o.lt[1]] : 0;
+        if (r.p1 < 0 || (o.k == 2 && r.p2 < 0)) return fail(QSV_EINVAL, "internal: target not in registers");
+      } else if (o.kind == 1 && o.k <= 2) {
+        r.kind = 2;
+        for (int j = 0; j < o.k; ++j) {
+          if (o.lt[j] >= 0) {
+            if (regidx[o.lt[j]] >= 0) {
+              r.dsrc[j] = 0;
+              r.dbit[j] = regidx[o.lt[j]];
+            } else {
+              r.dsrc[j] = 1;
+              r.dbit[j] = thridx[o.lt[j]];
+            }
+          } else {
+            r.dsrc[j] = 2;
+            r.dbit[j] = o.gq[j];
+          }
+        }
+      } else {
+        r.kind = 3;
+      }
+      p->h_rops.push_back(r);
+    }
+    p->h_segs.push_back(sd);
+    d.seg_count++;
+  }
+  return QSV_OK;
+}
+
 // Device tables for the passes and ops (matrix offsets fixed here; matrix
 // values are uploaded at apply time).
 static int upload_tables(qsv_plan* p, std::vector<int>& moffs, size_t& pool_elems) {
@@ -386,6 +452,7 @@ static int upload_tables(qsv_plan* p, std::vector<int>& moffs, size_t& pool_elem
       const Block& B = p->blocks[bi];
       TileOpDev o{};
       o.kind = B.diagonal ? 1 : 0;
+      o.xswap = B.xswap ? 1 : 0;
       o.k = int(B.targets.size());
       o.moff = moffs[bi];
       for (size_t j = 0; j < B.controls.size(); ++j) {
@@ -424,7 +491,14 @@ static int upload_tables(qsv_plan* p, std::vector<int>& moffs, size_t& pool_elem
           o.off[i] = off;
         }
       }
+      if (o.kind == 0) p->kmax_dense = std::max(p->kmax_dense, o.k);
       ho.push_back(o);
+    }
+    d.seg_begin = int(p->h_segs.size());
+    d.seg_count = 0;
+    if (p->reg_bits > 0 && d.L == p->reg_bits + kRegThreadBits) {
+      int rc = build_segments(p, ho, d);
+      if (rc) return rc;
     }
     hp.push_back(d);
   }
@@ -445,10 +519,21 @@ static int ensure_tables(qsv_plan* p, hipStream_t stream) {
     p->d_pass = nullptr;
     return fail(QSV_ENOMEM, "plan table allocation failed");
   }
+  if (hipMalloc(reinterpret_cast<void**>(&p->d_segs),
+                std::max<size_t>(1, p->h_segs.size()) * sizeof(RegSegDev)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&p->d_rops),
+                std::max<size_t>(1, p->h_rops.size()) * sizeof(RegOpDev)) != hipSuccess)
+    return fail(QSV_ENOMEM, "plan table allocation failed");
   QSV_HIP_CHECK(hipMemcpyAsync(p->d_pass, p->h_pass.data(), p->h_pass.size() * sizeof(TilePassDev),
                                hipMemcpyHostToDevice, stream));
   if (!p->h_ops.empty())
     QSV_HIP_CHECK(hipMemcpyAsync(p->d_ops, p->h_ops.data(), p->h_ops.size() * sizeof(TileOpDev),
+                                 hipMemcpyHostToDevice, stream));
+  if (!p->h_segs.empty())
+    QSV_HIP_CHECK(hipMemcpyAsync(p->d_segs, p->h_segs.data(), p->h_segs.size() * sizeof(RegSegDev),
+                                 hipMemcpyHostToDevice, stream));
+  if (!p->h_rops.empty())
+    QSV_HIP_CHECK(hipMemcpyAsync(p->d_rops, p->h_rops.data(), p->h_rops.size() * sizeof(RegOpDev),
                                  hipMemcpyHostToDevice, stream));
   QSV_HIP_CHECK(hipStreamSynchronize(stream));
   return QSV_OK;
@@ -529,14 +614,42 @@ static int apply_fused_t(qsv_state* s, qsv_plan* p, const double* theta) {
   for (size_t pi = 0; pi < p->passes.size(); ++pi) {
     const int L = int(p->passes[pi].local.size());
     const uint64_t tiles = dim(n - L);
-    const size_t lds = (size_t(1) << L) * sizeof(cx<R>);
-    if (lds > 65536)
-      QSV_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tile<R>),
+    size_t lds = (size_t(1) << L) * sizeof(cx<R>);
+    const TilePassDev& hp = p->h_pass[pi];
+    if (hp.seg_count == 1) {
+      // a single register-resident segment never touches LDS unless one of
+      // its blocks runs through LDS: launch without it (higher occupancy)
+      const RegSegDev& sg = p->h_segs[hp.seg_begin];
+      bool needs = false;
+      for (int o = sg.op_begin; o < sg.op_begin + sg.op_count; ++o) needs |= p->h_rops[o].kind == 3;
+      if (!needs) lds = 0;
+    }
+    if (lds > 65536) {
+      QSV_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tile<R, 2>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+      QSV_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tile<R, 3>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+      QSV_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tile<R, 5>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    }
     ProfScope ps("tile", 2.0 * sizeof(cx<R>) * double(dim(n)), s->stream);
-    hipLaunchKernelGGL((k_tile<R>), dim3(unsigned(tiles)), dim3(256), lds, s->stream,
-                       static_cast<R*>(s->ptr), p->d_pass, int(pi), p->d_ops,
-                       static_cast<const cx<R>*>(p->d_pool));
+    constexpr int RB = sizeof(R) == 4 ? 5 : 4;
+    R* psi = static_cast<R*>(s->ptr);
+    const cx<R>* pool = static_cast<const cx<R>*>(p->d_pool);
+    const dim3 grid(static_cast<unsigned>(tiles)), block(256);
+#define QSV_TILE_LAUNCH(KM)                                                                    \
+  do {                                                                                         \
+    if (p->h_pass[pi].seg_count > 0)                                                           \
+      hipLaunchKernelGGL((k_tile_reg<R, RB, KM>), grid, block, lds, s->stream, psi, p->d_pass, \
+                         int(pi), p->d_segs, p->d_rops, p->d_ops, pool);                       \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_tile<R, KM>), grid, block, lds, s->stream, psi, p->d_pass, int(pi), \
+                         p->d_ops, pool);                                                      \
+  } while (0)
+    if (p->kmax_dense <= 2) QSV_TILE_LAUNCH(2);
+    else if (p->kmax_dense <= 3) QSV_TILE_LAUNCH(3);
+    else QSV_TILE_LAUNCH(5);
+#undef QSV_TILE_LAUNCH
     QSV_HIP_CHECK(hipGetLastError());
   }
   QSV_HIP_CHECK(hipEventRecord(p->stage_ev, s->stream));
@@ -574,6 +687,10 @@ int qsv_plan_fused(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qu
   p->max_k = max_k;
   p->L = L;
   p->b = b;
+  // register-resident passes when the tile is 256 threads x 2^RB amplitudes
+  // (RB = 5 for complex64, 4 for complex128: 64 KiB of LDS for re-mapping)
+  const int RB = dtype == QSV_C64 ? 5 : 4;
+  p->reg_bits = (L == RB + kRegThreadBits && n >= L) ? RB : 0;
   p->circ_copy = *c;
   int rc = build_plan(p);
   std::vector<int> moffs;
@@ -598,6 +715,18 @@ int qsv_plan_info(const qsv_plan* p, int* passes, int* blocks, int* gates) {
   return QSV_OK;
 }
 
+int qsv_plan_stats(const qsv_plan* p, int* segments, int* lds_ops, int* kmax) {
+  clear_error();
+  if (!p) return fail(QSV_EINVAL, "null plan");
+  int lo = 0;
+  for (const RegOpDev& r : p->h_rops)
+    if (r.kind == 3) ++lo;
+  if (segments) *segments = int(p->h_segs.size());
+  if (lds_ops) *lds_ops = lo;
+  if (kmax) *kmax = p->kmax_dense;
+  return QSV_OK;
+}
+
 int qsv_plan_free(qsv_plan* p) {
   clear_error();
   if (!p) return QSV_OK;
@@ -607,6 +736,8 @@ int qsv_plan_free(qsv_plan* p) {
   if (p->d_pool) (void)hipFree(p->d_pool);
   if (p->d_pass) (void)hipFree(p->d_pass);
   if (p->d_ops) (void)hipFree(p->d_ops);
+  if (p->d_segs) (void)hipFree(p->d_segs);
+  if (p->d_rops) (void)hipFree(p->d_rops);
   delete p;
   return QSV_OK;
 }

@@ -26,6 +26,8 @@
 
 namespace qsv {
 
+int expectation_tiled(qsv_state* s, const qsv_observable* o, double* out);
+
 constexpr int kRedThreads = 256;
 constexpr int kMaxRedBlocks = 2048;
 constexpr int kLdsTerms = 512;
@@ -292,6 +294,7 @@ int qsv_observable_add_term(qsv_observable* o, double coef, const int* qubits, c
     if (p == 2 || p == 3) t.zmask |= b;
     if (p == 2) t.ny++;
   }
+  o->drop_plans();
   o->terms.push_back(t);
   return QSV_OK;
 }
@@ -317,7 +320,7 @@ int qsv_expectation(const qsv_state* s_in, const qsv_observable* o, double* out)
   if (!o) return fail(QSV_EINVAL, "null observable");
   if (!out) return fail(QSV_EINVAL, "null output");
   if (o->n != s_in->n) return fail(QSV_ERANGE, "observable has %d qubits, state %d", o->n, s_in->n);
-  return expectation_impl(const_cast<qsv_state*>(s_in), o, out);
+  return expectation_tiled(const_cast<qsv_state*>(s_in), o, out);
 }
 
 }  // extern "C"

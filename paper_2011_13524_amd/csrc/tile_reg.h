@@ -1,0 +1,387 @@
+// Register-resident tile pass (device code, included by plan.hip).
+//
+// The 2^L amplitudes of a tile are spread over 256 threads, 2^RB per thread in
+// VGPRs (RB = L - 8). A segment's layout says which local bits index a
+// thread's registers (reg[0..RB-1]) and which index the thread (thr[0..7]).
+// Ops of a segment act on register bits: a one- or two-qubit dense block is a
+// fully unrolled loop over register pairs / quads with the matrix in scalar
+// registers; diagonal blocks and controls may sit on register bits, thread
+// bits or non-local qubits. Between segments the tile is re-mapped through LDS
+// (write in the old layout, barrier, read in the new one). LDS addresses are
+// XOR-swizzled so that lanes whose local indices differ only in high bits do
+// not collide on a bank. The first and last segments keep local bit 0 in
+// registers (complex64), so HBM is read and written with 16-byte vectors and
+// the low local bits index consecutive lanes (contiguous runs).
+#pragma once
+
+#include "dev_common.h"
+#include "plan.h"
+
+namespace qsv {
+
+// LDS index swizzle: XOR the low SB bits with two higher SB-bit fields.
+template <int SB>
+struct Swz {
+  __device__ __forceinline__ uint32_t operator()(uint32_t j) const {
+    constexpr uint32_t m = (1u << SB) - 1;
+    return j ^ ((j >> SB) & m) ^ ((j >> (2 * SB)) & m);
+  }
+};
+
+struct NoSwz {
+  __device__ __forceinline__ uint32_t operator()(uint32_t j) const { return j; }
+};
+
+__device__ __forceinline__ uint32_t insert_zeros32(uint32_t i, const int* pos, int m) {
+  for (int j = 0; j < m; ++j) {
+    const uint32_t lo = i & ((1u << pos[j]) - 1);
+    i = ((i >> pos[j]) << (pos[j] + 1)) | lo;
+  }
+  return i;
+}
+
+// Dense block on local targets, whole tile in LDS (addresses through sw).
+template <typename R, int K, typename SW>
+__device__ __forceinline__ void lds_dense(cx<R>* __restrict__ t, const TileOpDev& op,
+                                          const cx<R>* __restrict__ mat, int L, SW sw) {
+  constexpr int D = 1 << K;
+  const int cnt = 1 << (L - op.m);
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const uint32_t j0 = insert_zeros32(i, op.ins, op.m) | op.lcv;
+    cx<R> v[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) v[c] = t[sw(j0 + op.off[c])];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      cx<R> acc = {R(0), R(0)};
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc = cfma(mat[r * D + c], v[c], acc);
+      t[sw(j0 + op.off[r])] = acc;
+    }
+  }
+}
+
+template <typename R, typename SW>
+__device__ __forceinline__ void lds_diag(cx<R>* __restrict__ t, const TileOpDev& op,
+                                         const cx<R>* __restrict__ d, int L, uint64_t base, SW sw) {
+  int gidx = 0;
+  for (int b = 0; b < op.k; ++b)
+    if (op.gq[b] >= 0) gidx |= int((base >> op.gq[b]) & 1) << b;
+  const int TS = 1 << L;
+  for (int j = threadIdx.x; j < TS; j += blockDim.x) {
+    if ((uint32_t(j) & op.lcm) != op.lcv) continue;
+    int idx = gidx;
+    for (int b = 0; b < op.k; ++b)
+      if (op.lt[b] >= 0) idx |= ((j >> op.lt[b]) & 1) << b;
+    const uint32_t a = sw(uint32_t(j));
+    t[a] = d[idx] * t[a];
+  }
+}
+
+// KMAX bounds the widest dense block compiled in: a kernel instantiated for
+// small blocks does not pay the register cost of 32-amplitude temporaries.
+template <typename R, int KMAX, typename SW>
+__device__ __forceinline__ void lds_op(cx<R>* t, const TileOpDev& op, const cx<R>* pool, int L,
+                                       uint64_t base, SW sw) {
+  const cx<R>* mat = pool + op.moff;
+  if (op.kind == 1) {
+    lds_diag<R>(t, op, mat, L, base, sw);
+  } else {
+    switch (op.k) {
+      case 1: lds_dense<R, 1>(t, op, mat, L, sw); break;
+      case 2: if constexpr (KMAX >= 2) lds_dense<R, 2>(t, op, mat, L, sw); break;
+      case 3: if constexpr (KMAX >= 3) lds_dense<R, 3>(t, op, mat, L, sw); break;
+      case 4: if constexpr (KMAX >= 4) lds_dense<R, 4>(t, op, mat, L, sw); break;
+      default: if constexpr (KMAX >= 5) lds_dense<R, 5>(t, op, mat, L, sw); break;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ register ops
+//
+// Register element indices are compile-time constants in every loop below
+// (loops run over the compressed index g and insert the target bits), so the
+// per-thread amplitude array stays in VGPRs.
+
+template <int P>
+__device__ __forceinline__ constexpr int ins1(int g) {
+  return ((g >> P) << (P + 1)) | (g & ((1 << P) - 1));
+}
+
+template <int A, int B>
+__device__ __forceinline__ constexpr int ins2(int g) {
+  constexpr int lo = A < B ? A : B, hi = A < B ? B : A;
+  return ins1<hi>(ins1<lo>(g));
+}
+
+// Each variant writes EVERY element of `o` (updated or copied), so that after
+// a runtime switch over variants each register slot has one definition per
+// path: the compiler then keeps the array in VGPRs instead of merging
+// per-variant stores to different slots through memory.
+template <typename R, int NR, int P, bool HASC>
+__device__ __forceinline__ void reg_dense1(const cx<R>* v, cx<R>* o, const cx<R>* __restrict__ m,
+                                           uint32_t cm, uint32_t cv) {
+  const cx<R> m00 = m[0], m01 = m[1], m10 = m[2], m11 = m[3];
+#pragma unroll
+  for (int g = 0; g < NR / 2; ++g) {
+    const int i = ins1<P>(g), j = i | (1 << P);
+    const cx<R> a = v[i], b = v[j];
+    const bool on = !HASC || (uint32_t(i) & cm) == cv;
+    const cx<R> na = cfma(m00, a, m01 * b), nb = cfma(m10, a, m11 * b);
+    o[i] = on ? na : a;
+    o[j] = on ? nb : b;
+  }
+}
+
+// Pauli-X exchange (X, CNOT on register bits): moves only.
+template <typename R, int NR, int P, bool HASC>
+__device__ __forceinline__ void reg_swap1(const cx<R>* v, cx<R>* o, const cx<R>* __restrict__,
+                                          uint32_t cm, uint32_t cv) {
+#pragma unroll
+  for (int g = 0; g < NR / 2; ++g) {
+    const int i = ins1<P>(g), j = i | (1 << P);
+    const bool on = !HASC || (uint32_t(i) & cm) == cv;
+    o[i] = on ? v[j] : v[i];
+    o[j] = on ? v[i] : v[j];
+  }
+}
+
+// Matrix index bit 0 <-> register bit A, bit 1 <-> register bit B.
+template <typename R, int NR, int A, int B, bool HASC>
+__device__ __forceinline__ void reg_dense2(const cx<R>* v, cx<R>* o, const cx<R>* __restrict__ m,
+                                           uint32_t cm, uint32_t cv) {
+  const cx<R> k0 = m[0], k1 = m[1], k2 = m[2], k3 = m[3], k4 = m[4], k5 = m[5], k6 = m[6],
+              k7 = m[7], k8 = m[8], k9 = m[9], k10 = m[10], k11 = m[11], k12 = m[12],
+              k13 = m[13], k14 = m[14], k15 = m[15];
+#pragma unroll
+  for (int g = 0; g < NR / 4; ++g) {
+    const int i0 = ins2<A, B>(g);
+    const int i1 = i0 | (1 << A), i2 = i0 | (1 << B), i3 = i0 | (1 << A) | (1 << B);
+    const bool on = !HASC || (uint32_t(i0) & cm) == cv;
+    const cx<R> x0 = v[i0], x1 = v[i1], x2 = v[i2], x3 = v[i3];
+    const cx<R> y0 = cfma(k3, x3, cfma(k2, x2, cfma(k1, x1, k0 * x0)));
+    const cx<R> y1 = cfma(k7, x3, cfma(k6, x2, cfma(k5, x1, k4 * x0)));
+    const cx<R> y2 = cfma(k11, x3, cfma(k10, x2, cfma(k9, x1, k8 * x0)));
+    const cx<R> y3 = cfma(k15, x3, cfma(k14, x2, cfma(k13, x1, k12 * x0)));
+    o[i0] = on ? y0 : x0;
+    o[i1] = on ? y1 : x1;
+    o[i2] = on ? y2 : x2;
+    o[i3] = on ? y3 : x3;
+  }
+}
+
+// One flat switch over (op type, control presence, register bits): every case
+// writes every element of a fresh array, and a single copy follows. Keeping
+// the variants in one switch (rather than nested dispatchers) lets the
+// compiler keep the amplitude array in VGPRs.
+#define QSV_C1(SW, HC, P)                                                        \
+  case ((SW) * 2 + (HC)) * 8 + (P):                                              \
+    if constexpr (SW) reg_swap1<R, NR, P, HC>(v, o, m, cm, cv);                  \
+    else reg_dense1<R, NR, P, HC>(v, o, m, cm, cv);                              \
+    break;
+#define QSV_C1P(SW, HC) QSV_C1(SW, HC, 0) QSV_C1(SW, HC, 1) QSV_C1(SW, HC, 2) QSV_C1(SW, HC, 3)
+#define QSV_C2(HC, A, B)                                                         \
+  case 32 + (HC) * 64 + (A) * 8 + (B):                                           \
+    reg_dense2<R, NR, A, B, HC>(v, o, m, cm, cv);                                \
+    break;
+#define QSV_C2P4(HC)                                                             \
+  QSV_C2(HC, 0, 1) QSV_C2(HC, 0, 2) QSV_C2(HC, 0, 3) QSV_C2(HC, 1, 0) QSV_C2(HC, 1, 2) \
+  QSV_C2(HC, 1, 3) QSV_C2(HC, 2, 0) QSV_C2(HC, 2, 1) QSV_C2(HC, 2, 3) QSV_C2(HC, 3, 0) \
+  QSV_C2(HC, 3, 1) QSV_C2(HC, 3, 2)
+#define QSV_C2P5(HC)                                                             \
+  QSV_C2(HC, 0, 4) QSV_C2(HC, 1, 4) QSV_C2(HC, 2, 4) QSV_C2(HC, 3, 4) QSV_C2(HC, 4, 0) \
+  QSV_C2(HC, 4, 1) QSV_C2(HC, 4, 2) QSV_C2(HC, 4, 3)
+
+// kind 0 dense one-qubit, 1 dense two-qubit, 4 Pauli-X exchange.
+template <typename R, int NR>
+__device__ __forceinline__ void reg_apply(cx<R>* v, int kind, int a, int b, const cx<R>* m,
+                                          uint32_t cm, uint32_t cv) {
+  const int hc = cm != 0;
+  const int key = kind == 1 ? 32 + hc * 64 + a * 8 + b : ((kind == 4) * 2 + hc) * 8 + a;
+  cx<R> o[NR];
+  switch (key) {
+    QSV_C1P(0, 0) QSV_C1P(0, 1) QSV_C1P(1, 0) QSV_C1P(1, 1)
+    QSV_C2P4(0) QSV_C2P4(1)
+    default:
+      if constexpr (NR > 16) {
+        switch (key) {
+          QSV_C1(0, 0, 4) QSV_C1(0, 1, 4) QSV_C1(1, 0, 4) QSV_C1(1, 1, 4)
+          QSV_C2P5(0) QSV_C2P5(1)
+          default:
+#pragma unroll
+            for (int i = 0; i < NR; ++i) o[i] = v[i];
+            break;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) o[i] = v[i];
+      }
+      break;
+  }
+#pragma unroll
+  for (int i = 0; i < NR; ++i) v[i] = o[i];
+}
+#undef QSV_C1
+#undef QSV_C1P
+#undef QSV_C2
+#undef QSV_C2P4
+#undef QSV_C2P5
+
+// Diagonal block (k <= 2): amplitude factor d[idx], idx bit j from target j.
+// The factor of register element i is selected from (at most) four values with
+// a runtime bit test, never by indexing the register array.
+template <typename R, int NR>
+__device__ __forceinline__ void reg_diag(cx<R>* v, const RegOpDev& op, const cx<R>* __restrict__ d,
+                                         uint32_t tau, uint64_t base) {
+  int fixed = 0;  // index bits from thread and non-local targets
+  int rb0 = 31, rb1 = 31;  // register bits of targets 0 and 1 (31: not a register bit)
+  for (int j = 0; j < op.k; ++j) {
+    if (op.dsrc[j] == 1) fixed |= int((tau >> op.dbit[j]) & 1) << j;
+    else if (op.dsrc[j] == 2) fixed |= int((base >> op.dbit[j]) & 1) << j;
+    else if (j == 0) rb0 = op.dbit[j];
+    else rb1 = op.dbit[j];
+  }
+  const int nd = 1 << op.k;
+  cx<R> dv[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) dv[e] = d[e < nd ? (e | fixed) : 0];
+  const uint32_t cm = op.ri_cm, cv = op.ri_cv;
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int b0 = (i >> rb0) & 1, b1 = (i >> rb1) & 1;
+    const cx<R> lo = b0 ? dv[1] : dv[0], hi = b0 ? dv[3] : dv[2];
+    const cx<R> f = b1 ? hi : lo;
+    const cx<R> r = f * v[i];
+    if ((uint32_t(i) & cm) == cv) v[i] = r;
+  }
+}
+
+// Local index of register element i / of this thread under a segment layout.
+template <int RB>
+__device__ __forceinline__ uint32_t lreg(const RegSegDev& s, int i) {
+  uint32_t j = 0;
+#pragma unroll
+  for (int b = 0; b < RB; ++b)
+    if ((i >> b) & 1) j |= 1u << s.reg[b];
+  return j;
+}
+
+__device__ __forceinline__ uint32_t lthr(const RegSegDev& s, uint32_t tau) {
+  uint32_t j = 0;
+#pragma unroll
+  for (int b = 0; b < kRegThreadBits; ++b) j |= ((tau >> b) & 1) << s.thr[b];
+  return j;
+}
+
+template <typename R, int RB, int KMAX>
+__global__ void __launch_bounds__(256)
+    k_tile_reg(R* __restrict__ psi, const TilePassDev* __restrict__ passes, int pass_idx,
+               const RegSegDev* __restrict__ segs, const RegOpDev* __restrict__ rops,
+               const TileOpDev* __restrict__ lops, const cx<R>* __restrict__ pool) {
+  constexpr int NR = 1 << RB;
+  constexpr int SB = sizeof(R) == 4 ? 5 : 4;
+  const Swz<SB> sw;
+  extern __shared__ __align__(16) char smem[];
+  cx<R>* t = reinterpret_cast<cx<R>*>(smem);
+  const TilePassDev& P = passes[pass_idx];
+  const int L = P.L, b = P.b;
+  const uint64_t g = blockIdx.x;
+  uint64_t base = 0;
+  for (int j = 0; j < P.ng; ++j) base |= ((g >> j) & 1) << P.gpos[j];
+  const uint32_t tau = threadIdx.x;
+  auto gbit = [&](int p) -> uint64_t { return uint64_t(1) << (p < b ? p : P.hq[p - b]); };
+
+  cx<R> v[NR];
+  // HBM -> registers in the first segment's layout
+  const RegSegDev* S = &segs[P.seg_begin];
+  uint64_t gthr = base;
+  for (int k = 0; k < kRegThreadBits; ++k)
+    if ((tau >> k) & 1) gthr |= gbit(S->thr[k]);
+  uint64_t greg[RB];
+#pragma unroll
+  for (int k = 0; k < RB; ++k) greg[k] = gbit(S->reg[k]);
+  const bool vec = sizeof(R) == 4 && S->reg[0] == 0;
+  if (vec) {
+#pragma unroll
+    for (int i = 0; i < NR; i += 2) {
+      uint64_t x = gthr;
+#pragma unroll
+      for (int k = 1; k < RB; ++k)
+        if ((i >> k) & 1) x |= greg[k];
+      AmpIO<R, 2>::load(psi, x, &v[i]);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      uint64_t x = gthr;
+#pragma unroll
+      for (int k = 0; k < RB; ++k)
+        if ((i >> k) & 1) x |= greg[k];
+      AmpIO<R, 1>::load(psi, x, &v[i]);
+    }
+  }
+
+  for (int sgi = 0; sgi < P.seg_count; ++sgi) {
+    const RegSegDev* Sn = &segs[P.seg_begin + sgi];
+    if (sgi > 0) {
+      // re-map through LDS
+      const uint32_t to = lthr(*S, tau);
+#pragma unroll
+      for (int i = 0; i < NR; ++i) t[sw(lreg<RB>(*S, i) | to)] = v[i];
+      __syncthreads();
+      const uint32_t tn = lthr(*Sn, tau);
+#pragma unroll
+      for (int i = 0; i < NR; ++i) v[i] = t[sw(lreg<RB>(*Sn, i) | tn)];
+      __syncthreads();
+    }
+    S = Sn;
+    for (int o = 0; o < S->op_count; ++o) {
+      const RegOpDev& op = rops[S->op_begin + o];
+      if ((base & op.gcm) != op.gcv) continue;  // non-local controls: uniform per tile
+      const cx<R>* m = pool + op.moff;
+      if (op.kind == 3) {
+        const uint32_t to = lthr(*S, tau);
+#pragma unroll
+        for (int i = 0; i < NR; ++i) t[sw(lreg<RB>(*S, i) | to)] = v[i];
+        __syncthreads();
+        lds_op<R, KMAX>(t, lops[op.lop], pool, L, base, sw);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NR; ++i) v[i] = t[sw(lreg<RB>(*S, i) | to)];
+        __syncthreads();
+        continue;
+      }
+      if ((tau & op.ti_cm) != op.ti_cv) continue;  // controls on thread bits
+      if (op.kind == 2) reg_diag<R, NR>(v, op, m, tau, base);
+      else reg_apply<R, NR>(v, op.kind, op.p1, op.p2, m, op.ri_cm, op.ri_cv);
+    }
+  }
+
+  // registers -> HBM in the last segment's layout
+  gthr = base;
+  for (int k = 0; k < kRegThreadBits; ++k)
+    if ((tau >> k) & 1) gthr |= gbit(S->thr[k]);
+#pragma unroll
+  for (int k = 0; k < RB; ++k) greg[k] = gbit(S->reg[k]);
+  if (sizeof(R) == 4 && S->reg[0] == 0) {
+#pragma unroll
+    for (int i = 0; i < NR; i += 2) {
+      uint64_t x = gthr;
+#pragma unroll
+      for (int k = 1; k < RB; ++k)
+        if ((i >> k) & 1) x |= greg[k];
+      AmpIO<R, 2>::store(psi, x, &v[i]);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      uint64_t x = gthr;
+#pragma unroll
+      for (int k = 0; k < RB; ++k)
+        if ((i >> k) & 1) x |= greg[k];
+      AmpIO<R, 1>::store(psi, x, &v[i]);
+    }
+  }
+}
+
+}  // namespace qsv

@@ -71,6 +71,29 @@ def test_mixed_gates(dt, kw):
         assert err <= AMP_TOL[dt], (err, info)
 
 
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("max_k", [1, 2, 3])
+def test_register_resident_tiles(dt, max_k):
+    # default tiles (13 local qubits for complex64, 12 for complex128) run
+    # register-resident once the state is at least one tile; max_k=3 also
+    # exercises blocks applied through LDS inside a register-resident pass
+    for n, seed in ((13, 3), (14, 4), (16, 5)):
+        gates = mixed_circuit(n, 220, seed)
+        got, info = fused_state(n, gates, dt, max_k=max_k)
+        ref = O.run_circuit(n, gates)
+        err = np.max(np.abs(got - ref))
+        assert err <= AMP_TOL[dt], (n, err, info)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_register_resident_layered_and_random(dt):
+    n = 16
+    for gates in (W.layered_rx_rz_cnot(n, 10, seed_key=(2, n)), W.random_u_cz(n, 20, seed_key=(1, n))):
+        for max_k in (1, 2):
+            got, info = fused_state(n, gates, dt, max_k=max_k)
+            assert np.max(np.abs(got - O.run_circuit(n, gates))) <= AMP_TOL[dt], info
+
+
 def test_layered_10q_single_pass():
     n = 10
     gates = W.layered_rx_rz_cnot(n, 10, seed_key=(0,))
