@@ -13,6 +13,7 @@
 // with one pass per flip mask, HBM traffic drops by the number of masks per
 // pass. Z/Y signs on non-local qubits are constants per tile.
 #include <algorithm>
+#include <cstdlib>
 
 #include "dev_common.h"
 #include "observable.h"
@@ -21,7 +22,7 @@
 
 namespace qsv {
 
-constexpr int kExpThreads = 256;
+constexpr int kExpThreads = 512;
 constexpr int kExpMaxHigh = 16;
 constexpr int kExpMaxGlobal = 40;
 
@@ -44,6 +45,14 @@ struct ExpTermDev {
   uint32_t zl;    // sign mask on local qubits (local index space)
   uint32_t pad;
 };
+
+// A term as staged in LDS for one tile: coefficient with the tile's sign on
+// non-local qubits folded in, and the local sign mask.
+struct ExpTermLds {
+  double re, im;
+  uint32_t zl;
+};
+constexpr int kExpLdsTerms = 256;
 
 struct ExpPlan {
   int n = 0, L = 0, b = 0;
@@ -68,6 +77,7 @@ __global__ void __launch_bounds__(kExpThreads)
                   double* __restrict__ partial, int accumulate) {
   extern __shared__ __align__(16) char smem[];
   __shared__ double red[kExpThreads / 64];
+  __shared__ ExpTermLds et[kExpLdsTerms];
   cx<R>* t = reinterpret_cast<cx<R>*>(smem);
   const ExpPassDev& P = passes[pass_idx];
   const int L = P.L, b = P.b, nh = P.nh;
@@ -84,38 +94,99 @@ __global__ void __launch_bounds__(kExpThreads)
     for (int i = 0; i < nh; ++i) x |= uint64_t((h >> i) & 1) << P.hq[i];
     AmpIO<R, V>::load(psi, x, &t[j]);
   }
-  __syncthreads();
   double acc = 0.0;
   for (int gi = 0; gi < P.grp_count; ++gi) {
     const ExpGroupDev G = groups[P.grp_begin + gi];
-    if (G.lf == 0) {
+    const int nt = G.term_count;
+    if (gi == 0) __syncthreads();  // tile loaded
+    if (nt > 1) {
+      // stage the group's terms with their sign on non-local qubits folded in
+      // (a constant for this tile)
+      __syncthreads();
+      const int ns = min(nt, kExpLdsTerms);
+      for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+        const ExpTermDev T = terms[G.term_begin + k];
+        const bool gneg = __popcll(base & T.zg) & 1;
+        et[k] = {gneg ? -T.re : T.re, gneg ? -T.im : T.im, T.zl};
+      }
+      __syncthreads();
+    }
+    if (G.lf == 0 && nt == 1) {
+      const ExpTermDev T = terms[G.term_begin];
+      const double re = (__popcll(base & T.zg) & 1) ? -T.re : T.re;
+      double sum = 0.0;
+      for (int j = threadIdx.x; j < TS; j += blockDim.x) {
+        const cx<R> a = t[j];
+        const double p = double(a.re) * a.re + double(a.im) * a.im;
+        sum += (__popc(uint32_t(j) & T.zl) & 1) ? -p : p;
+      }
+      acc += re * sum;
+    } else if (G.lf == 0) {
       for (int j = threadIdx.x; j < TS; j += blockDim.x) {
         const cx<R> a = t[j];
         double c = 0.0;
-        for (int k = G.term_begin; k < G.term_begin + G.term_count; ++k) {
-          const ExpTermDev T = terms[k];
-          const int s = (__popc(uint32_t(j) & T.zl) + __popcll(base & T.zg)) & 1;
-          c += s ? -T.re : T.re;
+        for (int k = 0; k < nt; ++k) {
+          double re;
+          uint32_t zl;
+          if (k < kExpLdsTerms) {
+            re = et[k].re;
+            zl = et[k].zl;
+          } else {
+            const ExpTermDev T = terms[G.term_begin + k];
+            re = (__popcll(base & T.zg) & 1) ? -T.re : T.re;
+            zl = T.zl;
+          }
+          c += (__popc(uint32_t(j) & zl) & 1) ? -re : re;
         }
         acc += (double(a.re) * a.re + double(a.im) * a.im) * c;
       }
     } else {
       const int hb = G.hbit;
-      for (int i = threadIdx.x; i < TS / 2; i += blockDim.x) {
-        const uint32_t x = ((uint32_t(i) >> hb) << (hb + 1)) | (uint32_t(i) & ((1u << hb) - 1));
-        const uint32_t y = x ^ G.lf;
-        const cx<R> a = t[x], bb = t[y];
-        // w = conj(psi[y]) psi[x]
-        const double wr = double(bb.re) * a.re + double(bb.im) * a.im;
-        const double wi = double(bb.re) * a.im - double(bb.im) * a.re;
-        double cr = 0.0, ci = 0.0;
-        for (int k = G.term_begin; k < G.term_begin + G.term_count; ++k) {
-          const ExpTermDev T = terms[k];
-          const int s = (__popc(x & T.zl) + __popcll(base & T.zg)) & 1;
-          cr += s ? -T.re : T.re;
-          ci += s ? -T.im : T.im;
+      const uint32_t lf = G.lf;
+      if (nt == 1) {
+        // one term (the common case for random strings): c(x) = +-(re + i im)
+        const ExpTermDev T = terms[G.term_begin];
+        const bool gneg = __popcll(base & T.zg) & 1;
+        const double re = gneg ? -T.re : T.re, im = gneg ? -T.im : T.im;
+        const uint32_t zl = T.zl;
+        double sum = 0.0;
+        for (int i = threadIdx.x; i < TS / 2; i += blockDim.x) {
+          const uint32_t x = ((uint32_t(i) >> hb) << (hb + 1)) | (uint32_t(i) & ((1u << hb) - 1));
+          const cx<R> a = t[x], bb = t[x ^ lf];
+          const double wr = double(bb.re) * a.re + double(bb.im) * a.im;
+          const double wi = double(bb.re) * a.im - double(bb.im) * a.re;
+          const double v = wr * re - wi * im;
+          sum += (__popc(x & zl) & 1) ? -v : v;
         }
-        acc += 2.0 * (wr * cr - wi * ci);
+        acc += 2.0 * sum;
+      } else {
+        for (int i = threadIdx.x; i < TS / 2; i += blockDim.x) {
+          const uint32_t x = ((uint32_t(i) >> hb) << (hb + 1)) | (uint32_t(i) & ((1u << hb) - 1));
+          const cx<R> a = t[x], bb = t[x ^ lf];
+          // w = conj(psi[y]) psi[x]
+          const double wr = double(bb.re) * a.re + double(bb.im) * a.im;
+          const double wi = double(bb.re) * a.im - double(bb.im) * a.re;
+          double cr = 0.0, ci = 0.0;
+          for (int k = 0; k < nt; ++k) {
+            double re, im;
+            uint32_t zl;
+            if (k < kExpLdsTerms) {
+              re = et[k].re;
+              im = et[k].im;
+              zl = et[k].zl;
+            } else {
+              const ExpTermDev T = terms[G.term_begin + k];
+              const bool gneg = __popcll(base & T.zg) & 1;
+              re = gneg ? -T.re : T.re;
+              im = gneg ? -T.im : T.im;
+              zl = T.zl;
+            }
+            const bool neg = __popc(x & zl) & 1;
+            cr += neg ? -re : re;
+            ci += neg ? -im : im;
+          }
+          acc += 2.0 * (wr * cr - wi * ci);
+        }
       }
     }
   }
@@ -159,7 +230,12 @@ ExpPlan* build_exp_plan(const qsv_observable* o, qsv_dtype dt) {
   ExpPlan* p = new ExpPlan();
   const int n = o->n;
   p->n = n;
-  p->L = std::min(n, dt == QSV_C64 ? 13 : 12);
+  // tile: 2^L amplitudes, 32 KiB (measured on MI355X at 30 qubits: 32 KiB
+  // tiles under 512-thread workgroups beat 64 KiB and 16 KiB ones);
+  // QSV_EXPECT_TILE overrides L, for tuning
+  int Ldef = dt == QSV_C64 ? 12 : 11;
+  if (const char* e = std::getenv("QSV_EXPECT_TILE")) Ldef = std::max(6, std::min(Ldef, std::atoi(e)));
+  p->L = std::min(n, Ldef);
   p->b = std::min(p->L, dt == QSV_C64 ? 6 : 5);
   const int L = p->L, b = p->b;
   const uint64_t low = (uint64_t(1) << b) - 1;
