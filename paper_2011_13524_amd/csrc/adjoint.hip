@@ -16,6 +16,7 @@
 // psi[y ^ F] for every flip mask F of the observable and writes lambda once.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "circuit.h"
 #include "dev_common.h"
@@ -129,6 +130,9 @@ __global__ void __launch_bounds__(kAdjThreads)
 
 int expectation_impl(qsv_state* s, const qsv_observable* o, double* out);
 int circuit_apply_unfused(qsv_state* s, const qsv_circuit* c, const double* theta);
+template <typename R>
+int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state* psi, qsv_state* lam,
+                           std::vector<int>& row_slot, std::vector<double>& rows);
 
 namespace {
 
@@ -206,6 +210,19 @@ int adjoint_t(const qsv_circuit* c, qsv_plan* plan, const double* theta, const q
   int nrot = 0;
   for (const Gate& g : c->gates)
     if (g.kind == Gate::ROTATION && g.slot >= 0) ++nrot;
+  // large states: reverse sweep by tile passes (both states streamed once per
+  // pass); small states keep one launch per gate, which spreads better
+  const int Ltile = sizeof(R) == 4 ? 12 : 11;
+  int tiled_min = Ltile + 8;
+  if (const char* e = std::getenv("QSV_ADJOINT_TILED_MIN")) tiled_min = std::atoi(e);  // testing
+  if (n >= tiled_min) {
+    std::vector<int> rs;
+    std::vector<double> rv;
+    if ((rc = adjoint_backward_tiled<R>(c, theta, psi, lam, rs, rv))) return rc;
+    for (int i = 0; i < c->nparams; ++i) grad[i] = 0.0;
+    for (size_t r = 0; r < rs.size(); ++r) grad[rs[r]] += rv[r];
+    return QSV_OK;
+  }
   const int B = adj_blocks(N / 2);
   if ((rc = ensure_reduce_scratch(psi, size_t(nrot) * B + size_t(nrot) + 1))) return rc;
   double* partial = psi->red;

@@ -134,3 +134,28 @@ def test_zz_autograd_function():
     assert abs(e.item() - O.energy(n, gates, theta0, obs_t)) <= 1e-12
     np.testing.assert_allclose(theta.grad.numpy(), O.param_shift_grad(n, gates, theta0, obs_t),
                                atol=1e-11)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_tiled_reverse_sweep_vs_parameter_shift(dt, monkeypatch):
+    # the tile-pass reverse sweep (used by default from 20 qubits) forced on
+    # small states: one tile (n=9) and several tiles with non-local controls
+    # and diagonal gates (n=14)
+    monkeypatch.setenv("QSV_ADJOINT_TILED_MIN", "1")
+    cases = [(9, W.ry_rz_cnot_ring(9, 2)), (14, W.hea_ry_rz_cz(14, 1))]
+    for n, (gates, npar) in cases:
+        # (one gate per slot: the two-term shift rule is exact only then)
+        gates = gates + [{"op": "rx", "q": [n - 1], "slot": npar}, {"op": "h", "q": [3]},
+                         {"op": "dense", "q": [0, n - 2], "mat": W.haar_unitary(np.random.default_rng(n), 4)},
+                         {"op": "ry", "q": [1], "slot": npar + 1}]
+        npar += 2
+        theta = W.uniform_angles(npar, (11, n))
+        obs = W.random_pauli_observable(n, 12, (1, 4), seed_key=(11, n)) + [(0.2, [])]
+        c = Circuit.from_records(n, gates)
+        psi, lam = State(n, dt), State(n, dt)
+        e, g = adjoint_gradient(c, theta, Observable(n, obs), psi, lam)
+        scale = sum(abs(cf) for cf, _ in obs)
+        slots = list(range(0, npar, max(1, npar // 12))) + [0, npar - 1]
+        g_ref = O.param_shift_grad(n, gates, theta, obs, slots=slots)
+        assert abs(e - O.energy(n, gates, theta, obs)) <= TOL[dt] * scale
+        assert np.max(np.abs(g[slots] - g_ref)) <= TOL[dt] * scale, (n, np.max(np.abs(g[slots] - g_ref)))
