@@ -23,24 +23,82 @@ namespace qsv {
 constexpr int kAdjTileThreads = 256;
 constexpr int kAdjTileGrid = 2048;
 
-// TileOpDev with kind 2 = gradient term: k = Pauli id, lt[0] = local target or
-// -1, gq[0] = global qubit (Z on a non-local qubit), moff = partial row.
+// TileOpDev with kind 2 = parametric rotation exp(i t P/2) seen by the reverse
+// sweep: k = Pauli id, lt[0] = local target or -1, gq[0] = global qubit (Z on
+// a non-local qubit), moff = pool offset of exp(-i t P/2) (2x2), ins[0] =
+// partial row. One LDS sweep adds -Im<lambda|P|psi> of the tile and multiplies
+// both states by exp(-i t P/2).
 
+// Dense one-qubit op on both states in one sweep (matrix in registers).
 template <typename R>
-__device__ __forceinline__ double grad_term(const cx<R>* __restrict__ ps, const cx<R>* __restrict__ la,
-                                           const TileOpDev& op, int L, uint64_t base) {
+__device__ __forceinline__ void adj_dense1(cx<R>* __restrict__ ts, cx<R>* __restrict__ tl,
+                                           const TileOpDev& op, const cx<R>* __restrict__ mat, int L) {
+  const cx<R> m00 = mat[0], m01 = mat[1], m10 = mat[2], m11 = mat[3];
+  const int cnt = 1 << (L - op.m);
+  const uint32_t o1 = op.off[1];
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const uint32_t j0 = insert_zeros32(i, op.ins, op.m) | op.lcv;
+    const cx<R> a = ts[j0], b = ts[j0 + o1], c = tl[j0], d = tl[j0 + o1];
+    ts[j0] = cfma(m00, a, m01 * b);
+    ts[j0 + o1] = cfma(m10, a, m11 * b);
+    tl[j0] = cfma(m00, c, m01 * d);
+    tl[j0 + o1] = cfma(m10, c, m11 * d);
+  }
+}
+
+// Diagonal op on both states in one sweep.
+template <typename R>
+__device__ __forceinline__ void adj_diag(cx<R>* __restrict__ ts, cx<R>* __restrict__ tl,
+                                         const TileOpDev& op, const cx<R>* __restrict__ d, int L,
+                                         uint64_t base) {
+  int gidx = 0;
+  for (int b = 0; b < op.k; ++b)
+    if (op.gq[b] >= 0) gidx |= int((base >> op.gq[b]) & 1) << b;
+  const int TS = 1 << L;
+  for (int j = threadIdx.x; j < TS; j += blockDim.x) {
+    if ((uint32_t(j) & op.lcm) != op.lcv) continue;
+    int idx = gidx;
+    for (int b = 0; b < op.k; ++b)
+      if (op.lt[b] >= 0) idx |= ((j >> op.lt[b]) & 1) << b;
+    const cx<R> f = d[idx];
+    ts[j] = f * ts[j];
+    tl[j] = f * tl[j];
+  }
+}
+
+// Gradient term of a rotation fused with its uncompute; returns this thread's
+// share of -Im<lambda|P|psi> (taken before the uncompute).
+template <typename R>
+__device__ __forceinline__ double adj_rot(cx<R>* __restrict__ ps, cx<R>* __restrict__ la,
+                                          const TileOpDev& op, const cx<R>* __restrict__ u, int L,
+                                          uint64_t base) {
   double acc = 0.0;
   const int pauli = op.k;
   const int TS = 1 << L;
+  const cx<R> u00 = u[0], u01 = u[1], u10 = u[2], u11 = u[3];
   if (pauli == 3) {
-    // Z: sum_x (-1)^{x_q} Im(conj(lambda_x) psi_x)
+    // Z: sum_x (-1)^{x_q} Im(conj(lambda_x) psi_x); exp(-i t Z/2) is diagonal
     const int p = op.lt[0];
-    const double gsign = (p < 0 && ((base >> op.gq[0]) & 1)) ? -1.0 : 1.0;
-    for (int j = threadIdx.x; j < TS; j += blockDim.x) {
-      const cx<R> a = ps[j], l = la[j];
-      double im = double(l.re) * a.im - double(l.im) * a.re;
-      if (p >= 0 && ((j >> p) & 1)) im = -im;
-      acc -= gsign * im;
+    if (p < 0) {
+      const bool one = (base >> op.gq[0]) & 1;
+      const double sg = one ? -1.0 : 1.0;
+      const cx<R> f = one ? u11 : u00;
+      for (int j = threadIdx.x; j < TS; j += blockDim.x) {
+        const cx<R> a = ps[j], l = la[j];
+        acc -= sg * (double(l.re) * a.im - double(l.im) * a.re);
+        ps[j] = f * a;
+        la[j] = f * l;
+      }
+    } else {
+      for (int j = threadIdx.x; j < TS; j += blockDim.x) {
+        const cx<R> a = ps[j], l = la[j];
+        const bool one = (j >> p) & 1;
+        const double im = double(l.re) * a.im - double(l.im) * a.re;
+        acc -= one ? -im : im;
+        const cx<R> f = one ? u11 : u00;
+        ps[j] = f * a;
+        la[j] = f * l;
+      }
     }
   } else {
     const int p = op.lt[0];
@@ -55,6 +113,10 @@ __device__ __forceinline__ double grad_term(const cx<R>* __restrict__ ps, const 
       if (pauli == 1) im = (l0r * a1i - l0i * a1r) + (l1r * a0i - l1i * a0r);
       else im = -(l0r * a1r + l0i * a1i) + (l1r * a0r + l1i * a0i);
       acc -= im;
+      ps[x0] = cfma(u00, a0, u01 * a1);
+      ps[x1] = cfma(u10, a0, u11 * a1);
+      la[x0] = cfma(u00, l0, u01 * l1);
+      la[x1] = cfma(u10, l0, u11 * l1);
     }
   }
   return acc;
@@ -91,7 +153,7 @@ __global__ void __launch_bounds__(kAdjTileThreads)
       const TileOpDev& op = ops[P.op_begin + o];
       if ((base & op.gcm) != op.gcv) continue;
       if (op.kind == 2) {
-        double acc = grad_term<R>(ts, tl, op, L, base);
+        double acc = adj_rot<R>(ts, tl, op, pool + op.moff, L, base);
 #pragma unroll
         for (int s = 32; s > 0; s >>= 1) acc += __shfl_xor(acc, s, 64);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -99,14 +161,17 @@ __global__ void __launch_bounds__(kAdjTileThreads)
         if (threadIdx.x == 0) {
           double r = 0.0;
           for (int w = 0; w < kAdjTileThreads / 64; ++w) r += red[w];
-          partial[size_t(op.moff) * gridDim.x + blockIdx.x] += r;
+          partial[size_t(op.ins[0]) * gridDim.x + blockIdx.x] += r;
         }
-        __syncthreads();
+      } else if (op.kind == 1) {
+        adj_diag<R>(ts, tl, op, pool + op.moff, L, base);
+      } else if (op.k == 1) {
+        adj_dense1<R>(ts, tl, op, pool + op.moff, L);
       } else {
         lds_op<R, KMAX>(ts, op, pool, L, base, NoSwz());
         lds_op<R, KMAX>(tl, op, pool, L, base, NoSwz());
-        __syncthreads();
       }
+      __syncthreads();
     }
     for (int e = threadIdx.x; e < TS / V; e += blockDim.x) {
       const uint32_t j = uint32_t(e) * V;
@@ -118,6 +183,7 @@ __global__ void __launch_bounds__(kAdjTileThreads)
     }
   }
 }
+
 
 // rows[r] = sum of the cols partials of row r (fixed order)
 __global__ void __launch_bounds__(kAdjTileThreads)
@@ -182,13 +248,17 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
   for (int gi = int(c->gates.size()) - 1; gi >= 0; --gi) {
     const Gate& g = c->gates[gi];
     if (g.kind == Gate::ROTATION && g.slot >= 0) {
+      // gradient term fused with the uncompute exp(-i t P/2)
       BOp gr;
       gr.kind = 2;
       gr.pauli = g.pauli;
       gr.targets = g.targets;
       gr.row = int(row_slot.size());
       row_slot.push_back(g.slot);
+      gr.val.resize(4);
+      rotation_matrix(g.pauli, -theta[g.slot], gr.val.data());
       ops.push_back(gr);
+      continue;
     }
     gate_matrix(g, theta, m);
     std::vector<int> tq = g.targets;
@@ -287,7 +357,9 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
       if (o.kind == 2) {
         t.kind = 2;
         t.k = o.pauli;
-        t.moff = o.row;
+        t.ins[0] = o.row;
+        t.moff = int(pool.size());
+        for (const cd& v : o.val) pool.push_back({R(v.re), R(v.im)});
         const int q = o.targets[0];
         if (lpos[q] >= 0) t.lt[0] = lpos[q];
         else t.gq[0] = q;

@@ -42,11 +42,12 @@ struct TilePassDev {
 // registers (reg) and which index the thread (thr); ops of the segment whose
 // dense targets are register bits run without touching LDS.
 constexpr int kRegMaxBits = 6;
-constexpr int kRegThreadBits = 8;
+constexpr int kRegThreadBits = 8;      // default: 256-thread workgroups
+constexpr int kRegMaxThreadBits = 9;   // up to 512-thread workgroups
 
 struct RegSegDev {
   int reg[kRegMaxBits];      // local positions of register-index bits, ascending
-  int thr[kRegThreadBits];   // local positions of thread-index bits, ascending
+  int thr[kRegMaxThreadBits];  // local positions of thread-index bits, ascending
   int op_begin, op_count;
 };
 
@@ -96,6 +97,7 @@ struct qsv_plan {
   std::vector<qsv::RegSegDev> h_segs;
   std::vector<qsv::RegOpDev> h_rops;
   int reg_bits = 0;  // > 0: passes run register-resident
+  int thread_bits = qsv::kRegThreadBits;  // workgroup = 2^thread_bits threads
   int kmax_dense = 1;  // widest dense op (selects the kernel instantiation)
   // device buffers
   qsv::TilePassDev* d_pass = nullptr;

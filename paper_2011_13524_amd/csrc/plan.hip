@@ -26,6 +26,7 @@
 // and writes the state once however many gates it applies.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "dev_common.h"
 #include "plan.h"
@@ -365,7 +366,7 @@ static int build_segments(qsv_plan* p, const std::vector<TileOpDev>& ho, TilePas
         regidx[pos] = -1;
       }
     }
-    if (nr != RB || nt != kRegThreadBits) return fail(QSV_EINVAL, "internal: bad segment layout");
+    if (nr != RB || nt != p->thread_bits) return fail(QSV_EINVAL, "internal: bad segment layout");
     sd.op_begin = int(p->h_rops.size());
     sd.op_count = int(s.ops.size());
     for (int oi : s.ops) {
@@ -496,7 +497,7 @@ static int upload_tables(qsv_plan* p, std::vector<int>& moffs, size_t& pool_elem
     }
     d.seg_begin = int(p->h_segs.size());
     d.seg_count = 0;
-    if (p->reg_bits > 0 && d.L == p->reg_bits + kRegThreadBits) {
+    if (p->reg_bits > 0 && d.L == p->reg_bits + p->thread_bits) {
       int rc = build_segments(p, ho, d);
       if (rc) return rc;
     }
@@ -636,15 +637,24 @@ static int apply_fused_t(qsv_state* s, qsv_plan* p, const double* theta) {
     constexpr int RB = sizeof(R) == 4 ? 5 : 4;
     R* psi = static_cast<R*>(s->ptr);
     const cx<R>* pool = static_cast<const cx<R>*>(p->d_pool);
-    const dim3 grid(static_cast<unsigned>(tiles)), block(256);
-#define QSV_TILE_LAUNCH(KM)                                                                    \
-  do {                                                                                         \
-    if (p->h_pass[pi].seg_count > 0)                                                           \
-      hipLaunchKernelGGL((k_tile_reg<R, RB, KM>), grid, block, lds, s->stream, psi, p->d_pass, \
-                         int(pi), p->d_segs, p->d_rops, p->d_ops, pool);                       \
-    else                                                                                       \
-      hipLaunchKernelGGL((k_tile<R, KM>), grid, block, lds, s->stream, psi, p->d_pass, int(pi), \
-                         p->d_ops, pool);                                                      \
+    const dim3 grid(static_cast<unsigned>(tiles)), block(256), block512(512);
+    const bool wide = p->thread_bits == 9;
+#define QSV_TILE_LAUNCH(KM)                                                                      \
+  do {                                                                                           \
+    if (p->h_pass[pi].seg_count > 0) {                                                           \
+      if constexpr (sizeof(R) == 4) {                                                            \
+        if (wide) {                                                                              \
+          hipLaunchKernelGGL((k_tile_reg<R, 4, KM, 9>), grid, block512, lds, s->stream, psi,     \
+                             p->d_pass, int(pi), p->d_segs, p->d_rops, p->d_ops, pool);          \
+          break;                                                                                 \
+        }                                                                                        \
+      }                                                                                          \
+      hipLaunchKernelGGL((k_tile_reg<R, RB, KM, 8>), grid, block, lds, s->stream, psi,           \
+                         p->d_pass, int(pi), p->d_segs, p->d_rops, p->d_ops, pool);              \
+    } else {                                                                                     \
+      hipLaunchKernelGGL((k_tile<R, KM>), grid, block, lds, s->stream, psi, p->d_pass, int(pi),   \
+                         p->d_ops, pool);                                                        \
+    }                                                                                            \
   } while (0)
     if (p->kmax_dense <= 2) QSV_TILE_LAUNCH(2);
     else if (p->kmax_dense <= 3) QSV_TILE_LAUNCH(3);
@@ -689,8 +699,16 @@ int qsv_plan_fused(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qu
   p->b = b;
   // register-resident passes when the tile is 256 threads x 2^RB amplitudes
   // (RB = 5 for complex64, 4 for complex128: 64 KiB of LDS for re-mapping)
-  const int RB = dtype == QSV_C64 ? 5 : 4;
-  p->reg_bits = (L == RB + kRegThreadBits && n >= L) ? RB : 0;
+  // QSV_TILE_THREAD_BITS=9 selects 512-thread workgroups (tuning)
+  // complex64: 512-thread workgroups x 16 amplitudes (measured ~7% faster than
+  // 256 x 32 at 30 qubits: twice the waves hide more latency); complex128:
+  // 256 x 16 (2^3 per thread would leave too few register bits)
+  int TB = dtype == QSV_C64 ? 9 : kRegThreadBits;
+  if (const char* e = std::getenv("QSV_TILE_THREAD_BITS")) TB = std::atoi(e) == 9 ? 9 : 8;
+  if (dtype == QSV_C128) TB = kRegThreadBits;
+  const int RB = (dtype == QSV_C64 ? 13 : 12) - TB;
+  p->thread_bits = TB;
+  p->reg_bits = (L == RB + TB && n >= L) ? RB : 0;
   p->circ_copy = *c;
   int rc = build_plan(p);
   std::vector<int> moffs;

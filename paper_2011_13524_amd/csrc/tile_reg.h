@@ -266,15 +266,16 @@ __device__ __forceinline__ uint32_t lreg(const RegSegDev& s, int i) {
   return j;
 }
 
+template <int TB>
 __device__ __forceinline__ uint32_t lthr(const RegSegDev& s, uint32_t tau) {
   uint32_t j = 0;
 #pragma unroll
-  for (int b = 0; b < kRegThreadBits; ++b) j |= ((tau >> b) & 1) << s.thr[b];
+  for (int b = 0; b < TB; ++b) j |= ((tau >> b) & 1) << s.thr[b];
   return j;
 }
 
-template <typename R, int RB, int KMAX>
-__global__ void __launch_bounds__(256)
+template <typename R, int RB, int KMAX, int TB>
+__global__ void __launch_bounds__(1 << TB)
     k_tile_reg(R* __restrict__ psi, const TilePassDev* __restrict__ passes, int pass_idx,
                const RegSegDev* __restrict__ segs, const RegOpDev* __restrict__ rops,
                const TileOpDev* __restrict__ lops, const cx<R>* __restrict__ pool) {
@@ -295,7 +296,7 @@ __global__ void __launch_bounds__(256)
   // HBM -> registers in the first segment's layout
   const RegSegDev* S = &segs[P.seg_begin];
   uint64_t gthr = base;
-  for (int k = 0; k < kRegThreadBits; ++k)
+  for (int k = 0; k < TB; ++k)
     if ((tau >> k) & 1) gthr |= gbit(S->thr[k]);
   uint64_t greg[RB];
 #pragma unroll
@@ -325,11 +326,11 @@ __global__ void __launch_bounds__(256)
     const RegSegDev* Sn = &segs[P.seg_begin + sgi];
     if (sgi > 0) {
       // re-map through LDS
-      const uint32_t to = lthr(*S, tau);
+      const uint32_t to = lthr<TB>(*S, tau);
 #pragma unroll
       for (int i = 0; i < NR; ++i) t[sw(lreg<RB>(*S, i) | to)] = v[i];
       __syncthreads();
-      const uint32_t tn = lthr(*Sn, tau);
+      const uint32_t tn = lthr<TB>(*Sn, tau);
 #pragma unroll
       for (int i = 0; i < NR; ++i) v[i] = t[sw(lreg<RB>(*Sn, i) | tn)];
       __syncthreads();
@@ -340,7 +341,7 @@ __global__ void __launch_bounds__(256)
       if ((base & op.gcm) != op.gcv) continue;  // non-local controls: uniform per tile
       const cx<R>* m = pool + op.moff;
       if (op.kind == 3) {
-        const uint32_t to = lthr(*S, tau);
+        const uint32_t to = lthr<TB>(*S, tau);
 #pragma unroll
         for (int i = 0; i < NR; ++i) t[sw(lreg<RB>(*S, i) | to)] = v[i];
         __syncthreads();
@@ -359,7 +360,7 @@ __global__ void __launch_bounds__(256)
 
   // registers -> HBM in the last segment's layout
   gthr = base;
-  for (int k = 0; k < kRegThreadBits; ++k)
+  for (int k = 0; k < TB; ++k)
     if ((tau >> k) & 1) gthr |= gbit(S->thr[k]);
 #pragma unroll
   for (int k = 0; k < RB; ++k) greg[k] = gbit(S->reg[k]);
