@@ -58,7 +58,31 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fd-params", type=int, default=6)
     ap.add_argument("--batch-items", type=int, default=512)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also copy the state once (a device copy of known size, used to "
+                         "calibrate rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def traffic_from_profile(kernel_prefix):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "traffic_30q_c64_headline.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    h = hashlib.sha256()
+    for name in rec.get("sources", []):
+        h.update(open(os.path.join(ROOT, name), "rb").read())
+    if h.hexdigest() != rec.get("sources_sha256") or not rec.get("kernel", "").startswith(kernel_prefix):
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
 def sync(Q, state):
@@ -298,10 +322,15 @@ def main():
                             for f, v in fams.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": None,
+                     "traffic": traffic_from_profile("qsv::k_tile_reg") if dom == "tile" else None,
                      "bytes_per_launch": d["bytes"] / d["launches"],
                      "avg_launch_ms": d["ms"] / d["launches"]},
     }
+    if args.calib_copy:
+        other = Q.State(n, dt)
+        other.copy_from(state)  # device-to-device copy of 2^n x 8 bytes
+        other.norm2()
+        del other
     del state
     if not args.quick:
         out["adjoint_24q"] = adjoint_leg(Q, W, args.fd_params)
