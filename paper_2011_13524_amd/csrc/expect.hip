@@ -70,6 +70,23 @@ void free_exp_plan(ExpPlan* p) {
   delete p;
 }
 
+// Local index -> global index bits of a pass (bit placement: linear over OR
+// for local indices with disjoint bits, so per-thread and per-iteration parts
+// are placed once and combined with one OR).
+__device__ __forceinline__ uint64_t exp_place(const ExpPassDev& P, uint32_t j) {
+  uint64_t x = j & ((1u << P.b) - 1);
+  for (int i = 0; i < P.nh; ++i) x |= uint64_t((j >> (P.b + i)) & 1) << P.hq[i];
+  return x;
+}
+
+__device__ __forceinline__ uint32_t ins0(uint32_t i, int hb) {
+  return ((i >> hb) << (hb + 1)) | (i & ((1u << hb) - 1));
+}
+
+// One tile of one pass: the tile is read into LDS once, then every flip-mask
+// group of the pass is evaluated on it. Pair products conj(psi_y) psi_x and
+// the thread's few partial sums use the amplitude precision; every sum over
+// threads, tiles and passes is FP64.
 template <typename R>
 __global__ void __launch_bounds__(kExpThreads)
     k_expect_tile(const R* __restrict__ psi, const ExpPassDev* __restrict__ passes, int pass_idx,
@@ -80,19 +97,20 @@ __global__ void __launch_bounds__(kExpThreads)
   __shared__ ExpTermLds et[kExpLdsTerms];
   cx<R>* t = reinterpret_cast<cx<R>*>(smem);
   const ExpPassDev& P = passes[pass_idx];
-  const int L = P.L, b = P.b, nh = P.nh;
+  const int L = P.L;
   const uint64_t g = blockIdx.x;
   uint64_t base = 0;
   for (int j = 0; j < P.ng; ++j) base |= ((g >> j) & 1) << P.gpos[j];
   constexpr int V = sizeof(R) == 4 ? 2 : 1;
-  const int TS = 1 << L;
-  const uint32_t lowmask = (1u << b) - 1;
-  for (int e = threadIdx.x; e < TS / V; e += blockDim.x) {
-    const uint32_t j = uint32_t(e) * V;
-    const uint32_t h = j >> b;
-    uint64_t x = base + (j & lowmask);
-    for (int i = 0; i < nh; ++i) x |= uint64_t((h >> i) & 1) << P.hq[i];
-    AmpIO<R, V>::load(psi, x, &t[j]);
+  const uint32_t TS = 1u << L;
+  const uint32_t tid = threadIdx.x;
+  {
+    const uint64_t xt = base | exp_place(P, tid * V);
+    for (uint32_t e0 = 0; e0 < TS / V; e0 += kExpThreads) {
+      if (e0 + tid >= TS / V) break;
+      const uint64_t x = xt | exp_place(P, e0 * V);
+      AmpIO<R, V>::load(psi, x, &t[(e0 + tid) * V]);
+    }
   }
   double acc = 0.0;
   for (int gi = 0; gi < P.grp_count; ++gi) {
@@ -104,7 +122,7 @@ __global__ void __launch_bounds__(kExpThreads)
       // (a constant for this tile)
       __syncthreads();
       const int ns = min(nt, kExpLdsTerms);
-      for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+      for (int k = tid; k < ns; k += blockDim.x) {
         const ExpTermDev T = terms[G.term_begin + k];
         const bool gneg = __popcll(base & T.zg) & 1;
         et[k] = {gneg ? -T.re : T.re, gneg ? -T.im : T.im, T.zl};
@@ -112,17 +130,20 @@ __global__ void __launch_bounds__(kExpThreads)
       __syncthreads();
     }
     if (G.lf == 0 && nt == 1) {
+      // sum of +-|psi_x|^2: thread part of the sign once, uniform part per step
       const ExpTermDev T = terms[G.term_begin];
       const double re = (__popcll(base & T.zg) & 1) ? -T.re : T.re;
-      double sum = 0.0;
-      for (int j = threadIdx.x; j < TS; j += blockDim.x) {
-        const cx<R> a = t[j];
-        const double p = double(a.re) * a.re + double(a.im) * a.im;
-        sum += (__popc(uint32_t(j) & T.zl) & 1) ? -p : p;
+      const uint32_t pt = __popc(tid & T.zl) & 1;
+      R sum = R(0);
+      for (uint32_t j0 = 0; j0 < TS; j0 += kExpThreads) {
+        if (j0 + tid >= TS) break;
+        const cx<R> a = t[j0 + tid];
+        const R p = a.re * a.re + a.im * a.im;
+        sum += (pt ^ (__popc(j0 & T.zl) & 1)) ? -p : p;
       }
-      acc += re * sum;
+      acc += re * double(sum);
     } else if (G.lf == 0) {
-      for (int j = threadIdx.x; j < TS; j += blockDim.x) {
+      for (uint32_t j = tid; j < TS; j += blockDim.x) {
         const cx<R> a = t[j];
         double c = 0.0;
         for (int k = 0; k < nt; ++k) {
@@ -136,36 +157,43 @@ __global__ void __launch_bounds__(kExpThreads)
             re = (__popcll(base & T.zg) & 1) ? -T.re : T.re;
             zl = T.zl;
           }
-          c += (__popc(uint32_t(j) & zl) & 1) ? -re : re;
+          c += (__popc(j & zl) & 1) ? -re : re;
         }
-        acc += (double(a.re) * a.re + double(a.im) * a.im) * c;
+        acc += double(a.re * a.re + a.im * a.im) * c;
       }
     } else {
       const int hb = G.hbit;
       const uint32_t lf = G.lf;
+      // pairs (x, x ^ lf) with bit hb of x clear: x = ins0(i) for i < TS/2,
+      // i = tid + step; ins0 places bits, so x = ins0(tid) | ins0(step)
+      const uint32_t xt = ins0(tid, hb);
       if (nt == 1) {
         // one term (the common case for random strings): c(x) = +-(re + i im)
         const ExpTermDev T = terms[G.term_begin];
         const bool gneg = __popcll(base & T.zg) & 1;
         const double re = gneg ? -T.re : T.re, im = gneg ? -T.im : T.im;
         const uint32_t zl = T.zl;
-        double sum = 0.0;
-        for (int i = threadIdx.x; i < TS / 2; i += blockDim.x) {
-          const uint32_t x = ((uint32_t(i) >> hb) << (hb + 1)) | (uint32_t(i) & ((1u << hb) - 1));
-          const cx<R> a = t[x], bb = t[x ^ lf];
-          const double wr = double(bb.re) * a.re + double(bb.im) * a.im;
-          const double wi = double(bb.re) * a.im - double(bb.im) * a.re;
-          const double v = wr * re - wi * im;
-          sum += (__popc(x & zl) & 1) ? -v : v;
-        }
-        acc += 2.0 * sum;
-      } else {
-        for (int i = threadIdx.x; i < TS / 2; i += blockDim.x) {
-          const uint32_t x = ((uint32_t(i) >> hb) << (hb + 1)) | (uint32_t(i) & ((1u << hb) - 1));
+        const uint32_t pt = __popc(xt & zl) & 1;
+        R sr = R(0), si = R(0);
+        for (uint32_t i0 = 0; i0 < TS / 2; i0 += kExpThreads) {
+          if (i0 + tid >= TS / 2) break;
+          const uint32_t xs = ins0(i0, hb);
+          const uint32_t x = xt | xs;
           const cx<R> a = t[x], bb = t[x ^ lf];
           // w = conj(psi[y]) psi[x]
-          const double wr = double(bb.re) * a.re + double(bb.im) * a.im;
-          const double wi = double(bb.re) * a.im - double(bb.im) * a.re;
+          const R wr = bb.re * a.re + bb.im * a.im;
+          const R wi = bb.re * a.im - bb.im * a.re;
+          const bool neg = pt ^ (__popc(xs & zl) & 1);
+          sr += neg ? -wr : wr;
+          si += neg ? -wi : wi;
+        }
+        acc += 2.0 * (double(sr) * re - double(si) * im);
+      } else {
+        for (uint32_t i = tid; i < TS / 2; i += blockDim.x) {
+          const uint32_t x = ins0(i, hb);
+          const cx<R> a = t[x], bb = t[x ^ lf];
+          const double wr = double(bb.re * a.re + bb.im * a.im);
+          const double wi = double(bb.re * a.im - bb.im * a.re);
           double cr = 0.0, ci = 0.0;
           for (int k = 0; k < nt; ++k) {
             double re, im;
@@ -192,9 +220,9 @@ __global__ void __launch_bounds__(kExpThreads)
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     double r = 0.0;
     for (int w = 0; w < kExpThreads / 64; ++w) r += red[w];
     partial[blockIdx.x] = accumulate ? partial[blockIdx.x] + r : r;

@@ -37,18 +37,24 @@ struct TilePassDev {
   int gpos[kTileMaxGlobal];  // non-local qubits, ascending
 };
 
-// Register-resident tiles: the 2^L tile is spread over 256 threads holding
+// Register-resident tiles: the 2^L tile is spread over 2^TB threads holding
 // 2^RB amplitudes each. A segment fixes which local bits index a thread's
-// registers (reg) and which index the thread (thr); ops of the segment whose
-// dense targets are register bits run without touching LDS.
+// registers (reg) and which index the thread (thr: lanes first, then the
+// wavefront index); ops of the segment whose dense targets are register bits
+// run without touching LDS.
 constexpr int kRegMaxBits = 6;
 constexpr int kRegThreadBits = 8;      // default: 256-thread workgroups
 constexpr int kRegMaxThreadBits = 9;   // up to 512-thread workgroups
 
 struct RegSegDev {
-  int reg[kRegMaxBits];      // local positions of register-index bits, ascending
-  int thr[kRegMaxThreadBits];  // local positions of thread-index bits, ascending
+  int reg[kRegMaxBits];        // local positions of register-index bits, ascending
+  int thr[kRegMaxThreadBits];  // local position of thread-index bit k
+  int xwave;                   // re-map into this layout crosses wavefronts
   int op_begin, op_count;
+  // the re-map into this layout writes local index x of the previous layout
+  // to position M x ^ mcst (folded X / controlled-X ops); mcol[p] = M e_p
+  uint32_t mcol[kTileMaxHigh + 8];
+  uint32_t mcst;
 };
 
 struct RegOpDev {
@@ -76,6 +82,14 @@ struct Block {
   std::vector<int> controls, ctrl_vals;
 };
 
+}  // namespace qsv
+
+struct qsv_plan;
+
+namespace qsv {
+// Block matrices (dense: 2^k x 2^k row-major; diagonal: 2^k entries) for
+// parameters theta, concatenated in block order (the device pool layout).
+void plan_block_values(const qsv_plan* p, const double* theta, std::vector<cd>& pool);
 }  // namespace qsv
 
 struct qsv_plan {

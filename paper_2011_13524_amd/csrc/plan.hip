@@ -6,12 +6,15 @@
 //  2. Merge (section 5.4, merge of two successive gates): a gate joins the
 //     block it depends on when that block is the only earlier block sharing
 //     its qubits -- so it commutes with every block created in between -- and
-//     the merged block stays within max_k qubits. Diagonal gates join diagonal
-//     blocks (the product stays diagonal); a diagonal gate joins a dense block
-//     only on a subset of its qubits, and a dense gate absorbs a diagonal block
-//     only on a subset of its own qubits, so merging never forces extra qubits
-//     to be local. Block matrices are products K_later K_earlier on the
-//     ascending union of qubits.
+//     the merged block stays within max_k qubits. Merges never raise the
+//     arithmetic per amplitude: a dense k-qubit block costs 2^k complex
+//     multiply-adds per amplitude, a diagonal block one multiply and an
+//     exchange (X or controlled X) none. So diagonal gates join diagonal
+//     blocks (the product stays diagonal); diagonal and exchange gates join a
+//     dense block only on a subset of its qubits, and a dense gate absorbs a
+//     diagonal or exchange block only on a subset of its own qubits. Block
+//     matrices are products K_later K_earlier on the ascending union of
+//     qubits.
 //  3. Passes: a pass fixes a set of L local qubits (always including the low b
 //     qubits, so that each run of 2^b amplitudes is contiguous in HBM) and
 //     greedily takes, in order, every block whose non-diagonal targets are
@@ -99,6 +102,7 @@ struct GateInfo {
   std::vector<int> targets, controls, ctrl_vals;
   std::vector<cd> mat;  // extracted matrix (MATRIX gates only)
   bool diagonal = false;
+  bool exchange = false;  // extracted matrix is Pauli X on one target
   uint64_t qubits = 0;
 };
 
@@ -127,6 +131,8 @@ GateInfo analyse(const Gate& g) {
       for (int c = 0; c < D && dg; ++c)
         if (r != c && !(m[r * D + c].re == 0.0 && m[r * D + c].im == 0.0)) dg = false;
     gi.diagonal = dg;
+    gi.exchange = tq.size() == 1 && m[0].re == 0 && m[0].im == 0 && m[1].re == 1 && m[1].im == 0 &&
+                  m[2].re == 1 && m[2].im == 0 && m[3].re == 0 && m[3].im == 0;
     gi.mat = m;
   }
   gi.qubits = qmask(gi.targets) | qmask(gi.controls);
@@ -201,6 +207,7 @@ static int build_plan(qsv_plan* p) {
   std::vector<Block>& blocks = p->blocks;
   blocks.clear();
   std::vector<uint64_t> bq;  // qubit masks of blocks
+  std::vector<char> bx;      // block is a single exchange gate
   std::vector<int> last(n, -1);
   for (size_t gi = 0; gi < C.gates.size(); ++gi) {
     const GateInfo& I = info[gi];
@@ -215,14 +222,17 @@ static int build_plan(qsv_plan* p) {
       Block& B = blocks[cand];
       const uint64_t uni = bq[cand] | I.qubits;
       const int ku = __builtin_popcountll(uni);
+      const bool cheap_b = B.diagonal || bx[cand], cheap_i = I.diagonal || I.exchange;
       bool ok = false;
       if (B.diagonal && I.diagonal) ok = ku <= 2;  // diagonal blocks stay register-friendly
-      else if (!B.diagonal && I.diagonal) ok = (I.qubits & ~bq[cand]) == 0;
-      else if (B.diagonal && !I.diagonal) ok = (bq[cand] & ~I.qubits) == 0 && ku <= std::max(p->max_k, 1);
+      else if (cheap_b && cheap_i) ok = false;     // the product would be dense: costlier
+      else if (cheap_i) ok = (I.qubits & ~bq[cand]) == 0;
+      else if (cheap_b) ok = (bq[cand] & ~I.qubits) == 0 && ku <= std::max(p->max_k, 1);
       else ok = ku <= p->max_k;
       if (ok) {
         B.gates.push_back(int(gi));
         bq[cand] = uni;
+        bx[cand] = 0;
         B.diagonal = B.diagonal && I.diagonal;
         merged = true;
         for (int q : mask_list(I.qubits)) last[q] = cand;
@@ -234,6 +244,7 @@ static int build_plan(qsv_plan* p) {
       B.diagonal = I.diagonal;
       blocks.push_back(B);
       bq.push_back(I.qubits);
+      bx.push_back(I.exchange ? 1 : 0);
       for (int q : mask_list(I.qubits)) last[q] = int(blocks.size()) - 1;
     }
   }
@@ -245,10 +256,7 @@ static int build_plan(qsv_plan* p) {
       B.targets = I.targets;
       B.controls = I.controls;
       B.ctrl_vals = I.ctrl_vals;
-      const Gate& g0 = C.gates[B.gates[0]];
-      B.xswap = g0.kind == Gate::MATRIX && I.targets.size() == 1 && I.mat.size() == 4 &&
-                I.mat[0].re == 0 && I.mat[0].im == 0 && I.mat[1].re == 1 && I.mat[1].im == 0 &&
-                I.mat[2].re == 1 && I.mat[2].im == 0 && I.mat[3].re == 0 && I.mat[3].im == 0;
+      B.xswap = I.exchange;
     } else {
       B.targets = B.qubits;
       B.controls.clear();
@@ -296,80 +304,235 @@ static int build_plan(qsv_plan* p) {
   return QSV_OK;
 }
 
-// Split a pass's ops into register-resident segments. A segment gathers
-// consecutive ops while the union of their dense targets (one- and two-qubit
-// dense ops; other ops run through LDS) fits in reg_bits register bits; the
-// first and last segments of a complex64 pass also keep local bit 0 in
-// registers so HBM traffic uses 16-byte vectors. Remaining register bits are
-// filled with the highest free local bits, leaving the low local bits to the
-// lanes (contiguous HBM runs, conflict-free LDS rows).
+// Split a pass's ops into register-resident segments.
+//
+// Scheduling: ops that commute may run in any order. Two ops commute when
+// every local qubit they share is acted on diagonally by both (a control, or a
+// diagonal target); otherwise the later op depends on the earlier one. A
+// segment fixes reg_bits register bits and takes, by list scheduling over
+// this dependency order, every ready op whose register needs (the targets of
+// one- and two-qubit dense ops; diagonal and LDS ops need none) still fit;
+// when no ready op fits, the next segment starts.
+//
+// Folding: an X gate, or an X with one local control, permutes the tile's
+// local indices by an affine map over GF(2) (x_t ^= x_c, or ^= 1). Such an op
+// moves no data: it is folded into the next re-map through LDS, whose write
+// addresses go through the composed map. Ops that depend on a folded op wait
+// for the next segment; ops that commute with it are unaffected.
+//
+// Layouts: the first segment is the layout the tile is read in and the last
+// the one it is written in, so both put the low local bits that form
+// contiguous 128-byte runs on lanes 0..2 (and, for complex64, local bit 0 in
+// registers: amplitude pairs are 16-byte vectors). A segment's wave bits
+// (thread-index bits above the 64 lanes) are chosen so that consecutive
+// segments share them where possible: a re-map between two such layouts
+// moves data only within each wavefront and needs no workgroup barrier.
 static int build_segments(qsv_plan* p, const std::vector<TileOpDev>& ho, TilePassDev& d) {
-  const int RB = p->reg_bits, L = d.L;
+  const int RB = p->reg_bits, TB = p->thread_bits, L = d.L;
+  const int NW = TB - 6;
   const bool c64 = p->dtype == QSV_C64;
+  const uint32_t full = (1u << L) - 1;
+  const uint32_t io_reg = c64 ? 1u : 0u;
+  const uint32_t io_lane = c64 ? 0xEu : 0x7u;
+  const int nops = d.op_count;
+
+  // dependency order
+  std::vector<uint32_t> need(nops), nd(nops), dg(nops);
+  for (int i = 0; i < nops; ++i) {
+    const TileOpDev& o = ho[d.op_begin + i];
+    uint32_t tg = 0;
+    for (int j = 0; j < o.k && j < 5; ++j)
+      if (o.lt[j] >= 0) tg |= 1u << o.lt[j];
+    if (o.kind == 0) {
+      nd[i] = tg;
+      dg[i] = o.lcm;
+      need[i] = o.k <= 2 ? tg : 0u;
+    } else {
+      nd[i] = 0;
+      dg[i] = tg | o.lcm;
+      need[i] = 0;
+    }
+  }
+  std::vector<std::vector<int>> preds(nops);
+  for (int j = 0; j < nops; ++j)
+    for (int i = 0; i < j; ++i)
+      if ((nd[i] & (nd[j] | dg[j])) | (dg[i] & nd[j])) preds[j].push_back(i);
+  std::vector<char> foldable(nops, 0);
+  for (int i = 0; i < nops; ++i) {
+    const TileOpDev& o = ho[d.op_begin + i];
+    foldable[i] = o.kind == 0 && o.k == 1 && o.xswap && o.gcm == 0 && __builtin_popcount(o.lcm) <= 1;
+  }
+
+  // list scheduling into segments; state 1: executed or folded into an
+  // earlier re-map, 2: folded into the re-map after the current segment
   struct Seg {
-    uint32_t regs = 0;
-    bool fixed = false;  // layout already complete (the HBM layout)
+    uint32_t regs = 0;  // register positions the ops need (+ IO constraints)
+    bool io = false;
     std::vector<int> ops;
+    std::vector<int> fold;  // ops folded into the re-map after this segment
+    uint32_t w = 0;         // wave positions
+    bool xwave = false;
   };
-  // HBM layout: the highest local bits (and bit 0 for complex64, whose pairs
-  // form 16-byte vectors) in registers, the low bits on lanes, so every load /
-  // store instruction of a wavefront covers one contiguous span.
-  uint32_t io = c64 ? 1u : 0u;
-  for (int pos = L - 1; pos >= 0 && __builtin_popcount(io) < RB; --pos) io |= 1u << pos;
-  std::vector<Seg> segs(1);
-  segs[0].regs = io;
-  segs[0].fixed = true;
-  for (int oi = d.op_begin; oi < d.op_begin + d.op_count; ++oi) {
-    const TileOpDev& o = ho[oi];
-    uint32_t need = 0;
-    if (o.kind == 0 && o.k <= 2)
-      for (int j = 0; j < o.k; ++j) need |= 1u << o.lt[j];
-    Seg& cur = segs.back();
-    const bool fits = cur.fixed ? (need & ~cur.regs) == 0 : __builtin_popcount(cur.regs | need) <= RB;
-    if (fits) {
-      cur.regs |= need;
-      cur.ops.push_back(oi);
-    } else {
-      Seg s;
-      s.regs = need;
-      s.ops.push_back(oi);
-      segs.push_back(s);
+  std::vector<Seg> segs;
+  std::vector<char> st(nops, 0);
+  int left = nops;
+  do {
+    Seg s;
+    const bool first = segs.empty();
+    s.io = first;
+    s.regs = first ? io_reg : 0u;
+    const uint32_t forbid = first ? io_lane : 0u;
+    for (bool progress = true; progress;) {
+      progress = false;
+      for (int i = 0; i < nops; ++i) {
+        if (st[i]) continue;
+        bool exec_ready = true, fold_ready = true;
+        for (int q : preds[i]) {
+          exec_ready = exec_ready && st[q] == 1;
+          fold_ready = fold_ready && st[q] != 0;
+        }
+        if (foldable[i] && fold_ready) {
+          st[i] = 2;
+          s.fold.push_back(i);
+        } else {
+          const uint32_t u = s.regs | need[i];
+          if (!exec_ready || (need[i] & forbid) || __builtin_popcount(u) > RB) continue;
+          s.regs = u;
+          s.ops.push_back(i);
+          st[i] = 1;
+        }
+        --left;
+        progress = true;
+      }
+    }
+    if (s.ops.empty() && s.fold.empty() && !first) return fail(QSV_EINVAL, "internal: segment scheduling stalled");
+    for (int i : s.fold) st[i] = 1;
+    segs.push_back(std::move(s));
+  } while (left > 0);
+  {
+    Seg& last = segs.back();
+    // ops folded after the last segment need a re-map; when it would be the
+    // only reason for one, run them as register exchanges instead
+    if (!last.fold.empty() && (last.io || ((last.regs & io_lane) == 0 &&
+                                           __builtin_popcount(last.regs | io_reg) <= RB))) {
+      uint32_t u = last.regs | io_reg;
+      for (int i : last.fold) u |= need[i] | (1u << ho[d.op_begin + i].lt[0]);
+      if ((u & io_lane) == 0 && __builtin_popcount(u) <= RB) {
+        last.regs = u;
+        for (int i : last.fold) last.ops.push_back(i);
+        last.fold.clear();
+      }
+    }
+    if (!last.io || !last.fold.empty()) {
+      if (last.fold.empty() && (last.regs & io_lane) == 0 && __builtin_popcount(last.regs | io_reg) <= RB) {
+        last.regs |= io_reg;
+        last.io = true;
+      } else {
+        Seg s;
+        s.regs = io_reg;
+        s.io = true;
+        segs.push_back(std::move(s));
+      }
     }
   }
-  // the last segment must store in the HBM layout: extend it to that layout
-  // when its register bits allow, else add an empty re-mapping segment
-  Seg& last = segs.back();
-  if (!last.fixed) {
-    if ((last.regs & ~io) == 0) {
-      last.regs = io;
-      last.fixed = true;
-    } else {
-      Seg s;
-      s.regs = io;
-      s.fixed = true;
-      segs.push_back(s);
+  // affine map of each re-map (into segment k: the folds of segment k-1):
+  // image of local basis vector p, and the constant
+  const int K = int(segs.size());
+  std::vector<std::vector<uint32_t>> mcol(K, std::vector<uint32_t>(L));
+  std::vector<uint32_t> mcst(K, 0), ftarget(K, 0);
+  for (int k = 0; k < K; ++k) {
+    for (int q = 0; q < L; ++q) mcol[k][q] = 1u << q;
+    if (k == 0) continue;
+    for (int i : segs[k - 1].fold) {
+      const TileOpDev& o = ho[d.op_begin + i];
+      const uint32_t t = 1u << o.lt[0];
+      ftarget[k] |= t;
+      // x_t ^= x_c (control value 1) or x_t ^= x_c ^ 1 (value 0); no control: x_t ^= 1
+      auto apply = [&](uint32_t y) -> uint32_t {
+        if (o.lcm == 0) return y;
+        return (y & o.lcm) ? (y ^ t) : y;
+      };
+      for (int q = 0; q < L; ++q) mcol[k][q] = apply(mcol[k][q]);
+      mcst[k] = apply(mcst[k]);
+      if (o.lcm == 0 || (o.lcv & o.lcm) == 0) mcst[k] ^= t;
     }
   }
+
+  // wave bits: maximal runs of segments sharing NW available positions;
+  // prefer positions off the low lanes (longer contiguous HBM runs)
+  // (a run continues into segment k only if no op folded into the re-map
+  // before k targets a wave bit: that re-map would move data across waves)
+  std::vector<uint32_t> avail(K);
+  for (int k = 0; k < K; ++k) avail[k] = full & ~segs[k].regs & ~(segs[k].io ? (io_lane | io_reg) : 0u);
+  for (int k = 0; k < K;) {
+    uint32_t I = avail[k];
+    int m = k + 1;
+    while (m < K && __builtin_popcount(I & avail[m] & ~ftarget[m]) >= NW) {
+      I &= avail[m] & ~ftarget[m];
+      ++m;
+    }
+    uint32_t w = 0;
+    for (int pass = 0; pass < 2 && __builtin_popcount(w) < NW; ++pass)
+      for (int pos = L - 1; pos >= 0 && __builtin_popcount(w) < NW; --pos) {
+        const bool low = pos >= 1 && pos <= 6;
+        if ((I >> pos & 1) && (pass == 1 || !low)) w |= 1u << pos;
+      }
+    if (__builtin_popcount(w) != NW) return fail(QSV_EINVAL, "internal: no wave bits");
+    for (int t = k; t < m; ++t) {
+      segs[t].w = w;
+      segs[t].xwave = (t == k && k > 0);
+    }
+    k = m;
+  }
+
   for (Seg& s : segs) {
     RegSegDev sd{};
-    for (int pos = L - 1; pos >= 0 && __builtin_popcount(s.regs) < RB; --pos) s.regs |= 1u << pos;
+    uint32_t regs = s.regs;
+    const uint32_t keep_off = s.w | (s.io ? io_lane : 0u);
+    for (int pos = L - 1; pos >= 0 && __builtin_popcount(regs) < RB; --pos)
+      if (!(keep_off >> pos & 1)) regs |= 1u << pos;
+    if (__builtin_popcount(regs) != RB) return fail(QSV_EINVAL, "internal: bad segment layout");
     int nr = 0, nt = 0;
     int regidx[32], thridx[32];
     for (int pos = 0; pos < L; ++pos) {
-      if (s.regs >> pos & 1) {
+      regidx[pos] = -1;
+      thridx[pos] = -1;
+    }
+    for (int pos = 0; pos < L; ++pos)
+      if (regs >> pos & 1) {
         regidx[pos] = nr;
         sd.reg[nr++] = pos;
-        thridx[pos] = -1;
-      } else {
+      }
+    // lanes: the IO lane positions first, then the remaining ascending; then waves
+    const uint32_t lanes = full & ~regs & ~s.w;
+    if (s.io)
+      for (int pos = 0; pos < L; ++pos)
+        if (io_lane >> pos & 1) {
+          thridx[pos] = nt;
+          sd.thr[nt++] = pos;
+        }
+    for (int pos = 0; pos < L; ++pos)
+      if ((lanes >> pos & 1) && thridx[pos] < 0) {
         thridx[pos] = nt;
         sd.thr[nt++] = pos;
-        regidx[pos] = -1;
       }
+    if (nt != 6) return fail(QSV_EINVAL, "internal: bad lane layout");
+    for (int pos = 0; pos < L; ++pos)
+      if (s.w >> pos & 1) {
+        thridx[pos] = nt;
+        sd.thr[nt++] = pos;
+      }
+    if (nr != RB || nt != TB) return fail(QSV_EINVAL, "internal: bad segment layout");
+    sd.xwave = s.xwave ? 1 : 0;
+    {
+      const int k = int(&s - segs.data());
+      for (int q = 0; q < L; ++q) sd.mcol[q] = mcol[k][q];
+      sd.mcst = mcst[k];
     }
-    if (nr != RB || nt != p->thread_bits) return fail(QSV_EINVAL, "internal: bad segment layout");
     sd.op_begin = int(p->h_rops.size());
     sd.op_count = int(s.ops.size());
-    for (int oi : s.ops) {
+    for (int li : s.ops) {
+      const int oi = d.op_begin + li;
       const TileOpDev& o = ho[oi];
       RegOpDev r{};
       r.lop = oi;
@@ -542,7 +705,7 @@ static int ensure_tables(qsv_plan* p, hipStream_t stream) {
 
 // Block matrices (or diagonals) for parameters theta, written as complex
 // doubles in block order.
-static void block_values(const qsv_plan* p, const double* theta, std::vector<cd>& pool) {
+void plan_block_values(const qsv_plan* p, const double* theta, std::vector<cd>& pool) {
   const qsv_circuit& C = p->circ_copy;
   pool.clear();
   std::vector<cd> gm, full, acc, tmp;
@@ -583,7 +746,7 @@ static int apply_fused_t(qsv_state* s, qsv_plan* p, const double* theta) {
   int trc = ensure_tables(p, s->stream);
   if (trc) return trc;
   std::vector<cd> vals;
-  block_values(p, theta, vals);
+  plan_block_values(p, theta, vals);
   const size_t bytes = vals.size() * sizeof(cx<R>);
   if (p->pool_cap < vals.size()) {
     if (p->d_pool) {
@@ -703,9 +866,11 @@ int qsv_plan_fused(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qu
   // complex64: 512-thread workgroups x 16 amplitudes (measured ~7% faster than
   // 256 x 32 at 30 qubits: twice the waves hide more latency); complex128:
   // 256 x 16 (2^3 per thread would leave too few register bits)
-  int TB = dtype == QSV_C64 ? 9 : kRegThreadBits;
+  // (blocks of 4-5 qubits run through LDS with 32-amplitude temporaries: the
+  // 512-thread kernel would spill, so such plans use 256 threads)
+  int TB = (dtype == QSV_C64 && max_k <= 3) ? 9 : kRegThreadBits;
   if (const char* e = std::getenv("QSV_TILE_THREAD_BITS")) TB = std::atoi(e) == 9 ? 9 : 8;
-  if (dtype == QSV_C128) TB = kRegThreadBits;
+  if (dtype == QSV_C128 || max_k > 3) TB = kRegThreadBits;
   const int RB = (dtype == QSV_C64 ? 13 : 12) - TB;
   p->thread_bits = TB;
   p->reg_bits = (L == RB + TB && n >= L) ? RB : 0;

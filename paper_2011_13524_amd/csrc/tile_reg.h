@@ -1,8 +1,8 @@
 // Register-resident tile pass (device code, included by plan.hip).
 //
-// The 2^L amplitudes of a tile are spread over 256 threads, 2^RB per thread in
-// VGPRs (RB = L - 8). A segment's layout says which local bits index a
-// thread's registers (reg[0..RB-1]) and which index the thread (thr[0..7]).
+// The 2^L amplitudes of a tile are spread over 2^TB threads, 2^RB per thread
+// in VGPRs (RB = L - TB). A segment's layout says which local bits index a
+// thread's registers (reg[0..RB-1]) and which index the thread (thr[0..TB-1]).
 // Ops of a segment act on register bits: a one- or two-qubit dense block is a
 // fully unrolled loop over register pairs / quads with the matrix in scalar
 // registers; diagonal blocks and controls may sit on register bits, thread
@@ -170,10 +170,23 @@ __device__ __forceinline__ void reg_dense2(const cx<R>* v, cx<R>* o, const cx<R>
   }
 }
 
+// Diagonal factor on up to two register bits (A < B; -1: absent): the factor
+// of element i is g[(bit A of i) | (bit B of i) << 1], picked at compile time.
+template <typename R, int NR, int A, int B, bool HASC>
+__device__ __forceinline__ void reg_diag(const cx<R>* v, cx<R>* o, const cx<R>* g, uint32_t cm,
+                                         uint32_t cv) {
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int idx = (A >= 0 ? (i >> A) & 1 : 0) | (B >= 0 ? ((i >> B) & 1) << 1 : 0);
+    const bool on = !HASC || (uint32_t(i) & cm) == cv;
+    o[i] = on ? g[idx] * v[i] : v[i];
+  }
+}
+
 // One flat switch over (op type, control presence, register bits): every case
 // writes every element of a fresh array, and a single copy follows. Keeping
 // the variants in one switch (rather than nested dispatchers) lets the
-// compiler keep the amplitude array in VGPRs.
+// compiler keep the amplitude array in VGPRs. Keys: reg_key().
 #define QSV_C1(SW, HC, P)                                                        \
   case ((SW) * 2 + (HC)) * 8 + (P):                                              \
     if constexpr (SW) reg_swap1<R, NR, P, HC>(v, o, m, cm, cv);                  \
@@ -191,22 +204,40 @@ __device__ __forceinline__ void reg_dense2(const cx<R>* v, cx<R>* o, const cx<R>
 #define QSV_C2P5(HC)                                                             \
   QSV_C2(HC, 0, 4) QSV_C2(HC, 1, 4) QSV_C2(HC, 2, 4) QSV_C2(HC, 3, 4) QSV_C2(HC, 4, 0) \
   QSV_C2(HC, 4, 1) QSV_C2(HC, 4, 2) QSV_C2(HC, 4, 3)
+#define QSV_CD(HC, A, B)                                                         \
+  case 160 + (HC) * 64 + ((A) + 1) * 8 + ((B) + 1):                              \
+    reg_diag<R, NR, A, B, HC>(v, o, g, cm, cv);                                  \
+    break;
+#define QSV_CDP4(HC)                                                             \
+  QSV_CD(HC, -1, -1) QSV_CD(HC, 0, -1) QSV_CD(HC, 1, -1) QSV_CD(HC, 2, -1)         \
+  QSV_CD(HC, 3, -1) QSV_CD(HC, 0, 1) QSV_CD(HC, 0, 2) QSV_CD(HC, 0, 3)             \
+  QSV_CD(HC, 1, 2) QSV_CD(HC, 1, 3) QSV_CD(HC, 2, 3)
+#define QSV_CDP5(HC)                                                             \
+  QSV_CD(HC, 4, -1) QSV_CD(HC, 0, 4) QSV_CD(HC, 1, 4) QSV_CD(HC, 2, 4) QSV_CD(HC, 3, 4)
 
-// kind 0 dense one-qubit, 1 dense two-qubit, 4 Pauli-X exchange.
+// kind 0 dense one-qubit, 1 dense two-qubit, 2 diagonal, 4 Pauli-X exchange;
+// a, b: register bits (diagonal: -1 when absent, a < b)
+__device__ __forceinline__ int reg_key(int kind, int a, int b, bool hc) {
+  const int h = hc ? 1 : 0;
+  if (kind == 1) return 32 + h * 64 + a * 8 + b;
+  if (kind == 2) return 160 + h * 64 + (a + 1) * 8 + (b + 1);
+  return ((kind == 4) * 2 + h) * 8 + a;
+}
+
 template <typename R, int NR>
-__device__ __forceinline__ void reg_apply(cx<R>* v, int kind, int a, int b, const cx<R>* m,
+__device__ __forceinline__ void reg_apply(cx<R>* v, int key, const cx<R>* m, const cx<R>* g,
                                           uint32_t cm, uint32_t cv) {
-  const int hc = cm != 0;
-  const int key = kind == 1 ? 32 + hc * 64 + a * 8 + b : ((kind == 4) * 2 + hc) * 8 + a;
   cx<R> o[NR];
   switch (key) {
     QSV_C1P(0, 0) QSV_C1P(0, 1) QSV_C1P(1, 0) QSV_C1P(1, 1)
     QSV_C2P4(0) QSV_C2P4(1)
+    QSV_CDP4(0) QSV_CDP4(1)
     default:
       if constexpr (NR > 16) {
         switch (key) {
           QSV_C1(0, 0, 4) QSV_C1(0, 1, 4) QSV_C1(1, 0, 4) QSV_C1(1, 1, 4)
           QSV_C2P5(0) QSV_C2P5(1)
+          QSV_CDP5(0) QSV_CDP5(1)
           default:
 #pragma unroll
             for (int i = 0; i < NR; ++i) o[i] = v[i];
@@ -226,53 +257,101 @@ __device__ __forceinline__ void reg_apply(cx<R>* v, int kind, int a, int b, cons
 #undef QSV_C2
 #undef QSV_C2P4
 #undef QSV_C2P5
+#undef QSV_CD
+#undef QSV_CDP4
+#undef QSV_CDP5
 
-// Diagonal block (k <= 2): amplitude factor d[idx], idx bit j from target j.
-// The factor of register element i is selected from (at most) four values with
-// a runtime bit test, never by indexing the register array.
-template <typename R, int NR>
-__device__ __forceinline__ void reg_diag(cx<R>* v, const RegOpDev& op, const cx<R>* __restrict__ d,
-                                         uint32_t tau, uint64_t base) {
-  int fixed = 0;  // index bits from thread and non-local targets
-  int rb0 = 31, rb1 = 31;  // register bits of targets 0 and 1 (31: not a register bit)
+// Factor table of a diagonal op (k <= 2) for this thread: index bits from
+// thread and non-local targets are fixed; register targets become the bits
+// a < b of the table index.
+template <typename R>
+__device__ __forceinline__ void diag_table(const RegOpDev& op, const cx<R>* __restrict__ d, uint32_t tau,
+                                           uint64_t base, cx<R>* g, int& a, int& b) {
+  int fixed = 0, ja = 0, jb = 0;
+  a = -1;
+  b = -1;
   for (int j = 0; j < op.k; ++j) {
     if (op.dsrc[j] == 1) fixed |= int((tau >> op.dbit[j]) & 1) << j;
     else if (op.dsrc[j] == 2) fixed |= int((base >> op.dbit[j]) & 1) << j;
-    else if (j == 0) rb0 = op.dbit[j];
-    else rb1 = op.dbit[j];
+    else if (a < 0) {
+      a = op.dbit[j];
+      ja = j;
+    } else {
+      b = op.dbit[j];
+      jb = j;
+    }
   }
-  const int nd = 1 << op.k;
-  cx<R> dv[4];
+  if (b >= 0 && b < a) {
+    const int t = a, tj = ja;
+    a = b;
+    ja = jb;
+    b = t;
+    jb = tj;
+  }
 #pragma unroll
-  for (int e = 0; e < 4; ++e) dv[e] = d[e < nd ? (e | fixed) : 0];
-  const uint32_t cm = op.ri_cm, cv = op.ri_cv;
-#pragma unroll
-  for (int i = 0; i < NR; ++i) {
-    const int b0 = (i >> rb0) & 1, b1 = (i >> rb1) & 1;
-    const cx<R> lo = b0 ? dv[1] : dv[0], hi = b0 ? dv[3] : dv[2];
-    const cx<R> f = b1 ? hi : lo;
-    const cx<R> r = f * v[i];
-    if ((uint32_t(i) & cm) == cv) v[i] = r;
+  for (int e = 0; e < 4; ++e) {
+    int idx = fixed;
+    if (a >= 0 && (e & 1)) idx |= 1 << ja;
+    if (b >= 0 && (e & 2)) idx |= 1 << jb;
+    g[e] = d[idx];
   }
 }
 
-// Local index of register element i / of this thread under a segment layout.
-template <int RB>
-__device__ __forceinline__ uint32_t lreg(const RegSegDev& s, int i) {
-  uint32_t j = 0;
-#pragma unroll
-  for (int b = 0; b < RB; ++b)
-    if ((i >> b) & 1) j |= 1u << s.reg[b];
-  return j;
+// Orders this wavefront's LDS accesses (a compiler barrier: the hardware
+// performs one wavefront's LDS operations in issue order).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int TB>
-__device__ __forceinline__ uint32_t lthr(const RegSegDev& s, uint32_t tau) {
-  uint32_t j = 0;
+// LDS addresses of a layout. The swizzle is linear over XOR and a local index
+// is the XOR of its register part and its thread part, so the byte offset of
+// element i is the per-thread part XOR a part that depends only on i and the
+// layout (uniform across the workgroup: scalar registers). The tile is the
+// kernel's only LDS block, so it starts at LDS address 0 and the base folds
+// into the per-thread part: one vector XOR per element remains.
+template <typename R, int RB, int TB, typename SW>
+struct LdsMap {
+  uint32_t thr;       // swizzled thread part, in bytes
+  uint32_t reg[1 << RB];  // swizzled register part of element i, in bytes
+  // layout s; with map m, local index x is placed at m->mcol-image of x ^ m->mcst
+  __device__ __forceinline__ LdsMap(const RegSegDev& s, uint32_t tau, SW sw, const RegSegDev* m) {
+    uint32_t j = m ? m->mcst : 0u;
 #pragma unroll
-  for (int b = 0; b < TB; ++b) j |= ((tau >> b) & 1) << s.thr[b];
-  return j;
-}
+    for (int b = 0; b < TB; ++b)
+      if ((tau >> b) & 1) j ^= m ? m->mcol[s.thr[b]] : (1u << s.thr[b]);
+    thr = sw(j) * uint32_t(sizeof(cx<R>));
+    uint32_t basis[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+      basis[b] = sw(m ? m->mcol[s.reg[b]] : (1u << s.reg[b])) * uint32_t(sizeof(cx<R>));
+#pragma unroll
+    for (int i = 0; i < (1 << RB); ++i) {
+      uint32_t r = 0;
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+        if ((i >> b) & 1) r ^= basis[b];
+      reg[i] = r;
+    }
+  }
+  typedef R R2 __attribute__((ext_vector_type(2)));
+  typedef __attribute__((address_space(3))) R2 lds_r2;
+  __device__ __forceinline__ lds_r2* at(char* lds, int i) const {
+    const uint32_t base = uint32_t(reinterpret_cast<uintptr_t>(lds));
+    return reinterpret_cast<lds_r2*>(uintptr_t((base + thr) ^ reg[i]));
+  }
+  __device__ __forceinline__ void put(char* lds, int i, const cx<R>& x) const {
+    R2 w;
+    w.x = x.re;
+    w.y = x.im;
+    *at(lds, i) = w;
+  }
+  __device__ __forceinline__ cx<R> get(char* lds, int i) const {
+    const R2 w = *at(lds, i);
+    return {w.x, w.y};
+  }
+};
 
 template <typename R, int RB, int KMAX, int TB>
 __global__ void __launch_bounds__(1 << TB)
@@ -325,15 +404,25 @@ __global__ void __launch_bounds__(1 << TB)
   for (int sgi = 0; sgi < P.seg_count; ++sgi) {
     const RegSegDev* Sn = &segs[P.seg_begin + sgi];
     if (sgi > 0) {
-      // re-map through LDS
-      const uint32_t to = lthr<TB>(*S, tau);
+      // re-map through LDS, applying the ops folded into it on the way; when
+      // both layouts share the wave bits (and no folded op targets one), every
+      // wavefront reads back only what it wrote, and LDS operations of one
+      // wavefront complete in order: no workgroup barrier is needed
+      const bool xw = Sn->xwave != 0;
+      {
+        const LdsMap<R, RB, TB, Swz<SB>> mo(*S, tau, sw, Sn);
 #pragma unroll
-      for (int i = 0; i < NR; ++i) t[sw(lreg<RB>(*S, i) | to)] = v[i];
-      __syncthreads();
-      const uint32_t tn = lthr<TB>(*Sn, tau);
+        for (int i = 0; i < NR; ++i) mo.put(smem, i, v[i]);
+      }
+      if (xw) __syncthreads();
+      else wave_sync();
+      {
+        const LdsMap<R, RB, TB, Swz<SB>> mn(*Sn, tau, sw, nullptr);
 #pragma unroll
-      for (int i = 0; i < NR; ++i) v[i] = t[sw(lreg<RB>(*Sn, i) | tn)];
-      __syncthreads();
+        for (int i = 0; i < NR; ++i) v[i] = mn.get(smem, i);
+      }
+      if (xw) __syncthreads();
+      else wave_sync();
     }
     S = Sn;
     for (int o = 0; o < S->op_count; ++o) {
@@ -341,20 +430,22 @@ __global__ void __launch_bounds__(1 << TB)
       if ((base & op.gcm) != op.gcv) continue;  // non-local controls: uniform per tile
       const cx<R>* m = pool + op.moff;
       if (op.kind == 3) {
-        const uint32_t to = lthr<TB>(*S, tau);
+        const LdsMap<R, RB, TB, Swz<SB>> ms(*S, tau, sw, nullptr);
 #pragma unroll
-        for (int i = 0; i < NR; ++i) t[sw(lreg<RB>(*S, i) | to)] = v[i];
+        for (int i = 0; i < NR; ++i) ms.put(smem, i, v[i]);
         __syncthreads();
         lds_op<R, KMAX>(t, lops[op.lop], pool, L, base, sw);
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < NR; ++i) v[i] = t[sw(lreg<RB>(*S, i) | to)];
+        for (int i = 0; i < NR; ++i) v[i] = ms.get(smem, i);
         __syncthreads();
         continue;
       }
       if ((tau & op.ti_cm) != op.ti_cv) continue;  // controls on thread bits
-      if (op.kind == 2) reg_diag<R, NR>(v, op, m, tau, base);
-      else reg_apply<R, NR>(v, op.kind, op.p1, op.p2, m, op.ri_cm, op.ri_cv);
+      cx<R> g[4];
+      int a = op.p1, bb = op.p2;
+      if (op.kind == 2) diag_table<R>(op, m, tau, base, g, a, bb);
+      reg_apply<R, NR>(v, reg_key(op.kind, a, bb, op.ri_cm != 0), m, g, op.ri_cm, op.ri_cv);
     }
   }
 

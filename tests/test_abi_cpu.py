@@ -121,13 +121,41 @@ def test_planner_on_host():
     c = Q.Circuit.from_records(n, gates)
     info = Q.Plan(c, "c64", max_k=2).info()
     assert info["gates"] == 890
-    assert info["blocks"] == 320  # RX/RZ pairs merged with the ladder CNOT into 2-qubit blocks
+    # RX/RZ pairs merged per qubit (300 one-qubit blocks); the 290 ladder CNOTs
+    # stay exchanges: a two-qubit dense block would cost more arithmetic
+    assert info["blocks"] == 590
     assert info["passes"] <= 40
     small = Q.Circuit.from_records(10, W.layered_rx_rz_cnot(10, 10, seed_key=(0,)))
     assert Q.Plan(small, "c128", max_k=2).info()["passes"] == 1
     assert _code(Q.Plan, c, "c64", 0) == EINVAL
     assert _code(Q.Plan, c, "c128", 2, 14) == EINVAL
     assert _code(Q.Plan, c, "c64", 5, 8, 6) == EINVAL
+
+
+def test_merge_never_raises_arithmetic():
+    rng = np.random.default_rng(3)
+    u1 = W.haar_unitary(rng, 2)
+    u2 = W.haar_unitary(rng, 4)
+
+    def blocks(recs, k=2):
+        return Q.Plan(Q.Circuit.from_records(3, recs), "c128", max_k=k).info()["blocks"]
+
+    U = {"op": "dense", "q": [0], "mat": u1}
+    U1 = {"op": "dense", "q": [1], "mat": u1}
+    U01 = {"op": "dense", "q": [0, 1], "mat": u2}
+    cx = {"op": "cnot", "q": [0, 1]}
+    cz = {"op": "cz", "q": [0, 1]}
+    assert blocks([U, cx]) == 2          # an exchange never widens a dense block
+    assert blocks([U01, cx]) == 1        # ... but is absorbed by one covering it
+    assert blocks([cx, U01]) == 1        # a dense gate absorbs an exchange it covers
+    assert blocks([cx, U]) == 2
+    assert blocks([cz, cx]) == 2         # diagonal x exchange would be dense
+    assert blocks([cx, cx]) == 2
+    assert blocks([cz, {"op": "rz", "q": [1], "slot": 0}]) == 1  # diagonal products stay diagonal
+    assert blocks([{"op": "rz", "q": [0], "slot": 0}, {"op": "rx", "q": [0], "slot": 1}]) == 1
+    assert blocks([U, U1]) == 2          # no shared qubit: independent blocks
+    assert blocks([U, U01]) == 1
+    assert blocks([U, U01], k=1) == 2
 
 
 def test_batch_validation():

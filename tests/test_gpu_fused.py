@@ -71,12 +71,17 @@ def test_mixed_gates(dt, kw):
         assert err <= AMP_TOL[dt], (err, info)
 
 
-@pytest.mark.parametrize("dt", ["c128", "c64"])
+# complex64 tiles run as 512 threads x 16 amplitudes (default) or 256 x 32
+WG = [("c128", "8"), ("c64", "9"), ("c64", "8")]
+
+
+@pytest.mark.parametrize("dt,tb", WG)
 @pytest.mark.parametrize("max_k", [1, 2, 3])
-def test_register_resident_tiles(dt, max_k):
+def test_register_resident_tiles(dt, tb, max_k, monkeypatch):
     # default tiles (13 local qubits for complex64, 12 for complex128) run
     # register-resident once the state is at least one tile; max_k=3 also
     # exercises blocks applied through LDS inside a register-resident pass
+    monkeypatch.setenv("QSV_TILE_THREAD_BITS", tb)
     for n, seed in ((13, 3), (14, 4), (16, 5)):
         gates = mixed_circuit(n, 220, seed)
         got, info = fused_state(n, gates, dt, max_k=max_k)
@@ -85,8 +90,9 @@ def test_register_resident_tiles(dt, max_k):
         assert err <= AMP_TOL[dt], (n, err, info)
 
 
-@pytest.mark.parametrize("dt", ["c128", "c64"])
-def test_register_resident_layered_and_random(dt):
+@pytest.mark.parametrize("dt,tb", WG)
+def test_register_resident_layered_and_random(dt, tb, monkeypatch):
+    monkeypatch.setenv("QSV_TILE_THREAD_BITS", tb)
     n = 16
     for gates in (W.layered_rx_rz_cnot(n, 10, seed_key=(2, n)), W.random_u_cz(n, 20, seed_key=(1, n))):
         for max_k in (1, 2):
