@@ -21,6 +21,8 @@ Extra legs (same JSON line):
   batch_vqe     512 hardware-efficient-ansatz items of 12..18 qubits: one
                 persistent launch vs one adjoint call per item
   random_26q    26-qubit Haar-1q + random-CZ circuit, fused vs unfused
+  adjoint_32q   32-qubit complex64 forward + adjoint pass (1920 gates, 1280
+                parameters), one gradient component checked by the shift rule
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode fused|unfused]
                        [--quick] [--no-cpu]
@@ -161,6 +163,50 @@ def adjoint_leg(Q, W, fd_params):
                        float(np.max(np.abs(g[slots] - np.array(fd))) / scale),
                    "energy": e}
     return out
+
+
+def adjoint32_leg(Q, W):
+    """32-qubit complex64 forward circuit and adjoint pass: psi, lambda and a
+    third state (for a sampled shift-rule check) resident in HBM."""
+    n = 32
+    gates, npar = W.ry_rz_cnot_ring(n, 20)
+    theta = W.uniform_angles(npar, (4, 2))
+    obs_t = W.random_pauli_observable(n, 500, (1, 6), seed_key=(4, 3))
+    circ = Q.Circuit.from_records(n, gates)
+    obs = Q.Observable(n, obs_t)
+    dt = "c64"
+    plan = Q.Plan(circ, dt, max_k=2)
+    psi, lam = Q.State(n, dt), Q.State(n, dt)
+    t0 = time.perf_counter()
+    psi.set_basis(0)
+    Q.apply_fused(psi, plan, theta)
+    sync(Q, psi)
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    e, g = Q.adjoint_gradient(circ, theta, obs, psi, lam, plan)
+    t_adj = time.perf_counter() - t0
+    s = Q.State(n, dt)
+
+    def energy(th):
+        s.set_basis(0)
+        Q.apply_fused(s, plan, th)
+        return Q.expectation(s, obs)
+
+    slot = npar // 2
+    tp, tm = theta.copy(), theta.copy()
+    tp[slot] += np.pi / 2
+    tm[slot] -= np.pi / 2
+    shift = 0.5 * (energy(tp) - energy(tm))
+    scale = sum(abs(c) for c, _ in obs_t)
+    del s, psi, lam
+    return {"workload": f"32 qubits complex64, 20 layers RY/RZ + CNOT ring ({len(gates)} gates, "
+                        f"{npar} parameters), 500 random Pauli strings of weight 1..6; psi, lambda "
+                        "and a check state (3 x 34.4 GB) in HBM",
+            "forward_s": t_fwd, "forward_gates_per_s": len(gates) / t_fwd,
+            "adjoint_s": t_adj, "grads_per_s": npar / t_adj, "energy": e,
+            "shift_rule_check_slot": slot,
+            "abs_adjoint_minus_shift_over_sum_abs_alpha": abs(g[slot] - shift) / scale,
+            "passes": plan.info()["passes"]}
 
 
 def batch_leg(Q, W, count):
@@ -336,6 +382,7 @@ def main():
         out["adjoint_24q"] = adjoint_leg(Q, W, args.fd_params)
         out["batch_vqe"] = batch_leg(Q, W, args.batch_items)
         out["random_26q"] = random_leg(Q, W)
+        out["adjoint_32q"] = adjoint32_leg(Q, W)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, gates, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -236,8 +236,10 @@ int qsv_observable_info(const qsv_observable* o, int* n, int* terms, int* groups
 int qsv_expectation(const qsv_state* s, const qsv_observable* o, double* out);
 
 /* out <- O in (out must be a different state of the same n and dtype): the
- * Pauli-string sum applied to a state, every flip mask in one kernel that reads
- * in[y ^ F] for each mask F and writes out once. */
+ * Pauli-string sum of section 4.5 applied to a state. Flip masks are packed
+ * into tile passes as for qsv_expectation; each pass reads `in` once and adds
+ * its masks' contributions to `out` (the first pass writes it). Asynchronous
+ * on in's stream (out's stream is synchronised first if it differs). */
 int qsv_apply_observable(const qsv_state* in, const qsv_observable* o, qsv_state* out);
 
 /* ---------------------------------------------------------------- gradients */

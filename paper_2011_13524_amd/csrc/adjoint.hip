@@ -12,8 +12,8 @@
 //
 // One fused kernel per parametric rotation reads psi and lambda once, adds its
 // share of -Im<lambda|P|psi> in FP64 and writes both uncomputed states
-// (4 * 2^n amplitudes of traffic). lambda = H psi is one kernel that gathers
-// psi[y ^ F] for every flip mask F of the observable and writes lambda once.
+// (4 * 2^n amplitudes of traffic). lambda = H psi runs in tile passes that
+// pack the observable's flip masks, like the expectation.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -28,8 +28,6 @@ namespace qsv {
 
 constexpr int kAdjThreads = 256;
 constexpr int kAdjBlocks = 1024;
-constexpr int kObsLdsTerms = 1024;
-constexpr int kObsLdsGroups = 512;
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
 #pragma unroll
@@ -41,43 +39,6 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   if (threadIdx.x == 0)
     for (int i = 0; i < int(blockDim.x >> 6); ++i) r += sh[i];
   return r;
-}
-
-struct GroupDev {
-  uint64_t flip;
-  int begin, count;
-};
-
-// lambda[y] = sum_groups sum_k alpha_k i^nY_k (-1)^|x & z_k| psi[x], x = y ^ F.
-template <typename R>
-__global__ void __launch_bounds__(kAdjThreads)
-    k_apply_obs(const R* __restrict__ psi, R* __restrict__ lam, uint64_t N,
-                const GroupDev* __restrict__ groups, int ngroups, const GTerm* __restrict__ terms,
-                int nterms) {
-  __shared__ GTerm st[kObsLdsTerms];
-  __shared__ GroupDev sg[kObsLdsGroups];
-  for (int i = threadIdx.x; i < min(nterms, kObsLdsTerms); i += blockDim.x) st[i] = terms[i];
-  for (int i = threadIdx.x; i < min(ngroups, kObsLdsGroups); i += blockDim.x) sg[i] = groups[i];
-  __syncthreads();
-  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  for (uint64_t y = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; y < N; y += stride) {
-    double ar = 0.0, ai = 0.0;
-    for (int g = 0; g < ngroups; ++g) {
-      const GroupDev G = g < kObsLdsGroups ? sg[g] : groups[g];
-      const uint64_t x = y ^ G.flip;
-      const cx<R> v = load1(psi, x);
-      double cr = 0.0, ci = 0.0;
-      for (int k = G.begin; k < G.begin + G.count; ++k) {
-        const GTerm t = k < kObsLdsTerms ? st[k] : terms[k];
-        const bool neg = __popcll(x & t.z) & 1;
-        cr += neg ? -t.re : t.re;
-        ci += neg ? -t.im : t.im;
-      }
-      ar += cr * double(v.re) - ci * double(v.im);
-      ai += cr * double(v.im) + ci * double(v.re);
-    }
-    store1(lam, y, cx<R>{R(ar), R(ai)});
-  }
 }
 
 // Fused adjoint step of a one-qubit rotation exp(i t P/2) on qubit q:
@@ -129,6 +90,7 @@ __global__ void __launch_bounds__(kAdjThreads)
 }
 
 int expectation_impl(qsv_state* s, const qsv_observable* o, double* out);
+int apply_observable_tiled(const qsv_state* in, const qsv_observable* o, qsv_state* out);
 int circuit_apply_unfused(qsv_state* s, const qsv_circuit* c, const double* theta);
 template <typename R>
 int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state* psi, qsv_state* lam,
@@ -141,41 +103,8 @@ int adj_blocks(uint64_t work) {
   return int(std::max<uint64_t>(1, std::min<uint64_t>(b, kAdjBlocks)));
 }
 
-template <typename R>
-int apply_obs_t(const qsv_state* in, const qsv_observable* o, qsv_state* out, qsv_state* scratch) {
-  std::vector<Group> groups;
-  std::vector<GTerm> terms;
-  build_groups(o, groups, terms);
-  const uint64_t N = dim(in->n);
-  std::vector<GroupDev> gd(groups.size());
-  for (size_t i = 0; i < groups.size(); ++i) gd[i] = {groups[i].flip, groups[i].begin, groups[i].count};
-  const size_t gbytes = gd.size() * sizeof(GroupDev), tbytes = terms.size() * sizeof(GTerm);
-  int rc = ensure_reduce_scratch(scratch, (gbytes + tbytes) / 8 + 2);
-  if (rc) return rc;
-  char* base = reinterpret_cast<char*>(scratch->red);
-  if (gbytes)
-    QSV_HIP_CHECK(hipMemcpyAsync(base, gd.data(), gbytes, hipMemcpyHostToDevice, scratch->stream));
-  if (tbytes)
-    QSV_HIP_CHECK(hipMemcpyAsync(base + gbytes, terms.data(), tbytes, hipMemcpyHostToDevice,
-                                 scratch->stream));
-  const uint64_t blocks = std::min<uint64_t>((N + kAdjThreads - 1) / kAdjThreads, 8192);
-  {
-    ProfScope ps("apply_obs", double(sizeof(cx<R>)) * double(N) * (double(groups.size()) + 1.0),
-                 scratch->stream);
-    hipLaunchKernelGGL((k_apply_obs<R>), dim3(unsigned(blocks)), dim3(kAdjThreads), 0,
-                       scratch->stream, static_cast<const R*>(in->ptr), static_cast<R*>(out->ptr), N,
-                       reinterpret_cast<const GroupDev*>(base), int(groups.size()),
-                       reinterpret_cast<const GTerm*>(base + gbytes), int(terms.size()));
-  }
-  QSV_HIP_CHECK(hipGetLastError());
-  // the term tables live in scratch memory that later calls reuse
-  QSV_HIP_CHECK(hipStreamSynchronize(scratch->stream));
-  return QSV_OK;
-}
-
 int apply_obs(const qsv_state* in, const qsv_observable* o, qsv_state* out) {
-  return in->dtype == QSV_C64 ? apply_obs_t<float>(in, o, out, out)
-                              : apply_obs_t<double>(in, o, out, out);
+  return apply_observable_tiled(in, o, out);
 }
 
 void dagger(std::vector<cd>& m) {

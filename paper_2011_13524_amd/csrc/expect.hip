@@ -7,11 +7,13 @@
 // low b ones, for contiguous HBM runs) and greedily packs the flip masks that
 // need the fewest extra local qubits until the set is full. Each pass reads the
 // state once into LDS, tile by tile, and evaluates every group of the pass on
-// it; a tile's contribution accumulates in FP64 into one partial per tile
-// (passes run in order on one stream, so each partial has a single writer in a
-// fixed order), and one final fixed-order reduction gives the value. Compared
-// with one pass per flip mask, HBM traffic drops by the number of masks per
-// pass. Z/Y signs on non-local qubits are constants per tile.
+// it. Workgroups are persistent and prefetch their next tile while computing
+// on the current one; each sums its tiles in a fixed order into one FP64
+// partial (passes run in order on one stream, so each partial has a single
+// writer in a fixed order), and one final fixed-order reduction gives the
+// value: bitwise reproducible. Compared with one pass per flip mask, HBM
+// traffic drops by the number of masks per pass. Z/Y signs on non-local qubits
+// are constants per tile. The same passes give lambda = O psi (adjoint).
 #include <algorithm>
 #include <cstdlib>
 
@@ -23,6 +25,11 @@
 namespace qsv {
 
 constexpr int kExpThreads = 512;
+// loads per thread for a whole tile: 2^12 complex64 (16-byte pairs) or 2^11
+// complex128 amplitudes over 512 threads
+constexpr int kExpTileMax = 4096;  // largest tile: 2^12 amplitudes
+constexpr int kExpThreadsE = 256;  // expectation workgroups (more work per wave: the
+                                   // per-group setup is scalar and repeats per wave)
 constexpr int kExpMaxHigh = 16;
 constexpr int kExpMaxGlobal = 40;
 
@@ -52,7 +59,9 @@ struct ExpTermLds {
   double re, im;
   uint32_t zl;
 };
-constexpr int kExpLdsTerms = 256;
+constexpr int kExpLdsTerms = 128;
+// persistent workgroups per observable pass: 4 per compute unit
+constexpr int kExpGrid = 1024;
 
 struct ExpPlan {
   int n = 0, L = 0, b = 0;
@@ -79,153 +88,388 @@ __device__ __forceinline__ uint64_t exp_place(const ExpPassDev& P, uint32_t j) {
   return x;
 }
 
+__device__ __forceinline__ uint64_t exp_tile_base(const ExpPassDev& P, uint64_t g) {
+  uint64_t base = 0;
+  for (int j = 0; j < P.ng; ++j) base |= ((g >> j) & 1) << P.gpos[j];
+  return base;
+}
+
+// -v when s is 1, v when 0 (one XOR into the sign bit).
+__device__ __forceinline__ double flip_sign(double v, uint32_t s) {
+  return __hiloint2double(__double2hiint(v) ^ int(s << 31), __double2loint(v));
+}
+
 __device__ __forceinline__ uint32_t ins0(uint32_t i, int hb) {
   return ((i >> hb) << (hb + 1)) | (i & ((1u << hb) - 1));
 }
 
-// One tile of one pass: the tile is read into LDS once, then every flip-mask
-// group of the pass is evaluated on it. Pair products conj(psi_y) psi_x and
-// the thread's few partial sums use the amplitude precision; every sum over
-// threads, tiles and passes is FP64.
-template <typename R>
-__global__ void __launch_bounds__(kExpThreads)
-    k_expect_tile(const R* __restrict__ psi, const ExpPassDev* __restrict__ passes, int pass_idx,
-                  const ExpGroupDev* __restrict__ groups, const ExpTermDev* __restrict__ terms,
-                  double* __restrict__ partial, int accumulate) {
-  extern __shared__ __align__(16) char smem[];
-  __shared__ double red[kExpThreads / 64];
-  __shared__ ExpTermLds et[kExpLdsTerms];
-  cx<R>* t = reinterpret_cast<cx<R>*>(smem);
-  const ExpPassDev& P = passes[pass_idx];
-  const int L = P.L;
-  const uint64_t g = blockIdx.x;
-  uint64_t base = 0;
-  for (int j = 0; j < P.ng; ++j) base |= ((g >> j) & 1) << P.gpos[j];
-  constexpr int V = sizeof(R) == 4 ? 2 : 1;
-  const uint32_t TS = 1u << L;
-  const uint32_t tid = threadIdx.x;
-  {
-    const uint64_t xt = base | exp_place(P, tid * V);
-    for (uint32_t e0 = 0; e0 < TS / V; e0 += kExpThreads) {
-      if (e0 + tid >= TS / V) break;
-      const uint64_t x = xt | exp_place(P, e0 * V);
-      AmpIO<R, V>::load(psi, x, &t[(e0 + tid) * V]);
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uni(double v) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
+__device__ __forceinline__ uint64_t uni(uint64_t v) {
+  return (uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(v >> 32))) << 32) |
+         __builtin_amdgcn_readfirstlane(uint32_t(v));
+}
+
+// Streaming of tiles through registers into LDS. Workgroups are persistent:
+// workgroup b takes tiles b, b + grid, b + 2 grid, ... in that order (so its
+// partial sums have a fixed order), and the loads of its next tile are issued
+// before it computes on the current one.
+template <typename R, int NT>
+struct ExpTileStream {
+  static constexpr int V = sizeof(R) == 4 ? 2 : 1;
+  static constexpr int NL = kExpTileMax / 2 / NT;  // at most 2048 loads (16-byte pairs or complex128)
+  uint64_t xt;          // per-thread part of the element addresses
+  uint64_t xk[NL];      // workgroup-uniform parts
+  cx<R> buf[NL * V];
+  uint32_t TS;
+  __device__ __forceinline__ ExpTileStream(const ExpPassDev& P) {
+    TS = 1u << P.L;
+    xt = exp_place(P, threadIdx.x * V);
+#pragma unroll
+    for (int k = 0; k < NL; ++k) xk[k] = exp_place(P, uint32_t(k) * NT * V);
+  }
+  __device__ __forceinline__ void fetch(const R* __restrict__ psi, uint64_t base) {
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const uint32_t e = threadIdx.x + uint32_t(k) * NT;
+      if (e < TS / V) AmpIO<R, V>::load(psi, base | xt | xk[k], &buf[k * V]);
     }
   }
-  double acc = 0.0;
-  for (int gi = 0; gi < P.grp_count; ++gi) {
-    const ExpGroupDev G = groups[P.grp_begin + gi];
-    const int nt = G.term_count;
-    if (gi == 0) __syncthreads();  // tile loaded
-    if (nt > 1) {
-      // stage the group's terms with their sign on non-local qubits folded in
-      // (a constant for this tile)
-      __syncthreads();
-      const int ns = min(nt, kExpLdsTerms);
-      for (int k = tid; k < ns; k += blockDim.x) {
-        const ExpTermDev T = terms[G.term_begin + k];
-        const bool gneg = __popcll(base & T.zg) & 1;
-        et[k] = {gneg ? -T.re : T.re, gneg ? -T.im : T.im, T.zl};
-      }
-      __syncthreads();
+  __device__ __forceinline__ void to_lds(cx<R>* t) const {
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const uint32_t e = threadIdx.x + uint32_t(k) * NT;
+      if (e < TS / V)
+#pragma unroll
+        for (int v = 0; v < V; ++v) t[e * V + v] = buf[k * V + v];
     }
-    if (G.lf == 0 && nt == 1) {
-      // sum of +-|psi_x|^2: thread part of the sign once, uniform part per step
-      const ExpTermDev T = terms[G.term_begin];
-      const double re = (__popcll(base & T.zg) & 1) ? -T.re : T.re;
-      const uint32_t pt = __popc(tid & T.zl) & 1;
-      R sum = R(0);
-      for (uint32_t j0 = 0; j0 < TS; j0 += kExpThreads) {
-        if (j0 + tid >= TS) break;
-        const cx<R> a = t[j0 + tid];
-        const R p = a.re * a.re + a.im * a.im;
-        sum += (pt ^ (__popc(j0 & T.zl) & 1)) ? -p : p;
+  }
+};
+
+// Tiles of a workgroup: a contiguous range of tile indices (fixed order); the
+// base of the next tile is the current one incremented within the mask of
+// non-local qubits (a carry that skips local bit positions).
+struct ExpTileRange {
+  uint64_t g, end, base, gmask;
+  __device__ __forceinline__ ExpTileRange(const ExpPassDev& P, uint64_t ntiles) {
+    const uint64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    g = uint64_t(blockIdx.x) * per;
+    end = g + per < ntiles ? g + per : ntiles;
+    gmask = 0;
+    for (int j = 0; j < P.ng; ++j) gmask |= uint64_t(1) << P.gpos[j];
+    base = g < end ? exp_tile_base(P, g) : 0;
+  }
+  __device__ __forceinline__ uint64_t next_base() const { return ((base | ~gmask) + 1) & gmask; }
+};
+
+// Group descriptors of a pass with the first term of each group, staged in
+// LDS once per workgroup; the sign of a term on non-local qubits (zg) is
+// applied per tile.
+constexpr int kExpPreGroups = 64;
+struct ExpGroupLds {
+  double re, im;  // first term's coefficient
+  uint64_t zg;
+  uint32_t lf, zl;
+  int hbit, term_begin, term_count;
+};
+
+__device__ __forceinline__ void exp_stage_groups(const ExpPassDev& P, const ExpGroupDev* __restrict__ groups,
+                                                 const ExpTermDev* __restrict__ terms, ExpGroupLds* sg) {
+  const int ng = min(P.grp_count, kExpPreGroups);
+  for (int i = threadIdx.x; i < ng; i += blockDim.x) {
+    const ExpGroupDev G = groups[P.grp_begin + i];
+    const ExpTermDev T = terms[G.term_begin];
+    sg[i] = {T.re, T.im, T.zg, G.lf, T.zl, G.hbit, G.term_begin, G.term_count};
+  }
+}
+
+// Group gi of the pass with its first term's sign for the tile at base
+// folded in, as workgroup-uniform values.
+__device__ __forceinline__ ExpGroupLds exp_group(const ExpPassDev& P, const ExpGroupDev* __restrict__ groups,
+                                                 const ExpTermDev* __restrict__ terms, uint64_t base,
+                                                 const ExpGroupLds* sg, int gi) {
+  ExpGroupLds r;
+  if (gi < kExpPreGroups) {
+    r = sg[gi];
+  } else {
+    const ExpGroupDev G = groups[P.grp_begin + gi];
+    const ExpTermDev T = terms[G.term_begin];
+    r = {T.re, T.im, T.zg, G.lf, T.zl, G.hbit, G.term_begin, G.term_count};
+  }
+  r = {uni(r.re), uni(r.im), uni(r.zg), uni(r.lf), uni(r.zl), uni(r.hbit), uni(r.term_begin), uni(r.term_count)};
+  if (__popcll(base & r.zg) & 1) {
+    r.re = -r.re;
+    r.im = -r.im;
+  }
+  return r;
+}
+
+// Stages the terms of a multi-term group for the tile at base (sign folded in).
+__device__ __forceinline__ void exp_stage_terms(const ExpTermDev* __restrict__ terms, const ExpGroupLds& G,
+                                                uint64_t base, ExpTermLds* et) {
+  const int ns = min(G.term_count, kExpLdsTerms);
+  for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+    const ExpTermDev T = terms[G.term_begin + k];
+    const bool gneg = __popcll(base & T.zg) & 1;
+    et[k] = {gneg ? -T.re : T.re, gneg ? -T.im : T.im, T.zl};
+  }
+}
+
+__device__ __forceinline__ void exp_term(const ExpTermDev* __restrict__ terms, const ExpTermLds* et,
+                                         const ExpGroupLds& G, uint64_t base, int k, double& re, double& im,
+                                         uint32_t& zl) {
+  if (k < kExpLdsTerms) {
+    re = et[k].re;
+    im = et[k].im;
+    zl = et[k].zl;
+  } else {
+    const ExpTermDev T = terms[G.term_begin + k];
+    const bool gneg = __popcll(base & T.zg) & 1;
+    re = gneg ? -T.re : T.re;
+    im = gneg ? -T.im : T.im;
+    zl = T.zl;
+  }
+}
+
+// <psi|O|psi> over the tiles of one pass. Products and sums are FP64 (the
+// product of two FP32 values is exact in FP64), so for complex64 states the
+// reduction adds no error beyond the stored amplitudes. Each workgroup sums its
+// tiles in a fixed order into partial[blockIdx.x] (added to the value of
+// earlier passes when accumulate is set). FULL: the tile has at least two
+// amplitudes per thread, so every loop below has a workgroup-uniform trip
+// count (no per-lane guards).
+template <typename R, bool FULL>
+__global__ void __launch_bounds__(kExpThreadsE)
+    k_expect_tile(const R* __restrict__ psi, const ExpPassDev* __restrict__ passes, int pass_idx,
+                  const ExpGroupDev* __restrict__ groups, const ExpTermDev* __restrict__ terms,
+                  double* __restrict__ partial, int accumulate, uint64_t ntiles) {
+  constexpr int NT = kExpThreadsE;
+  constexpr int NA = kExpTileMax / NT;  // amplitudes per thread, at most
+  extern __shared__ __align__(16) char smem[];
+  __shared__ double red[NT / 64];
+  __shared__ ExpTermLds et[kExpLdsTerms];
+  __shared__ ExpGroupLds sg[kExpPreGroups];
+  cx<R>* t = reinterpret_cast<cx<R>*>(smem);
+  const ExpPassDev& P = passes[pass_idx];
+  const uint32_t TS = 1u << P.L;
+  const uint32_t tid = threadIdx.x;
+  exp_stage_groups(P, groups, terms, sg);
+  ExpTileStream<R, NT> io(P);
+  ExpTileRange tr(P, ntiles);
+  double acc = 0.0;
+  if (tr.g < tr.end) io.fetch(psi, tr.base);
+  for (; tr.g < tr.end; ++tr.g) {
+    const uint64_t base = tr.base;
+    __syncthreads();  // previous tile consumed
+    io.to_lds(t);
+    if (tr.g + 1 < tr.end) {
+      tr.base = tr.next_base();
+      io.fetch(psi, tr.base);
+    }
+    __syncthreads();  // tile (and, first time, the group table) in LDS
+    for (int gi = 0; gi < P.grp_count; ++gi) {
+      const ExpGroupLds G = exp_group(P, groups, terms, base, sg, gi);
+      const int nt = G.term_count;
+      if (nt > 1) {
+        __syncthreads();
+        exp_stage_terms(terms, G, base, et);
+        __syncthreads();
       }
-      acc += re * double(sum);
-    } else if (G.lf == 0) {
-      for (uint32_t j = tid; j < TS; j += blockDim.x) {
-        const cx<R> a = t[j];
-        double c = 0.0;
-        for (int k = 0; k < nt; ++k) {
-          double re;
-          uint32_t zl;
-          if (k < kExpLdsTerms) {
-            re = et[k].re;
-            zl = et[k].zl;
-          } else {
-            const ExpTermDev T = terms[G.term_begin + k];
-            re = (__popcll(base & T.zg) & 1) ? -T.re : T.re;
-            zl = T.zl;
+      if (G.lf == 0 && nt == 1) {
+        // sum of +-|psi_x|^2: thread part of the sign once, uniform part per step
+        const uint32_t pt = __popc(tid & G.zl) & 1;
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+          const uint32_t j0 = uint32_t(k) * NT;
+          if (j0 >= TS) break;
+          if (FULL || j0 + tid < TS) {
+            const cx<R> a = t[j0 + tid];
+            const double p = double(a.re) * a.re + double(a.im) * a.im;
+            sum += flip_sign(p, pt ^ (__popc(j0 & G.zl) & 1));
           }
-          c += (__popc(j & zl) & 1) ? -re : re;
         }
-        acc += double(a.re * a.re + a.im * a.im) * c;
-      }
-    } else {
-      const int hb = G.hbit;
-      const uint32_t lf = G.lf;
-      // pairs (x, x ^ lf) with bit hb of x clear: x = ins0(i) for i < TS/2,
-      // i = tid + step; ins0 places bits, so x = ins0(tid) | ins0(step)
-      const uint32_t xt = ins0(tid, hb);
-      if (nt == 1) {
-        // one term (the common case for random strings): c(x) = +-(re + i im)
-        const ExpTermDev T = terms[G.term_begin];
-        const bool gneg = __popcll(base & T.zg) & 1;
-        const double re = gneg ? -T.re : T.re, im = gneg ? -T.im : T.im;
-        const uint32_t zl = T.zl;
-        const uint32_t pt = __popc(xt & zl) & 1;
-        R sr = R(0), si = R(0);
-        for (uint32_t i0 = 0; i0 < TS / 2; i0 += kExpThreads) {
-          if (i0 + tid >= TS / 2) break;
-          const uint32_t xs = ins0(i0, hb);
-          const uint32_t x = xt | xs;
-          const cx<R> a = t[x], bb = t[x ^ lf];
-          // w = conj(psi[y]) psi[x]
-          const R wr = bb.re * a.re + bb.im * a.im;
-          const R wi = bb.re * a.im - bb.im * a.re;
-          const bool neg = pt ^ (__popc(xs & zl) & 1);
-          sr += neg ? -wr : wr;
-          si += neg ? -wi : wi;
-        }
-        acc += 2.0 * (double(sr) * re - double(si) * im);
-      } else {
-        for (uint32_t i = tid; i < TS / 2; i += blockDim.x) {
-          const uint32_t x = ins0(i, hb);
-          const cx<R> a = t[x], bb = t[x ^ lf];
-          const double wr = double(bb.re * a.re + bb.im * a.im);
-          const double wi = double(bb.re * a.im - bb.im * a.re);
-          double cr = 0.0, ci = 0.0;
+        acc += G.re * sum;
+      } else if (G.lf == 0) {
+        for (uint32_t j = tid; j < TS; j += NT) {
+          const cx<R> a = t[j];
+          double c = 0.0;
           for (int k = 0; k < nt; ++k) {
             double re, im;
             uint32_t zl;
-            if (k < kExpLdsTerms) {
-              re = et[k].re;
-              im = et[k].im;
-              zl = et[k].zl;
-            } else {
-              const ExpTermDev T = terms[G.term_begin + k];
-              const bool gneg = __popcll(base & T.zg) & 1;
-              re = gneg ? -T.re : T.re;
-              im = gneg ? -T.im : T.im;
-              zl = T.zl;
-            }
-            const bool neg = __popc(x & zl) & 1;
-            cr += neg ? -re : re;
-            ci += neg ? -im : im;
+            exp_term(terms, et, G, base, k, re, im, zl);
+            c += (__popc(j & zl) & 1) ? -re : re;
           }
-          acc += 2.0 * (wr * cr - wi * ci);
+          acc += (double(a.re) * a.re + double(a.im) * a.im) * c;
+        }
+      } else {
+        const int hb = G.hbit;
+        const uint32_t lf = G.lf;
+        // pairs (x, x ^ lf) with bit hb of x clear: x = ins0(i) for i < TS/2,
+        // i = tid + step; ins0 places bits, so x = ins0(tid) | ins0(step)
+        const uint32_t xt = ins0(tid, hb);
+        if (nt == 1) {
+          // one term (the common case for random strings). A Hermitian term's
+          // coefficient alpha i^nY is real (nY even) or imaginary (nY odd):
+          // only Re or Im of w = conj(psi[y]) psi[x] counts
+          const uint32_t pt = __popc(xt & G.zl) & 1;
+          const bool real = G.im == 0.0;
+          double sw = 0.0;
+#pragma unroll
+          for (int k = 0; k < NA / 2; ++k) {
+            const uint32_t i0 = uint32_t(k) * NT;
+            if (i0 >= TS / 2) break;
+            if (FULL || i0 + tid < TS / 2) {
+              const uint32_t xs = ins0(i0, hb);
+              const uint32_t x = xt | xs;
+              const cx<R> a = t[x], bb = t[x ^ lf];
+              const double w = real ? double(bb.re) * a.re + double(bb.im) * a.im
+                                    : double(bb.re) * a.im - double(bb.im) * a.re;
+              sw += flip_sign(w, pt ^ (__popc(xs & G.zl) & 1));
+            }
+          }
+          acc += 2.0 * (real ? sw * G.re : -sw * G.im);
+        } else {
+          for (uint32_t i = tid; i < TS / 2; i += NT) {
+            const uint32_t x = ins0(i, hb);
+            const cx<R> a = t[x], bb = t[x ^ lf];
+            // w = conj(psi[y]) psi[x]
+            const double wr = double(bb.re) * a.re + double(bb.im) * a.im;
+            const double wi = double(bb.re) * a.im - double(bb.im) * a.re;
+            double cr = 0.0, ci = 0.0;
+            for (int k = 0; k < nt; ++k) {
+              double re, im;
+              uint32_t zl;
+              exp_term(terms, et, G, base, k, re, im, zl);
+              const bool neg = __popc(x & zl) & 1;
+              cr += neg ? -re : re;
+              ci += neg ? -im : im;
+            }
+            acc += 2.0 * (wr * cr - wi * ci);
+          }
         }
       }
     }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  __syncthreads();
   if ((tid & 63) == 0) red[tid >> 6] = acc;
   __syncthreads();
   if (tid == 0) {
     double r = 0.0;
-    for (int w = 0; w < kExpThreads / 64; ++w) r += red[w];
+    for (int w = 0; w < NT / 64; ++w) r += red[w];
     partial[blockIdx.x] = accumulate ? partial[blockIdx.x] + r : r;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kExpThreads) k_zero_amps(R* __restrict__ a, uint64_t n) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    store1(a, i, cx<R>{R(0), R(0)});
+}
+
+// lambda = O psi over the tiles of one pass (the pass's flip masks only): every
+// output y of a tile gathers psi[y ^ F] from LDS for each group F of the pass,
+// with c(x) = sum over the group's terms of alpha i^nY (-1)^|x & z|,
+// accumulated in FP64; the first pass writes lambda, later passes add to it.
+constexpr int kObsOut = 8;  // outputs per thread: 2^12 / 512
+template <typename R>
+__global__ void __launch_bounds__(kExpThreads)
+    k_apply_obs_tile(const R* __restrict__ psi, R* __restrict__ lam, const ExpPassDev* __restrict__ passes,
+                     int pass_idx, const ExpGroupDev* __restrict__ groups,
+                     const ExpTermDev* __restrict__ terms, int accumulate, uint64_t ntiles) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ ExpTermLds et[kExpLdsTerms];
+  __shared__ ExpGroupLds sg[kExpPreGroups];
+  cx<R>* t = reinterpret_cast<cx<R>*>(smem);
+  const ExpPassDev& P = passes[pass_idx];
+  const uint32_t TS = 1u << P.L;
+  const uint32_t tid = threadIdx.x;
+  exp_stage_groups(P, groups, terms, sg);
+  ExpTileStream<R, kExpThreads> io(P);
+  const uint64_t yt = exp_place(P, tid);
+  uint64_t yk[kObsOut];
+#pragma unroll
+  for (int k = 0; k < kObsOut; ++k) yk[k] = exp_place(P, uint32_t(k) * kExpThreads);
+  ExpTileRange tr(P, ntiles);
+  if (tr.g < tr.end) io.fetch(psi, tr.base);
+  for (; tr.g < tr.end; ++tr.g) {
+    const uint64_t base = tr.base;
+    __syncthreads();  // previous tile consumed
+    io.to_lds(t);
+    if (tr.g + 1 < tr.end) {
+      tr.base = tr.next_base();
+      io.fetch(psi, tr.base);
+    }
+    double ar[kObsOut], ai[kObsOut];
+    cx<R> old[kObsOut];
+#pragma unroll
+    for (int k = 0; k < kObsOut; ++k) {
+      ar[k] = ai[k] = 0.0;
+      if (accumulate && tid + uint32_t(k) * kExpThreads < TS) old[k] = load1(lam, base | yt | yk[k]);
+    }
+    __syncthreads();  // tile (and, first time, the group table) in LDS
+    for (int gi = 0; gi < P.grp_count; ++gi) {
+      const ExpGroupLds G = exp_group(P, groups, terms, base, sg, gi);
+      const int nt = G.term_count;
+      if (nt > 1) {
+        __syncthreads();
+        exp_stage_terms(terms, G, base, et);
+        __syncthreads();
+      }
+      const uint32_t lf = G.lf;
+      if (nt == 1) {
+        // alpha i^nY is real or imaginary: lambda += c psi or i c psi
+        const uint32_t pt = (__popc((tid ^ lf) & G.zl) & 1);
+        const bool real = G.im == 0.0;
+        const double cm = real ? G.re : G.im;
+#pragma unroll
+        for (int k = 0; k < kObsOut; ++k) {
+          const uint32_t y = tid + uint32_t(k) * kExpThreads;
+          if (y < TS) {
+            const cx<R> v = t[y ^ lf];
+            const double c = flip_sign(cm, pt ^ (__popc((uint32_t(k) * kExpThreads) & G.zl) & 1));
+            const double vr = v.re, vi = v.im;
+            ar[k] += real ? c * vr : -c * vi;
+            ai[k] += real ? c * vi : c * vr;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < kObsOut; ++k) {
+          const uint32_t y = tid + uint32_t(k) * kExpThreads;
+          if (y < TS) {
+            const uint32_t x = y ^ lf;
+            const cx<R> v = t[x];
+            double cr = 0.0, ci = 0.0;
+            for (int q = 0; q < nt; ++q) {
+              double re, im;
+              uint32_t zl;
+              exp_term(terms, et, G, base, q, re, im, zl);
+              const bool neg = __popc(x & zl) & 1;
+              cr += neg ? -re : re;
+              ci += neg ? -im : im;
+            }
+            ar[k] += cr * double(v.re) - ci * double(v.im);
+            ai[k] += cr * double(v.im) + ci * double(v.re);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kObsOut; ++k) {
+      if (tid + uint32_t(k) * kExpThreads >= TS) continue;
+      cx<R> r;
+      if (accumulate) r = {R(double(old[k].re) + ar[k]), R(double(old[k].im) + ai[k])};
+      else r = {R(ar[k]), R(ai[k])};
+      store1(lam, base | yt | yk[k], r);
+    }
   }
 }
 
@@ -364,25 +608,65 @@ int expect_tiled_t(qsv_state* s, qsv_observable* o, double* out) {
   int rc = upload_exp_plan(pl, s->device);
   if (rc) return rc;
   const uint64_t tiles = dim(s->n - pl->L);
-  if ((rc = ensure_reduce_scratch(s, size_t(tiles) + 1))) return rc;
+  const uint64_t grid = std::min<uint64_t>(tiles, kExpGrid);
+  if ((rc = ensure_reduce_scratch(s, size_t(grid) + 1))) return rc;
   const size_t lds = (size_t(1) << pl->L) * sizeof(cx<R>);
-  QSV_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_expect_tile<R>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  const bool full = (size_t(1) << pl->L) >= size_t(2 * kExpThreadsE);
+  const void* kfn = full ? reinterpret_cast<const void*>(&k_expect_tile<R, true>)
+                         : reinterpret_cast<const void*>(&k_expect_tile<R, false>);
+  QSV_HIP_CHECK(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   char* d = static_cast<char*>(pl->dev);
   for (size_t pi = 0; pi < pl->passes.size(); ++pi) {
     ProfScope ps("expect", double(sizeof(cx<R>)) * double(dim(s->n)), s->stream);
-    hipLaunchKernelGGL((k_expect_tile<R>), dim3(unsigned(tiles)), dim3(kExpThreads), lds, s->stream,
-                       static_cast<const R*>(s->ptr), reinterpret_cast<const ExpPassDev*>(d), int(pi),
-                       reinterpret_cast<const ExpGroupDev*>(d + pl->off_groups),
-                       reinterpret_cast<const ExpTermDev*>(d + pl->off_terms), s->red, pi > 0 ? 1 : 0);
+    const auto* pd = reinterpret_cast<const ExpPassDev*>(d);
+    const auto* gd = reinterpret_cast<const ExpGroupDev*>(d + pl->off_groups);
+    const auto* td = reinterpret_cast<const ExpTermDev*>(d + pl->off_terms);
+    const R* psi = static_cast<const R*>(s->ptr);
+    if (full)
+      hipLaunchKernelGGL((k_expect_tile<R, true>), dim3(unsigned(grid)), dim3(kExpThreadsE), lds, s->stream,
+                         psi, pd, int(pi), gd, td, s->red, pi > 0 ? 1 : 0, tiles);
+    else
+      hipLaunchKernelGGL((k_expect_tile<R, false>), dim3(unsigned(grid)), dim3(kExpThreadsE), lds, s->stream,
+                         psi, pd, int(pi), gd, td, s->red, pi > 0 ? 1 : 0, tiles);
     QSV_HIP_CHECK(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_exp_sum, dim3(1), dim3(kExpThreads), 0, s->stream, s->red, tiles, s->red + tiles);
+  hipLaunchKernelGGL(k_exp_sum, dim3(1), dim3(kExpThreads), 0, s->stream, s->red, grid, s->red + grid);
   QSV_HIP_CHECK(hipGetLastError());
-  QSV_HIP_CHECK(hipMemcpyAsync(s->red_host, s->red + tiles, sizeof(double), hipMemcpyDeviceToHost,
+  QSV_HIP_CHECK(hipMemcpyAsync(s->red_host, s->red + grid, sizeof(double), hipMemcpyDeviceToHost,
                                s->stream));
   QSV_HIP_CHECK(hipStreamSynchronize(s->stream));
   *out = s->red_host[0];
+  return QSV_OK;
+}
+
+template <typename R>
+int apply_obs_tiled_t(const qsv_state* in, qsv_observable* o, qsv_state* out) {
+  ExpPlan*& pl = o->exp_plan[in->dtype];
+  if (!pl) pl = build_exp_plan(o, in->dtype);
+  const uint64_t N = dim(in->n);
+  if (pl->passes.empty()) {  // no terms: lambda = 0
+    const uint64_t blocks = std::min<uint64_t>((N + kExpThreads - 1) / kExpThreads, 65536);
+    hipLaunchKernelGGL((k_zero_amps<R>), dim3(unsigned(blocks)), dim3(kExpThreads), 0, in->stream,
+                       static_cast<R*>(out->ptr), N);
+    QSV_HIP_CHECK(hipGetLastError());
+    return QSV_OK;
+  }
+  int rc = upload_exp_plan(pl, in->device);
+  if (rc) return rc;
+  const uint64_t tiles = dim(in->n - pl->L);
+  const size_t lds = (size_t(1) << pl->L) * sizeof(cx<R>);
+  QSV_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_obs_tile<R>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  char* d = static_cast<char*>(pl->dev);
+  for (size_t pi = 0; pi < pl->passes.size(); ++pi) {
+    ProfScope ps("apply_obs", double(sizeof(cx<R>)) * double(N) * (pi > 0 ? 3.0 : 2.0), in->stream);
+    hipLaunchKernelGGL((k_apply_obs_tile<R>), dim3(unsigned(std::min<uint64_t>(tiles, kExpGrid))),
+                       dim3(kExpThreads), lds, in->stream, static_cast<const R*>(in->ptr),
+                       static_cast<R*>(out->ptr), reinterpret_cast<const ExpPassDev*>(d), int(pi),
+                       reinterpret_cast<const ExpGroupDev*>(d + pl->off_groups),
+                       reinterpret_cast<const ExpTermDev*>(d + pl->off_terms), pi > 0 ? 1 : 0, tiles);
+    QSV_HIP_CHECK(hipGetLastError());
+  }
   return QSV_OK;
 }
 
@@ -391,6 +675,12 @@ int expect_tiled_t(qsv_state* s, qsv_observable* o, double* out) {
 int expectation_tiled(qsv_state* s, const qsv_observable* o, double* out) {
   qsv_observable* mo = const_cast<qsv_observable*>(o);  // plan cache only
   return s->dtype == QSV_C64 ? expect_tiled_t<float>(s, mo, out) : expect_tiled_t<double>(s, mo, out);
+}
+
+// lambda = O psi (out must not alias in; both on in's stream).
+int apply_observable_tiled(const qsv_state* in, const qsv_observable* o, qsv_state* out) {
+  qsv_observable* mo = const_cast<qsv_observable*>(o);  // plan cache only
+  return in->dtype == QSV_C64 ? apply_obs_tiled_t<float>(in, mo, out) : apply_obs_tiled_t<double>(in, mo, out);
 }
 
 int expectation_passes(const qsv_observable* o, qsv_dtype dt) {

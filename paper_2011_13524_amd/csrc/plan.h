@@ -49,7 +49,8 @@ constexpr int kRegMaxThreadBits = 9;   // up to 512-thread workgroups
 struct RegSegDev {
   int reg[kRegMaxBits];        // local positions of register-index bits, ascending
   int thr[kRegMaxThreadBits];  // local position of thread-index bit k
-  int xwave;                   // re-map into this layout crosses wavefronts
+  int xwave;                   // re-map into this layout: 0 within wavefronts, 1 across
+                               // them, 2 across them after a workgroup barrier
   int op_begin, op_count;
   // the re-map into this layout writes local index x of the previous layout
   // to position M x ^ mcst (folded X / controlled-X ops); mcol[p] = M e_p

@@ -484,6 +484,13 @@ static int build_segments(qsv_plan* p, const std::vector<TileOpDev>& ho, TilePas
     }
     k = m;
   }
+  // A cross-wave re-map writes with the folded map, which may move elements
+  // into other wavefronts' regions of the old layout; after a wave-local re-map
+  // (no trailing barrier) those wavefronts may still be reading there, so such
+  // a re-map also waits for the workgroup before writing.
+  std::vector<char> pre(K, 0);
+  for (int k = 2; k < K; ++k)
+    if (segs[k].xwave && !segs[k - 1].xwave && (ftarget[k] & segs[k - 1].w)) pre[k] = 1;
 
   for (Seg& s : segs) {
     RegSegDev sd{};
@@ -524,6 +531,7 @@ static int build_segments(qsv_plan* p, const std::vector<TileOpDev>& ho, TilePas
       }
     if (nr != RB || nt != TB) return fail(QSV_EINVAL, "internal: bad segment layout");
     sd.xwave = s.xwave ? 1 : 0;
+    if (pre[&s - segs.data()]) sd.xwave = 2;
     {
       const int k = int(&s - segs.data());
       for (int q = 0; q < L; ++q) sd.mcol[q] = mcol[k][q];

@@ -409,6 +409,7 @@ __global__ void __launch_bounds__(1 << TB)
       // wavefront reads back only what it wrote, and LDS operations of one
       // wavefront complete in order: no workgroup barrier is needed
       const bool xw = Sn->xwave != 0;
+      if (Sn->xwave == 2) __syncthreads();
       {
         const LdsMap<R, RB, TB, Swz<SB>> mo(*S, tau, sw, Sn);
 #pragma unroll
