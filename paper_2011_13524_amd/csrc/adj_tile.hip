@@ -293,7 +293,7 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
   // passes (as in the forward planner): dense targets must be local
   const int Lc = sizeof(R) == 4 ? 12 : 11;
   const int L = std::min(n, Lc);
-  const int b = std::min(L, sizeof(R) == 4 ? 6 : 5);
+  const int b = std::min(L, sizeof(R) == 4 ? 4 : 3);  // 128-byte contiguous runs
   const uint64_t low = (uint64_t(1) << b) - 1;
   std::vector<std::vector<int>> pass_ops;
   std::vector<uint64_t> pass_local;

@@ -854,7 +854,10 @@ int qsv_plan_fused(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qu
   if (max_k < 1 || max_k > 5) return fail(QSV_EINVAL, "max_k must be in 1..5");
   const int n = c->n;
   int L = tile_qubits > 0 ? tile_qubits : (dtype == QSV_C64 ? 13 : 12);
-  int b = low_qubits > 0 ? low_qubits : (dtype == QSV_C64 ? 6 : 5);
+  // low qubits always local: 2^b amplitudes form one contiguous run, 128 bytes
+  // (one cache line) at the default; fewer fixed low qubits leave more local
+  // qubits free for the circuit, so fewer passes
+  int b = low_qubits > 0 ? low_qubits : (dtype == QSV_C64 ? 4 : 3);
   if (L > 14 || (dtype == QSV_C128 && L > 13)) return fail(QSV_EINVAL, "tile of %d qubits exceeds LDS", L);
   L = std::min(L, n);
   b = std::min(b, L);
