@@ -25,7 +25,7 @@ Extra legs (same JSON line):
                 parameters), one gradient component checked by the shift rule
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode fused|unfused]
-                       [--quick] [--no-cpu]
+                       [--quick] [--no-cpu] [--leg NAME]
 """
 from __future__ import annotations
 
@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fd-params", type=int, default=6)
     ap.add_argument("--batch-items", type=int, default=512)
+    ap.add_argument("--leg", choices=["adjoint_24q", "batch_vqe", "random_26q", "adjoint_32q"],
+                    help="run only this extra leg and print its JSON (for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also copy the state once (a device copy of known size, used to "
                          "calibrate rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -283,6 +285,13 @@ def main():
 
     import paper_2011_13524_amd as Q
     from paper_2011_13524_amd import workloads as W
+
+    if args.leg:
+        legs = {"adjoint_24q": lambda: adjoint_leg(Q, W, args.fd_params),
+                "batch_vqe": lambda: batch_leg(Q, W, args.batch_items),
+                "random_26q": lambda: random_leg(Q, W), "adjoint_32q": lambda: adjoint32_leg(Q, W)}
+        print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
+        return
 
     n = args.n
     dt = "c64"
