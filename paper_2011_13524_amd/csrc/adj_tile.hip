@@ -185,6 +185,250 @@ __global__ void __launch_bounds__(kAdjTileThreads)
 }
 
 
+// ------------------------------------------------------------------ register-resident sweep
+//
+// The reverse sweep with both tiles (psi and lambda) register-resident, using
+// the segment layouts of the forward tile passes: ops on register bits run on
+// both states from registers, X / CNOT ops fold into the LDS re-maps (a
+// permutation of indices, applied to both states), and a rotation's gradient
+// term -Im<lambda|P|psi> is evaluated on the register pairs just before its
+// uncompute. Per gradient op, each wavefront sums its share (fixed order) into
+// its own LDS slot; workgroups are persistent over a contiguous range of tiles
+// and write one FP64 partial per (row, workgroup) at the end of the pass.
+constexpr int kAdjRegGrid = 1024;
+constexpr int kAdjMaxRows = 64;  // gradient rows per pass (LDS slots)
+
+// X/Y rotation on register bit P: share of -Im<lambda|P|psi>, then
+// psi, lambda <- u psi, u lambda (u = exp(-i t P/2)); writes every slot of os, ol.
+template <typename R, int NR, int P>
+__device__ __forceinline__ double grad_xy(const cx<R>* s, const cx<R>* l, cx<R>* os, cx<R>* ol, bool ypauli,
+                                          const cx<R>* __restrict__ u) {
+  const cx<R> u00 = u[0], u01 = u[1], u10 = u[2], u11 = u[3];
+  double acc = 0.0;
+#pragma unroll
+  for (int g = 0; g < NR / 2; ++g) {
+    const int i = ins1<P>(g), j = i | (1 << P);
+    const cx<R> a0 = s[i], a1 = s[j], l0 = l[i], l1 = l[j];
+    const double a0r = a0.re, a0i = a0.im, a1r = a1.re, a1i = a1.im;
+    const double l0r = l0.re, l0i = l0.im, l1r = l1.re, l1i = l1.im;
+    const double im = ypauli ? -(l0r * a1r + l0i * a1i) + (l1r * a0r + l1i * a0i)
+                             : (l0r * a1i - l0i * a1r) + (l1r * a0i - l1i * a0r);
+    acc -= im;
+    os[i] = cfma(u00, a0, u01 * a1);
+    os[j] = cfma(u10, a0, u11 * a1);
+    ol[i] = cfma(u00, l0, u01 * l1);
+    ol[j] = cfma(u10, l0, u11 * l1);
+  }
+  return acc;
+}
+
+// Z rotation: the bit of the target is register bit P (P >= 0) or `fixed`;
+// share of -Im<lambda|Z|psi>, then the diagonal u on both states.
+template <typename R, int NR, int P>
+__device__ __forceinline__ double grad_z(const cx<R>* s, const cx<R>* l, cx<R>* os, cx<R>* ol, int fixed,
+                                         const cx<R>* __restrict__ u) {
+  const cx<R> f0 = u[0], f1 = u[3];
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int bit = P >= 0 ? (i >> P) & 1 : fixed;
+    const cx<R> a = s[i], c = l[i];
+    const double im = double(c.re) * a.im - double(c.im) * a.re;
+    acc -= bit ? -im : im;
+    const cx<R> f = bit ? f1 : f0;
+    os[i] = f * a;
+    ol[i] = f * c;
+  }
+  return acc;
+}
+
+template <typename R, int NR>
+__device__ __forceinline__ double grad_apply(cx<R>* s, cx<R>* l, const RegOpDev& op, uint32_t tau,
+                                             uint64_t base, const cx<R>* __restrict__ u) {
+  cx<R> os[NR], ol[NR];
+  double acc = 0.0;
+  if (op.kind == 5) {
+    const bool y = op.k == 2;
+    switch (op.p1) {
+      case 0: acc = grad_xy<R, NR, 0>(s, l, os, ol, y, u); break;
+      case 1: acc = grad_xy<R, NR, 1>(s, l, os, ol, y, u); break;
+      case 2: acc = grad_xy<R, NR, 2>(s, l, os, ol, y, u); break;
+      default: acc = grad_xy<R, NR, 3>(s, l, os, ol, y, u); break;
+    }
+  } else {
+    int fixed = 0, p = -1;
+    if (op.dsrc[0] == 0) p = op.dbit[0];
+    else if (op.dsrc[0] == 1) fixed = int((tau >> op.dbit[0]) & 1);
+    else fixed = int((base >> op.dbit[0]) & 1);
+    switch (p) {
+      case 0: acc = grad_z<R, NR, 0>(s, l, os, ol, 0, u); break;
+      case 1: acc = grad_z<R, NR, 1>(s, l, os, ol, 0, u); break;
+      case 2: acc = grad_z<R, NR, 2>(s, l, os, ol, 0, u); break;
+      case 3: acc = grad_z<R, NR, 3>(s, l, os, ol, 0, u); break;
+      default: acc = grad_z<R, NR, -1>(s, l, os, ol, fixed, u); break;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    s[i] = os[i];
+    l[i] = ol[i];
+  }
+  return acc;
+}
+
+// Re-map of one state's registers through LDS (write in the old layout with
+// the folded map, read in the new one).
+template <typename R, int RB, int TB, typename SW>
+__device__ __forceinline__ void adj_remap(cx<R> (&v)[1 << RB], const LdsMap<R, RB, TB, SW>& mo,
+                                          const LdsMap<R, RB, TB, SW>& mn, bool xw, char* smem) {
+#pragma unroll
+  for (int i = 0; i < (1 << RB); ++i) mo.put(smem, i, v[i]);
+  if (xw) __syncthreads();
+  else wave_sync();
+#pragma unroll
+  for (int i = 0; i < (1 << RB); ++i) v[i] = mn.get(smem, i);
+  if (xw) __syncthreads();
+  else wave_sync();
+}
+
+// A block applied through LDS to one state held in registers.
+template <typename R, int RB, int TB, int KMAX, typename SW>
+__device__ __forceinline__ void adj_lds_op(cx<R> (&v)[1 << RB], const LdsMap<R, RB, TB, SW>& ms, char* smem,
+                                           const TileOpDev& op, const cx<R>* pool, int L, uint64_t base,
+                                           SW sw) {
+#pragma unroll
+  for (int i = 0; i < (1 << RB); ++i) ms.put(smem, i, v[i]);
+  __syncthreads();
+  lds_op<R, KMAX>(reinterpret_cast<cx<R>*>(smem), op, pool, L, base, sw);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < (1 << RB); ++i) v[i] = ms.get(smem, i);
+  __syncthreads();
+}
+
+template <typename R, int RB, int KMAX, int TB>
+__global__ void __launch_bounds__(1 << TB)
+    k_adj_reg(R* __restrict__ psi, R* __restrict__ lam, const TilePassDev* __restrict__ passes, int pass_idx,
+              const RegSegDev* __restrict__ segs, const RegOpDev* __restrict__ rops,
+              const TileOpDev* __restrict__ lops, const cx<R>* __restrict__ pool,
+              const int* __restrict__ prow, double* __restrict__ partial, uint64_t ntiles) {
+  constexpr int NR = 1 << RB;
+  constexpr int NW = 1 << (TB - 6);  // wavefronts per workgroup
+  constexpr int SB = sizeof(R) == 4 ? 5 : 4;
+  const Swz<SB> sw;
+  // one dynamic LDS block: the tile (first, at LDS address 0, as the re-map
+  // addressing requires) then the gradient slots [row][wave]
+  extern __shared__ __align__(16) char smem[];
+  cx<R>* t = reinterpret_cast<cx<R>*>(smem);
+  const TilePassDev& P = passes[pass_idx];
+  const int L = P.L, b = P.b;
+  double(*slot)[NW] = reinterpret_cast<double(*)[NW]>(smem + (size_t(1) << L) * sizeof(cx<R>));
+  const uint32_t tau = threadIdx.x;
+  const int wave = int(tau >> 6);
+  for (int i = int(tau); i < kAdjMaxRows * NW; i += blockDim.x) slot[i / NW][i % NW] = 0.0;
+  auto gbit = [&](int p) -> uint64_t { return uint64_t(1) << (p < b ? p : P.hq[p - b]); };
+  // tiles of this workgroup: a contiguous range (fixed order of its partial sums)
+  uint64_t gmask = 0;
+  for (int j = 0; j < P.ng; ++j) gmask |= uint64_t(1) << P.gpos[j];
+  const uint64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const uint64_t g0 = uint64_t(blockIdx.x) * per;
+  const uint64_t gend = g0 + per < ntiles ? g0 + per : ntiles;
+  uint64_t base = 0;
+  for (int j = 0; j < P.ng; ++j) base |= ((g0 >> j) & 1) << P.gpos[j];
+  const RegSegDev* S0 = &segs[P.seg_begin];
+  const RegSegDev* SL = &segs[P.seg_begin + P.seg_count - 1];
+  auto addr = [&](const RegSegDev& s, uint64_t bs, int i) -> uint64_t {
+    uint64_t x = bs;
+    for (int k = 0; k < TB; ++k)
+      if ((tau >> k) & 1) x |= gbit(s.thr[k]);
+#pragma unroll
+    for (int k = 0; k < RB; ++k)
+      if ((i >> k) & 1) x |= gbit(s.reg[k]);
+    return x;
+  };
+  cx<R> vs[NR], vl[NR];
+  for (uint64_t g = g0; g < gend; ++g) {
+    if (g > g0) base = ((base | ~gmask) + 1) & gmask;
+    // HBM -> registers in the first segment's layout
+    if (sizeof(R) == 4 && S0->reg[0] == 0) {
+#pragma unroll
+      for (int i = 0; i < NR; i += 2) {
+        const uint64_t x = addr(*S0, base, i);
+        AmpIO<R, 2>::load(psi, x, &vs[i]);
+        AmpIO<R, 2>::load(lam, x, &vl[i]);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const uint64_t x = addr(*S0, base, i);
+        AmpIO<R, 1>::load(psi, x, &vs[i]);
+        AmpIO<R, 1>::load(lam, x, &vl[i]);
+      }
+    }
+    __syncthreads();  // the previous tile's last LDS reads are done (and the slots cleared)
+    const RegSegDev* S = S0;
+    for (int sgi = 0; sgi < P.seg_count; ++sgi) {
+      const RegSegDev* Sn = &segs[P.seg_begin + sgi];
+      if (sgi > 0) {
+        // re-map both states through LDS (folded X / CNOT ops applied to both)
+        const bool xw = Sn->xwave != 0;
+        if (Sn->xwave == 2) __syncthreads();
+        const LdsMap<R, RB, TB, Swz<SB>> mo(*S, tau, sw, Sn), mn(*Sn, tau, sw, nullptr);
+        adj_remap<R, RB, TB, Swz<SB>>(vs, mo, mn, xw, smem);
+        adj_remap<R, RB, TB, Swz<SB>>(vl, mo, mn, xw, smem);
+      }
+      S = Sn;
+      for (int o = 0; o < S->op_count; ++o) {
+        const RegOpDev& op = rops[S->op_begin + o];
+        if ((base & op.gcm) != op.gcv) continue;  // non-local controls: uniform per tile
+        const cx<R>* m = pool + op.moff;
+        if (op.kind == 5 || op.kind == 6) {
+          double acc = grad_apply<R, NR>(vs, vl, op, tau, base, m);
+#pragma unroll
+          for (int sft = 32; sft > 0; sft >>= 1) acc += __shfl_xor(acc, sft, 64);
+          if ((tau & 63) == 0) slot[op.aux][wave] += acc;
+          continue;
+        }
+        if (op.kind == 3) {
+          const LdsMap<R, RB, TB, Swz<SB>> ms(*S, tau, sw, nullptr);
+          adj_lds_op<R, RB, TB, KMAX, Swz<SB>>(vs, ms, smem, lops[op.lop], pool, L, base, sw);
+          adj_lds_op<R, RB, TB, KMAX, Swz<SB>>(vl, ms, smem, lops[op.lop], pool, L, base, sw);
+          continue;
+        }
+        if ((tau & op.ti_cm) != op.ti_cv) continue;  // controls on thread bits
+        cx<R> gtab[4];
+        int a = op.p1, bb = op.p2;
+        if (op.kind == 2) diag_table<R>(op, m, tau, base, gtab, a, bb);
+        const int key = reg_key(op.kind, a, bb, op.ri_cm != 0);
+        reg_apply<R, NR>(vs, key, m, gtab, op.ri_cm, op.ri_cv);
+        reg_apply<R, NR>(vl, key, m, gtab, op.ri_cm, op.ri_cv);
+      }
+    }
+    // registers -> HBM in the last segment's layout
+    if (sizeof(R) == 4 && SL->reg[0] == 0) {
+#pragma unroll
+      for (int i = 0; i < NR; i += 2) {
+        const uint64_t x = addr(*SL, base, i);
+        AmpIO<R, 2>::store(psi, x, &vs[i]);
+        AmpIO<R, 2>::store(lam, x, &vl[i]);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const uint64_t x = addr(*SL, base, i);
+        AmpIO<R, 1>::store(psi, x, &vs[i]);
+        AmpIO<R, 1>::store(lam, x, &vl[i]);
+      }
+    }
+  }
+  __syncthreads();
+  for (int r = int(tau); r < P.row_count; r += blockDim.x) {
+    double sum = 0.0;
+    for (int w = 0; w < NW; ++w) sum += slot[r][w];
+    partial[size_t(prow[P.row_begin + r]) * gridDim.x + blockIdx.x] = sum;
+  }
+}
+
 // rows[r] = sum of the cols partials of row r (fixed order)
 __global__ void __launch_bounds__(kAdjTileThreads)
     k_rows_sum(const double* __restrict__ partial, int cols, double* __restrict__ rows) {
@@ -290,9 +534,13 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
     }
     ops.push_back(op);
   }
-  // passes (as in the forward planner): dense targets must be local
+  // passes (as in the forward planner): dense targets must be local. complex64
+  // states of at least one 2^12 tile run register-resident (256 threads x 16
+  // amplitudes per state), at most kAdjMaxRows gradient rows per pass
   const int Lc = sizeof(R) == 4 ? 12 : 11;
   const int L = std::min(n, Lc);
+  const bool reg = sizeof(R) == 4 && n >= 12;
+  const SegCfg cfg{4, 8, true};
   const int b = std::min(L, sizeof(R) == 4 ? 4 : 3);  // 128-byte contiguous runs
   const uint64_t low = (uint64_t(1) << b) - 1;
   std::vector<std::vector<int>> pass_ops;
@@ -302,6 +550,7 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
   while (!rem.empty()) {
     uint64_t local = low, blocked = 0;
     std::vector<int> take, deferred;
+    int nrow = 0;
     for (int oi : rem) {
       const BOp& o = ops[oi];
       const uint64_t all = qmask_of(o.targets) | qmask_of(o.controls);
@@ -313,7 +562,9 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
       uint64_t dense = 0;
       if (o.kind == 0 || (o.kind == 2 && o.pauli != 3)) dense = qmask_of(o.targets);
       const uint64_t need = dense & ~local;
-      if (__builtin_popcountll(local | need) <= L) {
+      const bool rows_full = reg && o.kind == 2 && nrow >= kAdjMaxRows;
+      if (!rows_full && __builtin_popcountll(local | need) <= L) {
+        if (o.kind == 2) ++nrow;
         local |= need;
         take.push_back(oi);
       } else {
@@ -331,6 +582,9 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
   std::vector<TilePassDev> hp;
   std::vector<TileOpDev> ho;
   std::vector<cx<R>> pool;
+  std::vector<int> prow;  // gradient rows of each pass, in slot order
+  std::vector<RegSegDev> segs;
+  std::vector<RegOpDev> rops;
   int kmax = 1;
   for (size_t pi = 0; pi < pass_ops.size(); ++pi) {
     const uint64_t local = pass_local[pi];
@@ -350,6 +604,8 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
       if (!(local >> q & 1)) d.gpos[d.ng++] = q;
     d.op_begin = int(ho.size());
     d.op_count = int(pass_ops[pi].size());
+    d.row_begin = int(prow.size());
+    d.row_count = 0;
     for (int oi : pass_ops[pi]) {
       const BOp& o = ops[oi];
       TileOpDev t{};
@@ -358,6 +614,8 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
         t.kind = 2;
         t.k = o.pauli;
         t.ins[0] = o.row;
+        t.ins[1] = d.row_count++;
+        prow.push_back(o.row);
         t.moff = int(pool.size());
         for (const cd& v : o.val) pool.push_back({R(v.re), R(v.im)});
         const int q = o.targets[0];
@@ -402,16 +660,25 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
       }
       ho.push_back(t);
     }
+    if (reg) {
+      d.seg_begin = int(segs.size());
+      d.seg_count = 0;
+      const int rc = build_reg_segments(cfg, ho, d, segs, rops);
+      if (rc) return rc;
+    }
     hp.push_back(d);
   }
   const int nrows = int(row_slot.size());
   const uint64_t tiles = dim(n - L);
-  const int G = int(std::min<uint64_t>(tiles, kAdjTileGrid));
-  // one device allocation: passes | ops | pool | partial[nrows x G] | rows[nrows]
+  const int G = int(std::min<uint64_t>(tiles, reg ? kAdjRegGrid : kAdjTileGrid));
+  // one device allocation: passes | ops | pool | segs | rops | prow | partial[nrows x G] | rows[nrows]
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t o_ops = al(hp.size() * sizeof(TilePassDev));
   const size_t o_pool = o_ops + al(std::max<size_t>(1, ho.size()) * sizeof(TileOpDev));
-  const size_t o_part = o_pool + al(std::max<size_t>(1, pool.size()) * sizeof(cx<R>));
+  const size_t o_segs = o_pool + al(std::max<size_t>(1, pool.size()) * sizeof(cx<R>));
+  const size_t o_rops = o_segs + al(std::max<size_t>(1, segs.size()) * sizeof(RegSegDev));
+  const size_t o_prow = o_rops + al(std::max<size_t>(1, rops.size()) * sizeof(RegOpDev));
+  const size_t o_part = o_prow + al(std::max<size_t>(1, prow.size()) * sizeof(int));
   const size_t o_rows = o_part + al(std::max<size_t>(1, size_t(nrows) * G) * sizeof(double));
   const size_t total = o_rows + al(std::max(1, nrows) * sizeof(double));
   char* d = nullptr;
@@ -428,29 +695,60 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
       (!ho.empty() && hipMemcpyAsync(d + o_ops, ho.data(), ho.size() * sizeof(TileOpDev),
                                      hipMemcpyHostToDevice, st) != hipSuccess) ||
       (!pool.empty() && hipMemcpyAsync(d + o_pool, pool.data(), pool.size() * sizeof(cx<R>),
+                                       hipMemcpyHostToDevice, st) != hipSuccess) ||
+      (!segs.empty() && hipMemcpyAsync(d + o_segs, segs.data(), segs.size() * sizeof(RegSegDev),
+                                       hipMemcpyHostToDevice, st) != hipSuccess) ||
+      (!rops.empty() && hipMemcpyAsync(d + o_rops, rops.data(), rops.size() * sizeof(RegOpDev),
+                                       hipMemcpyHostToDevice, st) != hipSuccess) ||
+      (!prow.empty() && hipMemcpyAsync(d + o_prow, prow.data(), prow.size() * sizeof(int),
                                        hipMemcpyHostToDevice, st) != hipSuccess))
     return fin(fail(QSV_EHIP, "tiled sweep table upload failed"));
   double* part = reinterpret_cast<double*>(d + o_part);
   hipLaunchKernelGGL(k_zero_doubles, dim3(256), dim3(256), 0, st, part, uint64_t(nrows) * G);
-  const size_t lds = 2 * (size_t(1) << L) * sizeof(cx<R>);
-  for (const void* k : {reinterpret_cast<const void*>(&k_tile_adj<R, 2>),
-                        reinterpret_cast<const void*>(&k_tile_adj<R, 3>),
-                        reinterpret_cast<const void*>(&k_tile_adj<R, 5>)})
-    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
-      return fin(fail(QSV_EHIP, "cannot raise LDS limit of the tiled sweep"));
-  for (size_t pi = 0; pi < hp.size(); ++pi) {
-    ProfScope ps("adjoint", 4.0 * sizeof(cx<R>) * double(dim(n)), st);
+  if constexpr (sizeof(R) == 4) {
+    if (reg) {
+      // register-resident passes (complex64 only): tile + gradient slots
+      const size_t lds = (size_t(1) << L) * sizeof(cx<R>) + size_t(kAdjMaxRows) * (256 / 64) * sizeof(double);
+      for (size_t pi = 0; pi < hp.size(); ++pi) {
+        ProfScope ps("adjoint", 4.0 * sizeof(cx<R>) * double(dim(n)), st);
+#define QSV_ADJR_LAUNCH(KM)                                                                      \
+    hipLaunchKernelGGL((k_adj_reg<R, 4, KM, 8>), dim3(G), dim3(256), lds, st,                      \
+                       static_cast<R*>(psi->ptr), static_cast<R*>(lam->ptr),                      \
+                       reinterpret_cast<const TilePassDev*>(d), int(pi),                          \
+                       reinterpret_cast<const RegSegDev*>(d + o_segs),                            \
+                       reinterpret_cast<const RegOpDev*>(d + o_rops),                             \
+                       reinterpret_cast<const TileOpDev*>(d + o_ops),                             \
+                       reinterpret_cast<const cx<R>*>(d + o_pool),                                \
+                       reinterpret_cast<const int*>(d + o_prow), part, tiles)
+        if (kmax <= 2) QSV_ADJR_LAUNCH(2);
+        else if (kmax <= 3) QSV_ADJR_LAUNCH(3);
+        else QSV_ADJR_LAUNCH(5);
+#undef QSV_ADJR_LAUNCH
+        if (hipGetLastError() != hipSuccess) return fin(fail(QSV_EHIP, "register sweep launch failed"));
+      }
+    }
+  }
+  if (!reg) {
+    const size_t lds = 2 * (size_t(1) << L) * sizeof(cx<R>);
+    for (const void* k : {reinterpret_cast<const void*>(&k_tile_adj<R, 2>),
+                          reinterpret_cast<const void*>(&k_tile_adj<R, 3>),
+                          reinterpret_cast<const void*>(&k_tile_adj<R, 5>)})
+      if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
+        return fin(fail(QSV_EHIP, "cannot raise LDS limit of the tiled sweep"));
+    for (size_t pi = 0; pi < hp.size(); ++pi) {
+      ProfScope ps("adjoint", 4.0 * sizeof(cx<R>) * double(dim(n)), st);
 #define QSV_ADJ_LAUNCH(KM)                                                                       \
-  hipLaunchKernelGGL((k_tile_adj<R, KM>), dim3(G), dim3(kAdjTileThreads), lds, st,               \
-                     static_cast<R*>(psi->ptr), static_cast<R*>(lam->ptr),                      \
-                     reinterpret_cast<const TilePassDev*>(d), int(pi),                          \
-                     reinterpret_cast<const TileOpDev*>(d + o_ops),                             \
-                     reinterpret_cast<const cx<R>*>(d + o_pool), part, tiles)
-    if (kmax <= 2) QSV_ADJ_LAUNCH(2);
-    else if (kmax <= 3) QSV_ADJ_LAUNCH(3);
-    else QSV_ADJ_LAUNCH(5);
+    hipLaunchKernelGGL((k_tile_adj<R, KM>), dim3(G), dim3(kAdjTileThreads), lds, st,               \
+                       static_cast<R*>(psi->ptr), static_cast<R*>(lam->ptr),                      \
+                       reinterpret_cast<const TilePassDev*>(d), int(pi),                          \
+                       reinterpret_cast<const TileOpDev*>(d + o_ops),                             \
+                       reinterpret_cast<const cx<R>*>(d + o_pool), part, tiles)
+      if (kmax <= 2) QSV_ADJ_LAUNCH(2);
+      else if (kmax <= 3) QSV_ADJ_LAUNCH(3);
+      else QSV_ADJ_LAUNCH(5);
 #undef QSV_ADJ_LAUNCH
-    if (hipGetLastError() != hipSuccess) return fin(fail(QSV_EHIP, "tiled sweep launch failed"));
+      if (hipGetLastError() != hipSuccess) return fin(fail(QSV_EHIP, "tiled sweep launch failed"));
+    }
   }
   rows.assign(nrows, 0.0);
   if (nrows > 0) {

@@ -376,8 +376,9 @@ __global__ void __launch_bounds__(kExpThreads) k_zero_amps(R* __restrict__ a, ui
 
 // lambda = O psi over the tiles of one pass (the pass's flip masks only): every
 // output y of a tile gathers psi[y ^ F] from LDS for each group F of the pass,
-// with c(x) = sum over the group's terms of alpha i^nY (-1)^|x & z|,
-// accumulated in FP64; the first pass writes lambda, later passes add to it.
+// with c(x) = sum over the group's terms of alpha i^nY (-1)^|x & z| (in FP64),
+// summed per pass in the amplitude precision (that of lambda itself); the
+// first pass writes lambda, later passes add to it.
 constexpr int kObsOut = 8;  // outputs per thread: 2^12 / 512
 template <typename R>
 __global__ void __launch_bounds__(kExpThreads)
@@ -407,13 +408,10 @@ __global__ void __launch_bounds__(kExpThreads)
       tr.base = tr.next_base();
       io.fetch(psi, tr.base);
     }
-    double ar[kObsOut], ai[kObsOut];
-    cx<R> old[kObsOut];
+    // per-pass sums in the amplitude precision (lambda is stored in it)
+    R ar[kObsOut], ai[kObsOut];
 #pragma unroll
-    for (int k = 0; k < kObsOut; ++k) {
-      ar[k] = ai[k] = 0.0;
-      if (accumulate && tid + uint32_t(k) * kExpThreads < TS) old[k] = load1(lam, base | yt | yk[k]);
-    }
+    for (int k = 0; k < kObsOut; ++k) ar[k] = ai[k] = R(0);
     __syncthreads();  // tile (and, first time, the group table) in LDS
     for (int gi = 0; gi < P.grp_count; ++gi) {
       const ExpGroupLds G = exp_group(P, groups, terms, base, sg, gi);
@@ -434,10 +432,9 @@ __global__ void __launch_bounds__(kExpThreads)
           const uint32_t y = tid + uint32_t(k) * kExpThreads;
           if (y < TS) {
             const cx<R> v = t[y ^ lf];
-            const double c = flip_sign(cm, pt ^ (__popc((uint32_t(k) * kExpThreads) & G.zl) & 1));
-            const double vr = v.re, vi = v.im;
-            ar[k] += real ? c * vr : -c * vi;
-            ai[k] += real ? c * vi : c * vr;
+            const R c = R(flip_sign(cm, pt ^ (__popc((uint32_t(k) * kExpThreads) & G.zl) & 1)));
+            ar[k] += real ? c * v.re : -c * v.im;
+            ai[k] += real ? c * v.im : c * v.re;
           }
         }
       } else {
@@ -456,8 +453,8 @@ __global__ void __launch_bounds__(kExpThreads)
               cr += neg ? -re : re;
               ci += neg ? -im : im;
             }
-            ar[k] += cr * double(v.re) - ci * double(v.im);
-            ai[k] += cr * double(v.im) + ci * double(v.re);
+            ar[k] += R(cr * double(v.re) - ci * double(v.im));
+            ai[k] += R(cr * double(v.im) + ci * double(v.re));
           }
         }
       }
@@ -466,8 +463,12 @@ __global__ void __launch_bounds__(kExpThreads)
     for (int k = 0; k < kObsOut; ++k) {
       if (tid + uint32_t(k) * kExpThreads >= TS) continue;
       cx<R> r;
-      if (accumulate) r = {R(double(old[k].re) + ar[k]), R(double(old[k].im) + ai[k])};
-      else r = {R(ar[k]), R(ai[k])};
+      if (accumulate) {
+        const cx<R> old = load1(lam, base | yt | yk[k]);
+        r = {old.re + ar[k], old.im + ai[k]};
+      } else {
+        r = {ar[k], ai[k]};
+      }
       store1(lam, base | yt | yk[k], r);
     }
   }

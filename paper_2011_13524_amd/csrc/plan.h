@@ -16,13 +16,15 @@ constexpr int kTileMaxGlobal = 40;
 // One operation inside a tile pass, in the tile's local index space (local
 // bit p <-> qubit local[p]).
 struct TileOpDev {
-  int kind;        // 0 dense on local targets, 1 diagonal (targets local or not)
+  int kind;        // 0 dense on local targets, 1 diagonal (targets local or not),
+                   // 2 gradient rotation of the reverse sweep (k = Pauli id)
   int k;           // number of targets
   int m;           // number of inserted zero positions (dense: targets + local controls)
   int moff;        // offset of the matrix / diagonal in the pool (complex elements)
   int lt[5];       // dense: local target positions; diag: local position or -1
   int gq[5];       // diag: global qubit of a non-local target, or -1
-  int ins[10];     // dense: sorted local positions with zero bits (targets + local controls)
+  int ins[10];     // dense: sorted local positions with zero bits (targets + local controls);
+                   // gradient: ins[0] = row of the gradient, ins[1] = its slot in the pass
   int xswap;       // 1: the one-qubit matrix is Pauli X (a pure exchange)
   uint32_t lcm, lcv;  // local control mask / values (local index space)
   uint64_t gcm, gcv;  // non-local control mask / values (global index space)
@@ -33,6 +35,7 @@ struct TilePassDev {
   int L, b, nh, ng;
   int op_begin, op_count;
   int seg_begin, seg_count;  // register-resident execution (seg_count > 0)
+  int row_begin, row_count;  // reverse sweep: gradient rows of the pass (slot s -> rows[row_begin + s])
   int hq[kTileMaxHigh];      // qubits of local bits b..L-1
   int gpos[kTileMaxGlobal];  // non-local qubits, ascending
 };
@@ -60,7 +63,8 @@ struct RegSegDev {
 
 struct RegOpDev {
   int kind;             // 0 dense one-qubit, 1 dense two-qubit, 2 diagonal (k <= 2), 3 via LDS,
-                        // 4 Pauli-X exchange on one register bit
+                        // 4 Pauli-X exchange on one register bit; reverse sweep: 5 gradient of an
+                        // X/Y rotation on register bit p1, 6 gradient of a Z rotation (dsrc/dbit[0])
   int p1, p2;           // register bits of matrix index bits 0 and 1
   int k;
   int dsrc[2], dbit[2]; // diagonal targets: source 0 register bit, 1 thread bit, 2 global qubit
@@ -69,7 +73,21 @@ struct RegOpDev {
   uint64_t gcm, gcv;      // controls on non-local qubits
   int moff;
   int lop;              // index of the equivalent TileOpDev (LDS execution)
+  int aux;              // gradient: slot of its row in the pass
 };
+
+// Register-resident layout of a tile: 2^reg_bits amplitudes per thread,
+// 2^thread_bits threads.
+struct SegCfg {
+  int reg_bits, thread_bits;
+  bool c64;  // complex64: the HBM layouts keep local bit 0 in registers (16-byte pairs)
+};
+
+// Splits the ops of pass d (ho[d.op_begin ..]) into register segments,
+// appending them to segs / rops; d.seg_count is incremented per segment (the
+// caller sets d.seg_begin = segs.size() and d.seg_count = 0 first).
+int build_reg_segments(const SegCfg& cfg, const std::vector<TileOpDev>& ho, TilePassDev& d,
+                       std::vector<RegSegDev>& segs, std::vector<RegOpDev>& rops);
 
 // A fused block: gates (indices into the circuit) applied in order, acting on
 // `qubits` (ascending). Single-gate blocks keep the gate's control structure.

@@ -327,10 +327,11 @@ static int build_plan(qsv_plan* p) {
 // (thread-index bits above the 64 lanes) are chosen so that consecutive
 // segments share them where possible: a re-map between two such layouts
 // moves data only within each wavefront and needs no workgroup barrier.
-static int build_segments(qsv_plan* p, const std::vector<TileOpDev>& ho, TilePassDev& d) {
-  const int RB = p->reg_bits, TB = p->thread_bits, L = d.L;
+int build_reg_segments(const SegCfg& cfg, const std::vector<TileOpDev>& ho, TilePassDev& d,
+                       std::vector<RegSegDev>& out_segs, std::vector<RegOpDev>& out_rops) {
+  const int RB = cfg.reg_bits, TB = cfg.thread_bits, L = d.L;
   const int NW = TB - 6;
-  const bool c64 = p->dtype == QSV_C64;
+  const bool c64 = cfg.c64;
   const uint32_t full = (1u << L) - 1;
   const uint32_t io_reg = c64 ? 1u : 0u;
   const uint32_t io_lane = c64 ? 0xEu : 0x7u;
@@ -341,9 +342,15 @@ static int build_segments(qsv_plan* p, const std::vector<TileOpDev>& ho, TilePas
   for (int i = 0; i < nops; ++i) {
     const TileOpDev& o = ho[d.op_begin + i];
     uint32_t tg = 0;
-    for (int j = 0; j < o.k && j < 5; ++j)
-      if (o.lt[j] >= 0) tg |= 1u << o.lt[j];
-    if (o.kind == 0) {
+    if (o.kind != 2)
+      for (int j = 0; j < o.k && j < 5; ++j)
+        if (o.lt[j] >= 0) tg |= 1u << o.lt[j];
+    if (o.kind == 2) {  // gradient rotation of the reverse sweep: k = Pauli id, target lt[0]/gq[0]
+      const uint32_t t1 = o.lt[0] >= 0 ? (1u << o.lt[0]) : 0u;
+      nd[i] = o.k == 3 ? 0u : t1;
+      dg[i] = o.k == 3 ? t1 : 0u;
+      need[i] = o.k == 3 ? 0u : t1;
+    } else if (o.kind == 0) {
       nd[i] = tg;
       dg[i] = o.lcm;
       need[i] = o.k <= 2 ? tg : 0u;
@@ -537,7 +544,7 @@ static int build_segments(qsv_plan* p, const std::vector<TileOpDev>& ho, TilePas
       for (int q = 0; q < L; ++q) sd.mcol[q] = mcol[k][q];
       sd.mcst = mcst[k];
     }
-    sd.op_begin = int(p->h_rops.size());
+    sd.op_begin = int(out_rops.size());
     sd.op_count = int(s.ops.size());
     for (int li : s.ops) {
       const int oi = d.op_begin + li;
@@ -559,7 +566,26 @@ static int build_segments(qsv_plan* p, const std::vector<TileOpDev>& ho, TilePas
           r.ti_cv |= val << thridx[pos];
         }
       }
-      if (o.kind == 0 && o.k <= 2) {
+      r.aux = o.kind == 2 ? o.ins[1] : 0;  // gradient: slot of the row in the pass
+      if (o.kind == 2 && o.k != 3) {
+        r.kind = 5;
+        r.p1 = regidx[o.lt[0]];
+        if (r.p1 < 0) return fail(QSV_EINVAL, "internal: gradient target not in registers");
+      } else if (o.kind == 2) {
+        r.kind = 6;
+        if (o.lt[0] >= 0) {
+          if (regidx[o.lt[0]] >= 0) {
+            r.dsrc[0] = 0;
+            r.dbit[0] = regidx[o.lt[0]];
+          } else {
+            r.dsrc[0] = 1;
+            r.dbit[0] = thridx[o.lt[0]];
+          }
+        } else {
+          r.dsrc[0] = 2;
+          r.dbit[0] = o.gq[0];
+        }
+      } else if (o.kind == 0 && o.k <= 2) {
         r.kind = o.k == 1 ? (o.xswap ? 4 : 0) : 1;
         r.p1 = regidx[o.lt[0]];
         r.p2 = o.k == 2 ? regidx[o.lt[1]] : 0;
@@ -583,9 +609,9 @@ static int build_segments(qsv_plan* p, const std::vector<TileOpDev>& ho, TilePas
       } else {
         r.kind = 3;
       }
-      p->h_rops.push_back(r);
+      out_rops.push_back(r);
     }
-    p->h_segs.push_back(sd);
+    out_segs.push_back(sd);
     d.seg_count++;
   }
   return QSV_OK;
@@ -669,7 +695,8 @@ static int upload_tables(qsv_plan* p, std::vector<int>& moffs, size_t& pool_elem
     d.seg_begin = int(p->h_segs.size());
     d.seg_count = 0;
     if (p->reg_bits > 0 && d.L == p->reg_bits + p->thread_bits) {
-      int rc = build_segments(p, ho, d);
+      const SegCfg cfg{p->reg_bits, p->thread_bits, p->dtype == QSV_C64};
+      int rc = build_reg_segments(cfg, ho, d, p->h_segs, p->h_rops);
       if (rc) return rc;
     }
     hp.push_back(d);

@@ -308,9 +308,10 @@ __device__ __forceinline__ void wave_sync() {
 // LDS addresses of a layout. The swizzle is linear over XOR and a local index
 // is the XOR of its register part and its thread part, so the byte offset of
 // element i is the per-thread part XOR a part that depends only on i and the
-// layout (uniform across the workgroup: scalar registers). The tile is the
-// kernel's only LDS block, so it starts at LDS address 0 and the base folds
-// into the per-thread part: one vector XOR per element remains.
+// layout (uniform across the workgroup: scalar registers). Kernels using it
+// declare no static LDS and put the tile first in their dynamic LDS, so it
+// starts at LDS address 0 and the base folds into the per-thread part: one
+// vector XOR per element remains.
 template <typename R, int RB, int TB, typename SW>
 struct LdsMap {
   uint32_t thr;       // swizzled thread part, in bytes
