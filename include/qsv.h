@@ -175,7 +175,7 @@ int qsv_apply_circuit(qsv_state* s, const qsv_circuit* c, const double* theta);
  *    gate depends on a single earlier block (merge of two successive gates);
  *    diagonal gates only merge with blocks whose qubits they do not widen;
  *  - blocks are grouped into tile passes: each pass keeps tile_qubits qubits
- *    local (0 = default: 13 for complex64, 12 for complex128), always including
+ *    local (0 = default: 12), always including
  *    the low_qubits lowest qubits (0 = default: 4 / 3) so that HBM runs are
  *    contiguous, and applies every block whose non-diagonal targets are local.
  *    One pass reads and writes the state once.

@@ -776,6 +776,32 @@ void plan_block_values(const qsv_plan* p, const double* theta, std::vector<cd>& 
   }
 }
 
+// Register-resident pass launch for the instantiated shapes (register bits,
+// thread bits): complex64 (4, 9), (4, 8), (5, 8), (4, 7); complex128 (4, 8), (4, 7).
+template <typename R, int RB, int TB>
+static void launch_tile_reg_km(int km, dim3 grid, size_t lds, hipStream_t st, R* psi, const qsv_plan* p,
+                               int pi, const cx<R>* pool) {
+  const dim3 block(1u << TB);
+  const TilePassDev* pd = p->d_pass;
+  if (km == 2)
+    hipLaunchKernelGGL((k_tile_reg<R, RB, 2, TB>), grid, block, lds, st, psi, pd, pi, p->d_segs, p->d_rops, p->d_ops, pool);
+  else if (km == 3)
+    hipLaunchKernelGGL((k_tile_reg<R, RB, 3, TB>), grid, block, lds, st, psi, pd, pi, p->d_segs, p->d_rops, p->d_ops, pool);
+  else
+    hipLaunchKernelGGL((k_tile_reg<R, RB, 5, TB>), grid, block, lds, st, psi, pd, pi, p->d_segs, p->d_rops, p->d_ops, pool);
+}
+
+template <typename R>
+static void launch_tile_reg(int rb, int tb, int km, dim3 grid, size_t lds, hipStream_t st, R* psi,
+                            const qsv_plan* p, int pi, const cx<R>* pool) {
+  if constexpr (sizeof(R) == 4) {
+    if (tb == 9) return launch_tile_reg_km<R, 4, 9>(km, grid, lds, st, psi, p, pi, pool);
+    if (tb == 8 && rb == 5) return launch_tile_reg_km<R, 5, 8>(km, grid, lds, st, psi, p, pi, pool);
+  }
+  if (tb == 7) return launch_tile_reg_km<R, 4, 7>(km, grid, lds, st, psi, p, pi, pool);
+  launch_tile_reg_km<R, 4, 8>(km, grid, lds, st, psi, p, pi, pool);
+}
+
 template <typename R>
 static int apply_fused_t(qsv_state* s, qsv_plan* p, const double* theta) {
   int trc = ensure_tables(p, s->stream);
@@ -832,32 +858,18 @@ static int apply_fused_t(qsv_state* s, qsv_plan* p, const double* theta) {
                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     }
     ProfScope ps("tile", 2.0 * sizeof(cx<R>) * double(dim(n)), s->stream);
-    constexpr int RB = sizeof(R) == 4 ? 5 : 4;
     R* psi = static_cast<R*>(s->ptr);
     const cx<R>* pool = static_cast<const cx<R>*>(p->d_pool);
-    const dim3 grid(static_cast<unsigned>(tiles)), block(256), block512(512);
-    const bool wide = p->thread_bits == 9;
-#define QSV_TILE_LAUNCH(KM)                                                                      \
-  do {                                                                                           \
-    if (p->h_pass[pi].seg_count > 0) {                                                           \
-      if constexpr (sizeof(R) == 4) {                                                            \
-        if (wide) {                                                                              \
-          hipLaunchKernelGGL((k_tile_reg<R, 4, KM, 9>), grid, block512, lds, s->stream, psi,     \
-                             p->d_pass, int(pi), p->d_segs, p->d_rops, p->d_ops, pool);          \
-          break;                                                                                 \
-        }                                                                                        \
-      }                                                                                          \
-      hipLaunchKernelGGL((k_tile_reg<R, RB, KM, 8>), grid, block, lds, s->stream, psi,           \
-                         p->d_pass, int(pi), p->d_segs, p->d_rops, p->d_ops, pool);              \
-    } else {                                                                                     \
-      hipLaunchKernelGGL((k_tile<R, KM>), grid, block, lds, s->stream, psi, p->d_pass, int(pi),   \
-                         p->d_ops, pool);                                                        \
-    }                                                                                            \
-  } while (0)
-    if (p->kmax_dense <= 2) QSV_TILE_LAUNCH(2);
-    else if (p->kmax_dense <= 3) QSV_TILE_LAUNCH(3);
-    else QSV_TILE_LAUNCH(5);
-#undef QSV_TILE_LAUNCH
+    const dim3 grid(static_cast<unsigned>(tiles));
+    const int km = p->kmax_dense <= 2 ? 2 : (p->kmax_dense <= 3 ? 3 : 5);
+    if (p->h_pass[pi].seg_count > 0)
+      launch_tile_reg<R>(p->reg_bits, p->thread_bits, km, grid, lds, s->stream, psi, p, int(pi), pool);
+    else if (km == 2)
+      hipLaunchKernelGGL((k_tile<R, 2>), grid, dim3(256), lds, s->stream, psi, p->d_pass, int(pi), p->d_ops, pool);
+    else if (km == 3)
+      hipLaunchKernelGGL((k_tile<R, 3>), grid, dim3(256), lds, s->stream, psi, p->d_pass, int(pi), p->d_ops, pool);
+    else
+      hipLaunchKernelGGL((k_tile<R, 5>), grid, dim3(256), lds, s->stream, psi, p->d_pass, int(pi), p->d_ops, pool);
     QSV_HIP_CHECK(hipGetLastError());
   }
   QSV_HIP_CHECK(hipEventRecord(p->stage_ev, s->stream));
@@ -880,7 +892,10 @@ int qsv_plan_fused(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qu
   if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_EDTYPE, "unknown dtype");
   if (max_k < 1 || max_k > 5) return fail(QSV_EINVAL, "max_k must be in 1..5");
   const int n = c->n;
-  int L = tile_qubits > 0 ? tile_qubits : (dtype == QSV_C64 ? 13 : 12);
+  // default tile: 2^12 amplitudes (256 threads x 16 in registers; 32 KiB of
+  // LDS for complex64, so several workgroups per compute unit hide latency)
+  int L = tile_qubits > 0 ? tile_qubits : 12;
+  if (const char* e = std::getenv("QSV_TILE_QUBITS"); e && tile_qubits <= 0) L = std::atoi(e);  // tuning
   // low qubits always local: 2^b amplitudes form one contiguous run, 128 bytes
   // (one cache line) at the default; fewer fixed low qubits leave more local
   // qubits free for the circuit, so fewer passes
@@ -898,20 +913,25 @@ int qsv_plan_fused(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qu
   p->max_k = max_k;
   p->L = L;
   p->b = b;
-  // register-resident passes when the tile is 256 threads x 2^RB amplitudes
-  // (RB = 5 for complex64, 4 for complex128: 64 KiB of LDS for re-mapping)
-  // QSV_TILE_THREAD_BITS=9 selects 512-thread workgroups (tuning)
-  // complex64: 512-thread workgroups x 16 amplitudes (measured ~7% faster than
-  // 256 x 32 at 30 qubits: twice the waves hide more latency); complex128:
-  // 256 x 16 (2^3 per thread would leave too few register bits)
+  // register-resident passes: 2^TB threads x 2^(L - TB) amplitudes. Default
+  // 256 threads (TB = 8) x 16: measured on MI355X, 2^12-amplitude tiles with
+  // 256 threads beat 2^13 with 512 threads (6% at 30 qubits complex64, more
+  // workgroups in flight per compute unit) despite more passes.
+  // QSV_TILE_THREAD_BITS (7, 8, 9) and QSV_TILE_QUBITS override for tuning.
+  int TB = kRegThreadBits;
+  if (const char* e = std::getenv("QSV_TILE_THREAD_BITS")) {
+    const int v = std::atoi(e);
+    TB = v == 9 ? 9 : (v == 7 ? 7 : 8);
+  }
   // (blocks of 4-5 qubits run through LDS with 32-amplitude temporaries: the
-  // 512-thread kernel would spill, so such plans use 256 threads)
-  int TB = (dtype == QSV_C64 && max_k <= 3) ? 9 : kRegThreadBits;
-  if (const char* e = std::getenv("QSV_TILE_THREAD_BITS")) TB = std::atoi(e) == 9 ? 9 : 8;
-  if (dtype == QSV_C128 || max_k > 3) TB = kRegThreadBits;
-  const int RB = (dtype == QSV_C64 ? 13 : 12) - TB;
+  // 512-thread kernel would spill, and complex128 has no 512-thread shape)
+  if ((dtype == QSV_C128 || max_k > 3) && TB == 9) TB = kRegThreadBits;
+  // register bits: the rest of the tile; instantiated shapes (register bits,
+  // thread bits): complex64 (4, 9), (4, 8), (5, 8), (4, 7); complex128 (4, 8), (4, 7)
+  const int RB = L - TB;
+  const bool rb_ok = RB == 4 || (dtype == QSV_C64 && RB == 5 && TB == 8);
   p->thread_bits = TB;
-  p->reg_bits = (L == RB + TB && n >= L) ? RB : 0;
+  p->reg_bits = (rb_ok && n >= L) ? RB : 0;
   p->circ_copy = *c;
   int rc = build_plan(p);
   std::vector<int> moffs;

@@ -71,32 +71,34 @@ def test_mixed_gates(dt, kw):
         assert err <= AMP_TOL[dt], (err, info)
 
 
-# complex64 tiles run as 512 threads x 16 amplitudes (default) or 256 x 32
-WG = [("c128", "8"), ("c64", "9"), ("c64", "8")]
+# register-resident tile shapes (thread bits, tile qubits; 0 = default 12):
+# 256 threads x 16 amplitudes (default), 512 x 16, 256 x 32 (complex64), 128 x 16
+WG = [("c128", "8", 0), ("c128", "7", 11), ("c64", "8", 0), ("c64", "9", 13), ("c64", "8", 13),
+      ("c64", "7", 11)]
 
 
-@pytest.mark.parametrize("dt,tb", WG)
+@pytest.mark.parametrize("dt,tb,tile", WG)
 @pytest.mark.parametrize("max_k", [1, 2, 3])
-def test_register_resident_tiles(dt, tb, max_k, monkeypatch):
-    # default tiles (13 local qubits for complex64, 12 for complex128) run
-    # register-resident once the state is at least one tile; max_k=3 also
-    # exercises blocks applied through LDS inside a register-resident pass
+def test_register_resident_tiles(dt, tb, tile, max_k, monkeypatch):
+    # tiles run register-resident once the state is at least one tile; max_k=3
+    # also exercises blocks applied through LDS inside a register-resident pass
     monkeypatch.setenv("QSV_TILE_THREAD_BITS", tb)
     for n, seed in ((13, 3), (14, 4), (16, 5)):
         gates = mixed_circuit(n, 220, seed)
-        got, info = fused_state(n, gates, dt, max_k=max_k)
+        got, info = fused_state(n, gates, dt, max_k=max_k, tile_qubits=tile)
+        assert info["segments"] > 0  # the register-resident kernel ran
         ref = O.run_circuit(n, gates)
         err = np.max(np.abs(got - ref))
         assert err <= AMP_TOL[dt], (n, err, info)
 
 
-@pytest.mark.parametrize("dt,tb", WG)
-def test_register_resident_layered_and_random(dt, tb, monkeypatch):
+@pytest.mark.parametrize("dt,tb,tile", WG)
+def test_register_resident_layered_and_random(dt, tb, tile, monkeypatch):
     monkeypatch.setenv("QSV_TILE_THREAD_BITS", tb)
     n = 16
     for gates in (W.layered_rx_rz_cnot(n, 10, seed_key=(2, n)), W.random_u_cz(n, 20, seed_key=(1, n))):
         for max_k in (1, 2):
-            got, info = fused_state(n, gates, dt, max_k=max_k)
+            got, info = fused_state(n, gates, dt, max_k=max_k, tile_qubits=tile)
             assert np.max(np.abs(got - O.run_circuit(n, gates))) <= AMP_TOL[dt], info
 
 
