@@ -230,6 +230,11 @@ int qsv_observable_add_term(qsv_observable* o, double coef, const int* qubits,
  * pointer may be NULL. Terms sharing a flip mask share one pass over the state. */
 int qsv_observable_info(const qsv_observable* o, int* n, int* terms, int* groups);
 
+/* Number of state passes an expectation (or qsv_apply_observable) of this
+ * observable takes for states of dtype `dtype`: its flip masks packed into
+ * tiles of 2^12 (complex64) or 2^11 (complex128) amplitudes. Host-only. */
+int qsv_observable_passes(const qsv_observable* o, qsv_dtype dtype, int* passes);
+
 /* <psi|O|psi> accumulated in double (section 4.5, get_expectation_value). The
  * state is not normalised first (basic gates need not be unitary). Synchronises
  * the state's stream. */

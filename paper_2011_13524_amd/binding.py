@@ -48,6 +48,7 @@ _SIGS = {
     "qsv_observable_free": (_c.c_int, [_vp]),
     "qsv_observable_add_term": (_c.c_int, [_vp, _c.c_double, _ip, _ip, _c.c_int]),
     "qsv_observable_info": (_c.c_int, [_vp, _ip, _ip, _ip]),
+    "qsv_observable_passes": (_c.c_int, [_vp, _c.c_int, _ip]),
     "qsv_expectation": (_c.c_int, [_vp, _vp, _dp]),
     "qsv_circuit_create": (_c.c_int, [_c.c_int, _c.POINTER(_vp)]),
     "qsv_circuit_free": (_c.c_int, [_vp]),
@@ -229,6 +230,12 @@ class Observable:
         n, t, g = _c.c_int(), _c.c_int(), _c.c_int()
         check(lib().qsv_observable_info(self.h, _c.byref(n), _c.byref(t), _c.byref(g)))
         return n.value, t.value, g.value
+
+    def passes(self, dtype: str = "c64") -> int:
+        """State passes an expectation of this observable takes (host-only)."""
+        p = _c.c_int()
+        check(lib().qsv_observable_passes(self.h, QSV_C64 if dtype == "c64" else QSV_C128, _c.byref(p)))
+        return p.value
 
     def __del__(self):
         try:

@@ -27,6 +27,7 @@
 namespace qsv {
 
 int expectation_tiled(qsv_state* s, const qsv_observable* o, double* out);
+int expectation_passes(const qsv_observable* o, qsv_dtype dt);
 
 constexpr int kRedThreads = 256;
 constexpr int kMaxRedBlocks = 2048;
@@ -296,6 +297,15 @@ int qsv_observable_add_term(qsv_observable* o, double coef, const int* qubits, c
   }
   o->drop_plans();
   o->terms.push_back(t);
+  return QSV_OK;
+}
+
+int qsv_observable_passes(const qsv_observable* o, qsv_dtype dtype, int* passes) {
+  clear_error();
+  if (!o) return fail(QSV_EINVAL, "null observable");
+  if (!passes) return fail(QSV_EINVAL, "null output");
+  if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_EDTYPE, "unknown dtype");
+  *passes = expectation_passes(o, dtype);
   return QSV_OK;
 }
 

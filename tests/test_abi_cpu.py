@@ -132,6 +132,17 @@ def test_planner_on_host():
     assert _code(Q.Plan, c, "c64", 5, 8, 6) == EINVAL
 
 
+def test_observable_pass_packing_on_host():
+    # flip masks of the 200-term weight-4 observable on 30 qubits packed into
+    # 2^12-amplitude tiles: far fewer passes than distinct masks
+    o = Q.Observable(30, W.random_pauli_observable(30, 200, 4, seed_key=(2, 1)))
+    n, terms, groups = o.info()
+    assert (n, terms, groups) == (30, 200, 186)
+    assert o.passes("c64") <= 30 and o.passes("c128") <= 32
+    assert Q.Observable(4, [(1.0, [(0, 3)])]).passes("c64") == 1  # pure Z: one pass
+    assert Q.Observable(4, []).passes("c64") == 0
+
+
 def test_merge_never_raises_arithmetic():
     rng = np.random.default_rng(3)
     u1 = W.haar_unitary(rng, 2)
