@@ -203,6 +203,11 @@ constexpr int kAdjMaxRows = 64;  // gradient rows per pass (LDS slots)
 template <typename R, int NR, int P>
 __device__ __forceinline__ double grad_xy(const cx<R>* s, const cx<R>* l, cx<R>* os, cx<R>* ol, bool ypauli,
                                           const cx<R>* __restrict__ u) {
+  if constexpr ((1 << P) >= NR) {  // no such register bit (never selected)
+    reg_copy<R, NR>(s, os);
+    reg_copy<R, NR>(l, ol);
+    return 0.0;
+  }
   const cx<R> u00 = u[0], u01 = u[1], u10 = u[2], u11 = u[3];
   double acc = 0.0;
 #pragma unroll
@@ -227,6 +232,11 @@ __device__ __forceinline__ double grad_xy(const cx<R>* s, const cx<R>* l, cx<R>*
 template <typename R, int NR, int P>
 __device__ __forceinline__ double grad_z(const cx<R>* s, const cx<R>* l, cx<R>* os, cx<R>* ol, int fixed,
                                          const cx<R>* __restrict__ u) {
+  if constexpr (P >= 0 && (1 << P) >= NR) {  // no such register bit (never selected)
+    reg_copy<R, NR>(s, os);
+    reg_copy<R, NR>(l, ol);
+    return 0.0;
+  }
   const cx<R> f0 = u[0], f1 = u[3];
   double acc = 0.0;
 #pragma unroll
@@ -539,8 +549,9 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
   // amplitudes per state), at most kAdjMaxRows gradient rows per pass
   const int Lc = sizeof(R) == 4 ? 12 : 11;
   const int L = std::min(n, Lc);
-  const bool reg = sizeof(R) == 4 && n >= 12;
-  const SegCfg cfg{4, 8, true};
+  // complex64: 256 threads x 16 amplitudes per state; complex128: 256 x 8
+  const bool reg = n >= Lc;
+  const SegCfg cfg{sizeof(R) == 4 ? 4 : 3, 8, sizeof(R) == 4};
   const int b = std::min(L, sizeof(R) == 4 ? 4 : 3);  // 128-byte contiguous runs
   const uint64_t low = (uint64_t(1) << b) - 1;
   std::vector<std::vector<int>> pass_ops;
@@ -705,14 +716,14 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
     return fin(fail(QSV_EHIP, "tiled sweep table upload failed"));
   double* part = reinterpret_cast<double*>(d + o_part);
   hipLaunchKernelGGL(k_zero_doubles, dim3(256), dim3(256), 0, st, part, uint64_t(nrows) * G);
-  if constexpr (sizeof(R) == 4) {
+  {
     if (reg) {
-      // register-resident passes (complex64 only): tile + gradient slots
+      // register-resident passes: tile + gradient slots
       const size_t lds = (size_t(1) << L) * sizeof(cx<R>) + size_t(kAdjMaxRows) * (256 / 64) * sizeof(double);
       for (size_t pi = 0; pi < hp.size(); ++pi) {
         ProfScope ps("adjoint", 4.0 * sizeof(cx<R>) * double(dim(n)), st);
 #define QSV_ADJR_LAUNCH(KM)                                                                      \
-    hipLaunchKernelGGL((k_adj_reg<R, 4, KM, 8>), dim3(G), dim3(256), lds, st,                      \
+    hipLaunchKernelGGL((k_adj_reg<R, sizeof(R) == 4 ? 4 : 3, KM, 8>), dim3(G), dim3(256), lds, st, \
                        static_cast<R*>(psi->ptr), static_cast<R*>(lam->ptr),                      \
                        reinterpret_cast<const TilePassDev*>(d), int(pi),                          \
                        reinterpret_cast<const RegSegDev*>(d + o_segs),                            \

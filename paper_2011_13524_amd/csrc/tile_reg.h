@@ -103,6 +103,15 @@ __device__ __forceinline__ void lds_op(cx<R>* t, const TileOpDev& op, const cx<R
 // (loops run over the compressed index g and insert the target bits), so the
 // per-thread amplitude array stays in VGPRs.
 
+// Register bits that do not exist for NR elements (a variant compiled for a
+// larger register file): the variant copies v to o unchanged; the planner
+// never selects it.
+template <typename R, int NR>
+__device__ __forceinline__ void reg_copy(const cx<R>* v, cx<R>* o) {
+#pragma unroll
+  for (int i = 0; i < NR; ++i) o[i] = v[i];
+}
+
 template <int P>
 __device__ __forceinline__ constexpr int ins1(int g) {
   return ((g >> P) << (P + 1)) | (g & ((1 << P) - 1));
@@ -121,6 +130,10 @@ __device__ __forceinline__ constexpr int ins2(int g) {
 template <typename R, int NR, int P, bool HASC>
 __device__ __forceinline__ void reg_dense1(const cx<R>* v, cx<R>* o, const cx<R>* __restrict__ m,
                                            uint32_t cm, uint32_t cv) {
+  if constexpr ((1 << P) >= NR) {
+    reg_copy<R, NR>(v, o);
+    return;
+  }
   const cx<R> m00 = m[0], m01 = m[1], m10 = m[2], m11 = m[3];
 #pragma unroll
   for (int g = 0; g < NR / 2; ++g) {
@@ -137,6 +150,10 @@ __device__ __forceinline__ void reg_dense1(const cx<R>* v, cx<R>* o, const cx<R>
 template <typename R, int NR, int P, bool HASC>
 __device__ __forceinline__ void reg_swap1(const cx<R>* v, cx<R>* o, const cx<R>* __restrict__,
                                           uint32_t cm, uint32_t cv) {
+  if constexpr ((1 << P) >= NR) {
+    reg_copy<R, NR>(v, o);
+    return;
+  }
 #pragma unroll
   for (int g = 0; g < NR / 2; ++g) {
     const int i = ins1<P>(g), j = i | (1 << P);
@@ -150,6 +167,10 @@ __device__ __forceinline__ void reg_swap1(const cx<R>* v, cx<R>* o, const cx<R>*
 template <typename R, int NR, int A, int B, bool HASC>
 __device__ __forceinline__ void reg_dense2(const cx<R>* v, cx<R>* o, const cx<R>* __restrict__ m,
                                            uint32_t cm, uint32_t cv) {
+  if constexpr ((1 << A) >= NR || (1 << B) >= NR) {
+    reg_copy<R, NR>(v, o);
+    return;
+  }
   const cx<R> k0 = m[0], k1 = m[1], k2 = m[2], k3 = m[3], k4 = m[4], k5 = m[5], k6 = m[6],
               k7 = m[7], k8 = m[8], k9 = m[9], k10 = m[10], k11 = m[11], k12 = m[12],
               k13 = m[13], k14 = m[14], k15 = m[15];
@@ -175,6 +196,10 @@ __device__ __forceinline__ void reg_dense2(const cx<R>* v, cx<R>* o, const cx<R>
 template <typename R, int NR, int A, int B, bool HASC>
 __device__ __forceinline__ void reg_diag(const cx<R>* v, cx<R>* o, const cx<R>* g, uint32_t cm,
                                          uint32_t cv) {
+  if constexpr ((A >= 0 && (1 << A) >= NR) || (B >= 0 && (1 << B) >= NR)) {
+    reg_copy<R, NR>(v, o);
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < NR; ++i) {
     const int idx = (A >= 0 ? (i >> A) & 1 : 0) | (B >= 0 ? ((i >> B) & 1) << 1 : 0);
