@@ -110,8 +110,10 @@ __device__ __forceinline__ double uni(double v) {
                           __builtin_amdgcn_readfirstlane(__double2loint(v)));
 }
 __device__ __forceinline__ uint64_t uni(uint64_t v) {
-  return (uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(v >> 32))) << 32) |
-         __builtin_amdgcn_readfirstlane(uint32_t(v));
+  // (readfirstlane yields a signed int: widen through uint32_t, no sign extension)
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(v >> 32)));
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(v)));
+  return (uint64_t(hi) << 32) | lo;
 }
 
 // Streaming of tiles through registers into LDS. Workgroups are persistent:

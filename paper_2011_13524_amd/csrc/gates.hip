@@ -57,27 +57,31 @@ __device__ __forceinline__ void pair_update(cx<R>* va, cx<R>* vb, const M2<R>& u
 
 template <typename R, int VEC, int KIND>
 __global__ void __launch_bounds__(256) k_pair(R* __restrict__ psi, const PairArgs<R> a) {
-  const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= a.nthreads) return;
-  const uint64_t x0 = insert_zeros(t * VEC, a.pos, a.m) | a.or_mask;
-  cx<R> va[VEC], vb[VEC];
-  AmpIO<R, VEC>::load(psi, x0 + a.offA, va);
-  AmpIO<R, VEC>::load(psi, x0 + a.offB, vb);
-  pair_update<R, VEC, KIND>(va, vb, a.u);
-  AmpIO<R, VEC>::store(psi, x0 + a.offA, va);
-  AmpIO<R, VEC>::store(psi, x0 + a.offB, vb);
+  // grid-stride: launches stay within 2^32 work-items for any state size
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < a.nthreads; t += stride) {
+    const uint64_t x0 = insert_zeros(t * VEC, a.pos, a.m) | a.or_mask;
+    cx<R> va[VEC], vb[VEC];
+    AmpIO<R, VEC>::load(psi, x0 + a.offA, va);
+    AmpIO<R, VEC>::load(psi, x0 + a.offB, vb);
+    pair_update<R, VEC, KIND>(va, vb, a.u);
+    AmpIO<R, VEC>::store(psi, x0 + a.offA, va);
+    AmpIO<R, VEC>::store(psi, x0 + a.offB, vb);
+  }
 }
 
 // complex64 one-qubit gate on qubit 0: the pair (x0, x0 + 1) is one 16-byte vector.
 template <int KIND>
 __global__ void __launch_bounds__(256) k_pair_adj(float* __restrict__ psi, const PairArgs<float> a) {
-  const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= a.nthreads) return;
-  const uint64_t x0 = insert_zeros(t, a.pos, a.m) | a.or_mask;
-  cx<float> v[2];
-  AmpIO<float, 2>::load(psi, x0, v);
-  pair_update<float, 1, KIND>(&v[0], &v[1], a.u);
-  AmpIO<float, 2>::store(psi, x0, v);
+  // grid-stride: launches stay within 2^32 work-items for any state size
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < a.nthreads; t += stride) {
+    const uint64_t x0 = insert_zeros(t, a.pos, a.m) | a.or_mask;
+    cx<float> v[2];
+    AmpIO<float, 2>::load(psi, x0, v);
+    pair_update<float, 1, KIND>(&v[0], &v[1], a.u);
+    AmpIO<float, 2>::store(psi, x0, v);
+  }
 }
 
 template <typename R>
@@ -91,14 +95,16 @@ struct ScaleArgs {
 
 template <typename R, int VEC>
 __global__ void __launch_bounds__(256) k_scale(R* __restrict__ psi, const ScaleArgs<R> a) {
-  const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= a.nthreads) return;
-  const uint64_t x = insert_zeros(t * VEC, a.pos, a.m) | a.pattern;
-  cx<R> v[VEC];
-  AmpIO<R, VEC>::load(psi, x, v);
-#pragma unroll
-  for (int j = 0; j < VEC; ++j) v[j] = a.c * v[j];
-  AmpIO<R, VEC>::store(psi, x, v);
+  // grid-stride: launches stay within 2^32 work-items for any state size
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < a.nthreads; t += stride) {
+    const uint64_t x = insert_zeros(t * VEC, a.pos, a.m) | a.pattern;
+    cx<R> v[VEC];
+    AmpIO<R, VEC>::load(psi, x, v);
+  #pragma unroll
+    for (int j = 0; j < VEC; ++j) v[j] = a.c * v[j];
+    AmpIO<R, VEC>::store(psi, x, v);
+  }
 }
 
 template <typename R>
@@ -114,19 +120,21 @@ struct DiagArgs {
 
 template <typename R, int VEC>
 __global__ void __launch_bounds__(256) k_diag(R* __restrict__ psi, const DiagArgs<R> a) {
-  const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= a.nthreads) return;
-  const uint64_t x = insert_zeros(t * VEC, a.pos, a.m) | a.or_mask;
-  cx<R> v[VEC];
-  AmpIO<R, VEC>::load(psi, x, v);
-#pragma unroll
-  for (int j = 0; j < VEC; ++j) {
-    const uint64_t xj = x + j;
-    int idx = 0;
-    for (int b = 0; b < a.k; ++b) idx |= int((xj >> a.tq[b]) & 1) << b;
-    v[j] = a.d[idx] * v[j];
+  // grid-stride: launches stay within 2^32 work-items for any state size
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < a.nthreads; t += stride) {
+    const uint64_t x = insert_zeros(t * VEC, a.pos, a.m) | a.or_mask;
+    cx<R> v[VEC];
+    AmpIO<R, VEC>::load(psi, x, v);
+  #pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+      const uint64_t xj = x + j;
+      int idx = 0;
+      for (int b = 0; b < a.k; ++b) idx |= int((xj >> a.tq[b]) & 1) << b;
+      v[j] = a.d[idx] * v[j];
+    }
+    AmpIO<R, VEC>::store(psi, x, v);
   }
-  AmpIO<R, VEC>::store(psi, x, v);
 }
 
 template <typename R, int K>
@@ -145,18 +153,20 @@ __global__ void __launch_bounds__(256) k_dense(R* __restrict__ psi, const cx<R>*
   __shared__ cx<R> sm[D * D];
   for (int i = threadIdx.x; i < D * D; i += blockDim.x) sm[i] = mat[i];
   __syncthreads();
-  const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= a.nthreads) return;
-  const uint64_t x0 = insert_zeros(t, a.pos, a.m) | a.or_mask;
-  cx<R> v[D];
-#pragma unroll
-  for (int c = 0; c < D; ++c) v[c] = load1(psi, x0 + a.off[c]);
-#pragma unroll
-  for (int r = 0; r < D; ++r) {
-    cx<R> acc = {R(0), R(0)};
-#pragma unroll
-    for (int c = 0; c < D; ++c) acc = cfma(sm[r * D + c], v[c], acc);
-    store1(psi, x0 + a.off[r], acc);
+  // grid-stride: launches stay within 2^32 work-items for any state size
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < a.nthreads; t += stride) {
+    const uint64_t x0 = insert_zeros(t, a.pos, a.m) | a.or_mask;
+    cx<R> v[D];
+  #pragma unroll
+    for (int c = 0; c < D; ++c) v[c] = load1(psi, x0 + a.off[c]);
+  #pragma unroll
+    for (int r = 0; r < D; ++r) {
+      cx<R> acc = {R(0), R(0)};
+  #pragma unroll
+      for (int c = 0; c < D; ++c) acc = cfma(sm[r * D + c], v[c], acc);
+      store1(psi, x0 + a.off[r], acc);
+    }
   }
 }
 
@@ -172,9 +182,9 @@ inline cx<R> to_dev(cd a) {
 }
 
 int launch_grid(uint64_t nthreads, dim3* grid) {
-  const uint64_t blocks = (nthreads + 255) / 256;
-  if (blocks > 0x7fffffffull) return fail(QSV_ERANGE, "launch too large");
-  *grid = dim3(unsigned(blocks));
+  // at most 2^22 workgroups of 256 (2^30 work-items); kernels stride over the rest
+  const uint64_t blocks = std::min<uint64_t>((nthreads + 255) / 256, uint64_t(1) << 22);
+  *grid = dim3(unsigned(std::max<uint64_t>(blocks, 1)));
   return QSV_OK;
 }
 

@@ -3,6 +3,8 @@
 #include <cstdarg>
 #include <cstdio>
 
+#include <algorithm>
+
 #include "dev_common.h"
 #include "qsv_internal.h"
 
@@ -92,15 +94,17 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_set_basis(R* psi, uint64_t nvec, uint64_t k) {
   // each thread writes one 16-byte vector (2 amplitudes for complex64, 1 for complex128)
   constexpr int A = sizeof(R) == 4 ? 2 : 1;
-  const uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= nvec) return;
-  R v[4] = {0, 0, 0, 0};
-  const uint64_t x0 = t * A;
-  if (k >= x0 && k < x0 + A) v[2 * (k - x0)] = R(1);
-  if constexpr (A == 2)
-    *reinterpret_cast<float4*>(psi + 4 * t) = make_float4(v[0], v[1], v[2], v[3]);
-  else
-    *reinterpret_cast<double2*>(psi + 2 * t) = make_double2(v[0], v[1]);
+  // grid-stride: launches stay within 2^32 work-items for any state size
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t t = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < nvec; t += stride) {
+    R v[4] = {0, 0, 0, 0};
+    const uint64_t x0 = t * A;
+    if (k >= x0 && k < x0 + A) v[2 * (k - x0)] = R(1);
+    if constexpr (A == 2)
+      *reinterpret_cast<float4*>(psi + 4 * t) = make_float4(v[0], v[1], v[2], v[3]);
+    else
+      *reinterpret_cast<double2*>(psi + 2 * t) = make_double2(v[0], v[1]);
+  }
 }
 
 int check_state(const qsv_state* s) {
@@ -134,7 +138,7 @@ int ensure_reduce_scratch(qsv_state* s, size_t doubles) {
 static int set_basis_impl(qsv_state* s, uint64_t k) {
   const uint64_t N = dim(s->n);
   const uint64_t nvec = s->dtype == QSV_C64 ? (N + 1) / 2 : N;
-  const dim3 grid(unsigned((nvec + 255) / 256));
+  const dim3 grid(unsigned(std::min<uint64_t>((nvec + 255) / 256, uint64_t(1) << 22)));
   if (s->dtype == QSV_C64) {
     hipLaunchKernelGGL(k_set_basis<float>, grid, dim3(256), 0, s->stream,
                        static_cast<float*>(s->ptr), nvec, k);

@@ -88,6 +88,7 @@ def test_state_without_device():
         L.qsv_state_free(h)
         return
     assert L.qsv_state_alloc(0, 1, None, ctypes.byref(h)) == ERANGE
+    assert L.qsv_state_alloc(35, 1, None, ctypes.byref(h)) == ERANGE  # 2^35 amplitudes: beyond 34
     assert L.qsv_state_alloc(4, 7, None, ctypes.byref(h)) == EDTYPE
 
 
