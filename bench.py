@@ -60,7 +60,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--fd-params", type=int, default=6)
     ap.add_argument("--batch-items", type=int, default=512)
-    ap.add_argument("--leg", choices=["adjoint_24q", "batch_vqe", "random_26q", "adjoint_32q"],
+    ap.add_argument("--leg", choices=["adjoint_24q", "batch_vqe", "random_26q", "adjoint_32q",
+                                      "autotune_30q"],
                     help="run only this extra leg and print its JSON (for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also copy the state once (a device copy of known size, used to "
@@ -261,9 +262,12 @@ def random_leg(Q, W):
     for dt in ("c64", "c128"):
         s = Q.State(n, dt)
         plan = Q.Plan(circ, dt, max_k=2)
+        t0 = time.perf_counter()
+        tuned = Q.Plan.autotune(circ, s, reps=1)  # fusion width and tile shape by measurement
+        t_tune = time.perf_counter() - t0
         r = {}
-        for mode in ("unfused", "fused"):
-            f = (lambda: Q.apply_circuit(s, circ)) if mode == "unfused" else (lambda: Q.apply_fused(s, plan))
+        for mode, pl in (("unfused", None), ("fused", plan), ("fused_autotuned", tuned)):
+            f = (lambda: Q.apply_circuit(s, circ)) if pl is None else (lambda: Q.apply_fused(s, pl))
             f()
             sync(Q, s)
             t0 = time.perf_counter()
@@ -272,7 +276,26 @@ def random_leg(Q, W):
             t = time.perf_counter() - t0
             r[mode] = {"s": t, "gates_per_s": len(gates) / t}
         r["passes"] = plan.info()["passes"]
+        r["autotune"] = {"choice": tuned.choice, "passes": tuned.info()["passes"], "tuning_s": t_tune}
         out[dt] = r
+    return out
+
+
+def autotune_leg(Q, W, n=30):
+    """The headline circuit's plan picked by the autotuner vs the default plan."""
+    gates = W.layered_rx_rz_cnot(n, 10, seed_key=(2,))
+    circ = Q.Circuit.from_records(n, gates)
+    s = Q.State(n, "c64")
+    t0 = time.perf_counter()
+    tuned = Q.Plan.autotune(circ, s, reps=1)
+    out = {"tuning_s": time.perf_counter() - t0, "choice": tuned.choice}
+    for name, pl in (("default", Q.Plan(circ, "c64", max_k=2)), ("autotuned", tuned)):
+        Q.apply_fused(s, pl)
+        sync(Q, s)
+        t0 = time.perf_counter()
+        Q.apply_fused(s, pl)
+        sync(Q, s)
+        out[name + "_ms"] = (time.perf_counter() - t0) * 1e3
     return out
 
 
@@ -289,7 +312,8 @@ def main():
     if args.leg:
         legs = {"adjoint_24q": lambda: adjoint_leg(Q, W, args.fd_params),
                 "batch_vqe": lambda: batch_leg(Q, W, args.batch_items),
-                "random_26q": lambda: random_leg(Q, W), "adjoint_32q": lambda: adjoint32_leg(Q, W)}
+                "random_26q": lambda: random_leg(Q, W), "adjoint_32q": lambda: adjoint32_leg(Q, W),
+                "autotune_30q": lambda: autotune_leg(Q, W)}
         print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
         return
 
@@ -392,6 +416,7 @@ def main():
         out["batch_vqe"] = batch_leg(Q, W, args.batch_items)
         out["random_26q"] = random_leg(Q, W)
         out["adjoint_32q"] = adjoint32_leg(Q, W)
+        out["autotune_30q"] = autotune_leg(Q, W)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, gates, args.cpu_seconds)
     print(json.dumps(out), flush=True)

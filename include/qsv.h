@@ -184,6 +184,22 @@ int qsv_apply_circuit(qsv_state* s, const qsv_circuit* c, const double* theta);
 int qsv_plan_fused(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qubits,
                    int low_qubits, qsv_plan** out);
 
+/* Autotuned plan (section 5.4: the fusion width is a tuning choice): builds
+ * candidate plans over fusion widths max_k = 1, 2, 3 and tile shapes
+ * (tile qubits, thread bits) = (12, 8), (11, 7) and, for complex64, (13, 9)
+ * and (13, 8), times `reps` (1..100) fused applications of each on `scratch`
+ * (a state of the circuit's width and the plan's dtype, on its stream, after
+ * one untimed warm-up application) with HIP events, and returns the fastest
+ * in *out (caller frees with qsv_plan_free). choice (may be NULL) receives
+ * int[4]: max_k, tile qubits, thread bits, register bits (0 = LDS kernel).
+ * The contents of `scratch` are overwritten with the circuit applied
+ * (1 + reps) times per candidate. Blocks the calling thread. Errors:
+ * QSV_EINVAL (null arguments, reps out of range, null theta for a
+ * parametric circuit, no candidate fits), QSV_ERANGE (width mismatch),
+ * QSV_EHIP (a launch or event failed; no plan is returned). */
+int qsv_plan_autotune(const qsv_circuit* c, qsv_state* scratch, const double* theta, int reps,
+                      qsv_plan** out, int* choice);
+
 /* Number of passes, fused blocks and original gates (any out pointer may be NULL). */
 int qsv_plan_info(const qsv_plan* p, int* passes, int* blocks, int* gates);
 

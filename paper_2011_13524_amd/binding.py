@@ -58,6 +58,7 @@ _SIGS = {
     "qsv_circuit_info": (_c.c_int, [_vp, _ip, _ip, _ip]),
     "qsv_apply_circuit": (_c.c_int, [_vp, _vp, _dp]),
     "qsv_plan_fused": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.POINTER(_vp)]),
+    "qsv_plan_autotune": (_c.c_int, [_vp, _vp, _dp, _c.c_int, _c.POINTER(_vp), _ip]),
     "qsv_plan_info": (_c.c_int, [_vp, _ip, _ip, _ip]),
     "qsv_plan_free": (_c.c_int, [_vp]),
     "qsv_plan_stats": (_c.c_int, [_vp, _ip, _ip, _ip]),
@@ -326,6 +327,20 @@ class Plan:
                                    tile_qubits, low_qubits, _c.byref(h)))
         self.h = h
         self.dtype = dtype
+
+    @classmethod
+    def autotune(cls, circ: Circuit, scratch: "State", theta=None, reps: int = 3) -> "Plan":
+        """Fastest plan over fusion widths and tile shapes (qsv_plan_autotune);
+        overwrites `scratch`. The choice is in `plan.choice`."""
+        keep, tp = _theta_ptr(theta)
+        h = _vp()
+        ch = (_c.c_int * 4)()
+        check(lib().qsv_plan_autotune(circ.h, scratch.h, tp, reps, _c.byref(h), ch))
+        self = cls.__new__(cls)
+        self.h = h
+        self.dtype = scratch.dtype
+        self.choice = {"max_k": ch[0], "tile_qubits": ch[1], "thread_bits": ch[2], "reg_bits": ch[3]}
+        return self
 
     def info(self):
         p, b, g = _c.c_int(), _c.c_int(), _c.c_int()

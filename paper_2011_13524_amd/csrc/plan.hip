@@ -877,25 +877,27 @@ static int apply_fused_t(qsv_state* s, qsv_plan* p, const double* theta) {
   return QSV_OK;
 }
 
-}  // namespace qsv
+// Releases a plan and its device tables (keeps the error message).
+static void plan_release(qsv_plan* p) {
+  if (!p) return;
+  if (p->stage_used) (void)hipEventSynchronize(p->stage_ev);
+  if (p->stage_ev) (void)hipEventDestroy(p->stage_ev);
+  if (p->h_stage) (void)hipHostFree(p->h_stage);
+  if (p->d_pool) (void)hipFree(p->d_pool);
+  if (p->d_pass) (void)hipFree(p->d_pass);
+  if (p->d_ops) (void)hipFree(p->d_ops);
+  if (p->d_segs) (void)hipFree(p->d_segs);
+  if (p->d_rops) (void)hipFree(p->d_rops);
+  delete p;
+}
 
-using namespace qsv;
-
-extern "C" {
-
-int qsv_plan_fused(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qubits, int low_qubits,
-                   qsv_plan** out) {
-  clear_error();
-  if (!out) return fail(QSV_EINVAL, "null output handle");
+// Plan with an explicit register tile shape (thread bits TB); tile_qubits /
+// low_qubits 0 select the defaults.
+static int plan_create(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qubits, int low_qubits,
+                       int TB, qsv_plan** out) {
   *out = nullptr;
-  if (!c) return fail(QSV_EINVAL, "null circuit");
-  if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_EDTYPE, "unknown dtype");
-  if (max_k < 1 || max_k > 5) return fail(QSV_EINVAL, "max_k must be in 1..5");
   const int n = c->n;
-  // default tile: 2^12 amplitudes (256 threads x 16 in registers; 32 KiB of
-  // LDS for complex64, so several workgroups per compute unit hide latency)
   int L = tile_qubits > 0 ? tile_qubits : 12;
-  if (const char* e = std::getenv("QSV_TILE_QUBITS"); e && tile_qubits <= 0) L = std::atoi(e);  // tuning
   // low qubits always local: 2^b amplitudes form one contiguous run, 128 bytes
   // (one cache line) at the default; fewer fixed low qubits leave more local
   // qubits free for the circuit, so fewer passes
@@ -913,16 +915,6 @@ int qsv_plan_fused(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qu
   p->max_k = max_k;
   p->L = L;
   p->b = b;
-  // register-resident passes: 2^TB threads x 2^(L - TB) amplitudes. Default
-  // 256 threads (TB = 8) x 16: measured on MI355X, 2^12-amplitude tiles with
-  // 256 threads beat 2^13 with 512 threads (6% at 30 qubits complex64, more
-  // workgroups in flight per compute unit) despite more passes.
-  // QSV_TILE_THREAD_BITS (7, 8, 9) and QSV_TILE_QUBITS override for tuning.
-  int TB = kRegThreadBits;
-  if (const char* e = std::getenv("QSV_TILE_THREAD_BITS")) {
-    const int v = std::atoi(e);
-    TB = v == 9 ? 9 : (v == 7 ? 7 : 8);
-  }
   // (blocks of 4-5 qubits run through LDS with 32-amplitude temporaries: the
   // 512-thread kernel would spill, and complex128 has no 512-thread shape)
   if ((dtype == QSV_C128 || max_k > 3) && TB == 9) TB = kRegThreadBits;
@@ -938,12 +930,111 @@ int qsv_plan_fused(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qu
   size_t pool_elems = 0;
   if (!rc) rc = upload_tables(p, moffs, pool_elems);
   if (rc) {
-    if (p->d_pass) (void)hipFree(p->d_pass);
-    if (p->d_ops) (void)hipFree(p->d_ops);
-    delete p;
+    plan_release(p);
     return rc;
   }
   *out = p;
+  return QSV_OK;
+}
+
+}  // namespace qsv
+
+using namespace qsv;
+
+extern "C" {
+
+int qsv_plan_fused(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qubits, int low_qubits,
+                   qsv_plan** out) {
+  clear_error();
+  if (!out) return fail(QSV_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!c) return fail(QSV_EINVAL, "null circuit");
+  if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_EDTYPE, "unknown dtype");
+  if (max_k < 1 || max_k > 5) return fail(QSV_EINVAL, "max_k must be in 1..5");
+  // default tile: 2^12 amplitudes over 256 threads (TB = 8) x 16 in registers:
+  // measured on MI355X, 2^12-amplitude tiles with 256 threads beat 2^13 with
+  // 512 threads (6% at 30 qubits complex64, more workgroups in flight per
+  // compute unit) despite more passes. QSV_TILE_QUBITS and
+  // QSV_TILE_THREAD_BITS (7, 8, 9) override the defaults; qsv_plan_autotune
+  // picks by measurement.
+  int L = tile_qubits;
+  if (const char* e = std::getenv("QSV_TILE_QUBITS"); e && tile_qubits <= 0) L = std::atoi(e);
+  int TB = kRegThreadBits;
+  if (const char* e = std::getenv("QSV_TILE_THREAD_BITS")) {
+    const int v = std::atoi(e);
+    TB = v == 9 ? 9 : (v == 7 ? 7 : 8);
+  }
+  return plan_create(c, dtype, max_k, L, low_qubits, TB, out);
+}
+
+int qsv_plan_autotune(const qsv_circuit* c, qsv_state* scratch, const double* theta, int reps,
+                      qsv_plan** out, int* choice) {
+  clear_error();
+  if (!out) return fail(QSV_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!c) return fail(QSV_EINVAL, "null circuit");
+  int rc = check_state(scratch);
+  if (rc) return rc;
+  if (scratch->n != c->n) return fail(QSV_ERANGE, "circuit has %d qubits, state %d", c->n, scratch->n);
+  if (c->nparams > 0 && !theta) return fail(QSV_EINVAL, "circuit has parameters but theta is null");
+  if (reps < 1 || reps > 100) return fail(QSV_EINVAL, "reps must be in 1..100");
+  const qsv_dtype dt = scratch->dtype;
+  // candidates: (max_k, tile qubits, thread bits)
+  struct Cand { int k, L, TB; };
+  std::vector<Cand> cands;
+  for (int k : {1, 2, 3}) {
+    cands.push_back({k, 12, 8});
+    cands.push_back({k, 11, 7});
+    if (dt == QSV_C64) {
+      cands.push_back({k, 13, 9});
+      cands.push_back({k, 13, 8});
+    }
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  QSV_HIP_CHECK(hipEventCreate(&e0));
+  QSV_HIP_CHECK(hipEventCreate(&e1));
+  qsv_plan* best = nullptr;
+  float best_ms = 0.f;
+  int best_i = -1;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    qsv_plan* p = nullptr;
+    if (plan_create(c, dt, cands[i].k, cands[i].L, 0, cands[i].TB, &p) != QSV_OK) {
+      clear_error();  // a shape that does not fit this circuit is skipped
+      continue;
+    }
+    int r = qsv_apply_fused(scratch, p, theta);  // warm-up (uploads tables)
+    if (!r) r = hipEventRecord(e0, scratch->stream) == hipSuccess ? QSV_OK : QSV_EHIP;
+    for (int k = 0; k < reps && !r; ++k) r = qsv_apply_fused(scratch, p, theta);
+    float ms = 0.f;
+    if (!r) r = hipEventRecord(e1, scratch->stream) == hipSuccess ? QSV_OK : QSV_EHIP;
+    if (!r) r = hipEventSynchronize(e1) == hipSuccess ? QSV_OK : QSV_EHIP;
+    if (!r) r = hipEventElapsedTime(&ms, e0, e1) == hipSuccess ? QSV_OK : QSV_EHIP;
+    if (r) {
+      plan_release(p);
+      plan_release(best);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return fail(r, "autotune: timing a candidate failed");
+    }
+    if (!best || ms < best_ms) {
+      plan_release(best);
+      best = p;
+      best_ms = ms;
+      best_i = int(i);
+    } else {
+      plan_release(p);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!best) return fail(QSV_EINVAL, "autotune: no candidate plan fits this circuit");
+  if (choice) {
+    choice[0] = cands[best_i].k;
+    choice[1] = best->L;
+    choice[2] = best->thread_bits;
+    choice[3] = best->reg_bits;
+  }
+  *out = best;
   return QSV_OK;
 }
 
@@ -970,16 +1061,7 @@ int qsv_plan_stats(const qsv_plan* p, int* segments, int* lds_ops, int* kmax) {
 
 int qsv_plan_free(qsv_plan* p) {
   clear_error();
-  if (!p) return QSV_OK;
-  if (p->stage_used) (void)hipEventSynchronize(p->stage_ev);
-  if (p->stage_ev) (void)hipEventDestroy(p->stage_ev);
-  if (p->h_stage) (void)hipHostFree(p->h_stage);
-  if (p->d_pool) (void)hipFree(p->d_pool);
-  if (p->d_pass) (void)hipFree(p->d_pass);
-  if (p->d_ops) (void)hipFree(p->d_ops);
-  if (p->d_segs) (void)hipFree(p->d_segs);
-  if (p->d_rops) (void)hipFree(p->d_rops);
-  delete p;
+  plan_release(p);
   return QSV_OK;
 }
 

@@ -10,6 +10,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2011_13524_amd import Circuit, Plan, State, apply_fused
+from paper_2011_13524_amd.binding import QsvError
 from paper_2011_13524_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -162,3 +163,32 @@ def test_qft_fused_matches_closed_form():
         apply_fused(s, p)
         ref = np.exp(2j * np.pi * np.arange(N) * k / N) / np.sqrt(N)
         assert np.max(np.abs(s.store() - ref)) <= 1e-12
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_autotuned_plan_matches_oracle(dt):
+    # the autotuner times candidate plans on a scratch state and returns the
+    # fastest; whichever it picks, the result is the circuit's
+    n = 16
+    gates, npar = W.ry_rz_cnot_ring(n, 3)
+    theta = W.uniform_angles(npar, (7, n))
+    c = Circuit.from_records(n, gates)
+    scratch = State(n, dt)
+    p = Plan.autotune(c, scratch, theta, reps=2)
+    ch = p.choice
+    assert ch["max_k"] in (1, 2, 3)
+    assert ch["tile_qubits"] in ((12, 11, 13) if dt == "c64" else (12, 11))
+    assert ch["thread_bits"] in (7, 8, 9)
+    assert ch["reg_bits"] == ch["tile_qubits"] - ch["thread_bits"]  # register-resident at 16 qubits
+    s = State(n, dt)
+    apply_fused(s, p, theta)
+    ref = O.run_circuit(n, gates, theta)
+    assert np.max(np.abs(s.store() - ref)) <= AMP_TOL[dt], ch
+    # the scratch state holds a unit vector (the circuit applied several times)
+    assert abs(np.linalg.norm(scratch.store()) - 1.0) <= 1e-4
+
+
+def test_autotune_rejects_mismatched_state():
+    c = Circuit.from_records(8, [{"op": "h", "q": [0]}])
+    with pytest.raises(QsvError):
+        Plan.autotune(c, State(9, "c64"))
