@@ -245,17 +245,19 @@ __device__ __forceinline__ double grad_z(const cx<R>* s, const cx<R>* l, cx<R>* 
     const cx<R> a = s[i], c = l[i];
     const double im = double(c.re) * a.im - double(c.im) * a.re;
     acc -= bit ? -im : im;
-    const cx<R> f = bit ? f1 : f0;
+    const cx<R> f = csel(bit != 0, f1, f0);
     os[i] = f * a;
     ol[i] = f * c;
   }
   return acc;
 }
 
+// Gradient op: share of the gradient from (s, l), the rotation applied into
+// (os, ol) (every element written).
 template <typename R, int NR>
-__device__ __forceinline__ double grad_apply(cx<R>* s, cx<R>* l, const RegOpDev& op, uint32_t tau,
-                                             uint64_t base, const cx<R>* __restrict__ u) {
-  cx<R> os[NR], ol[NR];
+__device__ __forceinline__ double grad_apply(const cx<R>* s, const cx<R>* l, cx<R>* os, cx<R>* ol,
+                                             const RegOpDev& op, uint32_t tau, uint64_t base,
+                                             const cx<R>* __restrict__ u) {
   double acc = 0.0;
   if (op.kind == 5) {
     const bool y = op.k == 2;
@@ -278,11 +280,6 @@ __device__ __forceinline__ double grad_apply(cx<R>* s, cx<R>* l, const RegOpDev&
       default: acc = grad_z<R, NR, -1>(s, l, os, ol, fixed, u); break;
     }
   }
-#pragma unroll
-  for (int i = 0; i < NR; ++i) {
-    s[i] = os[i];
-    l[i] = ol[i];
-  }
   return acc;
 }
 
@@ -301,19 +298,56 @@ __device__ __forceinline__ void adj_remap(cx<R> (&v)[1 << RB], const LdsMap<R, R
   else wave_sync();
 }
 
-// A block applied through LDS to one state held in registers.
+// A block applied through LDS to one state held in registers (v in, o out).
 template <typename R, int RB, int TB, int KMAX, typename SW>
-__device__ __forceinline__ void adj_lds_op(cx<R> (&v)[1 << RB], const LdsMap<R, RB, TB, SW>& ms, char* smem,
-                                           const TileOpDev& op, const cx<R>* pool, int L, uint64_t base,
-                                           SW sw) {
+__device__ __forceinline__ void adj_lds_op(const cx<R>* v, cx<R>* o, const LdsMap<R, RB, TB, SW>& ms,
+                                           char* smem, const TileOpDev& op, const cx<R>* pool, int L,
+                                           uint64_t base, SW sw) {
 #pragma unroll
   for (int i = 0; i < (1 << RB); ++i) ms.put(smem, i, v[i]);
   __syncthreads();
   lds_op<R, KMAX>(reinterpret_cast<cx<R>*>(smem), op, pool, L, base, sw);
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < (1 << RB); ++i) v[i] = ms.get(smem, i);
+  for (int i = 0; i < (1 << RB); ++i) o[i] = ms.get(smem, i);
   __syncthreads();
+}
+
+// One op of the reverse sweep on both states: reads (s, l) and writes every
+// element of (os, ol); gradient ops add this wavefront's share to its slot.
+template <typename R, int RB, int KMAX, int TB>
+__device__ __forceinline__ void adj_step(const RegOpDev& op, const cx<R>* s, const cx<R>* l, cx<R>* os,
+                                         cx<R>* ol, const RegSegDev& S, uint32_t tau, uint64_t base,
+                                         Swz<sizeof(R) == 4 ? 5 : 4> sw, char* smem,
+                                         const TileOpDev* __restrict__ lops, const cx<R>* __restrict__ pool,
+                                         int L, double* wslot) {
+  constexpr int NR = 1 << RB;
+  if ((base & op.gcm) != op.gcv) {  // non-local controls: uniform per tile
+    reg_copy<R, NR>(s, os);
+    reg_copy<R, NR>(l, ol);
+    return;
+  }
+  const cx<R>* m = pool + op.moff;
+  if (op.kind == 5 || op.kind == 6) {
+    double acc = grad_apply<R, NR>(s, l, os, ol, op, tau, base, m);
+#pragma unroll
+    for (int sft = 32; sft > 0; sft >>= 1) acc += __shfl_xor(acc, sft, 64);
+    if ((tau & 63) == 0) wslot[op.aux * (1 << (TB - 6))] += acc;
+    return;
+  }
+  if (op.kind == 3) {
+    const LdsMap<R, RB, TB, Swz<sizeof(R) == 4 ? 5 : 4>> ms(S, tau, sw, nullptr);
+    adj_lds_op<R, RB, TB, KMAX>(s, os, ms, smem, lops[op.lop], pool, L, base, sw);
+    adj_lds_op<R, RB, TB, KMAX>(l, ol, ms, smem, lops[op.lop], pool, L, base, sw);
+    return;
+  }
+  cx<R> gtab[4];
+  int a = op.p1, bb = op.p2;
+  if (op.kind == 2) diag_table<R>(op, m, tau, base, gtab, a, bb);
+  const int key = reg_key(op.kind, a, bb, op.ri_cm != 0 || op.ti_cm != 0);
+  const bool lane = (tau & op.ti_cm) == op.ti_cv;
+  reg_apply<R, NR>(s, os, key, m, gtab, op.ri_cm, op.ri_cv, lane);
+  reg_apply<R, NR>(l, ol, key, m, gtab, op.ri_cm, op.ri_cv, lane);
 }
 
 template <typename R, int RB, int KMAX, int TB>
@@ -356,7 +390,7 @@ __global__ void __launch_bounds__(1 << TB)
       if ((i >> k) & 1) x |= gbit(s.reg[k]);
     return x;
   };
-  cx<R> vs[NR], vl[NR];
+  cx<R> vs[NR], vl[NR], ws[NR], wl[NR];
   for (uint64_t g = g0; g < gend; ++g) {
     if (g > g0) base = ((base | ~gmask) + 1) & gmask;
     // HBM -> registers in the first segment's layout
@@ -388,30 +422,18 @@ __global__ void __launch_bounds__(1 << TB)
         adj_remap<R, RB, TB, Swz<SB>>(vl, mo, mn, xw, smem);
       }
       S = Sn;
-      for (int o = 0; o < S->op_count; ++o) {
-        const RegOpDev& op = rops[S->op_begin + o];
-        if ((base & op.gcm) != op.gcv) continue;  // non-local controls: uniform per tile
-        const cx<R>* m = pool + op.moff;
-        if (op.kind == 5 || op.kind == 6) {
-          double acc = grad_apply<R, NR>(vs, vl, op, tau, base, m);
-#pragma unroll
-          for (int sft = 32; sft > 0; sft >>= 1) acc += __shfl_xor(acc, sft, 64);
-          if ((tau & 63) == 0) slot[op.aux][wave] += acc;
-          continue;
+      // ops alternate between the register arrays (vs, vl) and (ws, wl)
+      const int oc = S->op_count, ob = S->op_begin;
+      for (int o = 0; o < oc; o += 2) {
+        adj_step<R, RB, KMAX, TB>(rops[ob + o], vs, vl, ws, wl, *S, tau, base, sw, smem, lops, pool, L,
+                                  &slot[0][wave]);
+        if (o + 1 < oc) {
+          adj_step<R, RB, KMAX, TB>(rops[ob + o + 1], ws, wl, vs, vl, *S, tau, base, sw, smem, lops, pool, L,
+                                    &slot[0][wave]);
+        } else {
+          reg_copy<R, NR>(ws, vs);
+          reg_copy<R, NR>(wl, vl);
         }
-        if (op.kind == 3) {
-          const LdsMap<R, RB, TB, Swz<SB>> ms(*S, tau, sw, nullptr);
-          adj_lds_op<R, RB, TB, KMAX, Swz<SB>>(vs, ms, smem, lops[op.lop], pool, L, base, sw);
-          adj_lds_op<R, RB, TB, KMAX, Swz<SB>>(vl, ms, smem, lops[op.lop], pool, L, base, sw);
-          continue;
-        }
-        if ((tau & op.ti_cm) != op.ti_cv) continue;  // controls on thread bits
-        cx<R> gtab[4];
-        int a = op.p1, bb = op.p2;
-        if (op.kind == 2) diag_table<R>(op, m, tau, base, gtab, a, bb);
-        const int key = reg_key(op.kind, a, bb, op.ri_cm != 0);
-        reg_apply<R, NR>(vs, key, m, gtab, op.ri_cm, op.ri_cv);
-        reg_apply<R, NR>(vl, key, m, gtab, op.ri_cm, op.ri_cv);
       }
     }
     // registers -> HBM in the last segment's layout

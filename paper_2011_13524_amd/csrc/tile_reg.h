@@ -112,6 +112,14 @@ __device__ __forceinline__ void reg_copy(const cx<R>* v, cx<R>* o) {
   for (int i = 0; i < NR; ++i) o[i] = v[i];
 }
 
+// Component-wise select: a conditional choice between two complex values
+// written on the scalars keeps both in registers (a select of whole structs
+// can become a select of their addresses, which pins the arrays in memory).
+template <typename R>
+__device__ __forceinline__ cx<R> csel(bool c, const cx<R>& a, const cx<R>& b) {
+  return {c ? a.re : b.re, c ? a.im : b.im};
+}
+
 template <int P>
 __device__ __forceinline__ constexpr int ins1(int g) {
   return ((g >> P) << (P + 1)) | (g & ((1 << P) - 1));
@@ -123,104 +131,110 @@ __device__ __forceinline__ constexpr int ins2(int g) {
   return ins1<hi>(ins1<lo>(g));
 }
 
-// Each variant writes EVERY element of `o` (updated or copied), so that after
-// a runtime switch over variants each register slot has one definition per
-// path: the compiler then keeps the array in VGPRs instead of merging
-// per-variant stores to different slots through memory.
+// Each variant reads v and writes EVERY element of o (updated or copied). The
+// kernels alternate two register arrays from op to op (v -> o, then o -> v),
+// so the values a variant produces already sit in the registers the next op
+// reads: no copies at the join after the switch over variants. A variant for
+// a register bit that does not exist for NR elements (compiled for a larger
+// register file, never selected) copies. Controlled variants (HASC) take the
+// per-element register-bit control (i & cm) == cv and the per-lane thread-bit
+// control `lane`.
 template <typename R, int NR, int P, bool HASC>
 __device__ __forceinline__ void reg_dense1(const cx<R>* v, cx<R>* o, const cx<R>* __restrict__ m,
-                                           uint32_t cm, uint32_t cv) {
+                                           uint32_t cm, uint32_t cv, bool lane) {
   if constexpr ((1 << P) >= NR) {
     reg_copy<R, NR>(v, o);
-    return;
-  }
-  const cx<R> m00 = m[0], m01 = m[1], m10 = m[2], m11 = m[3];
+  } else {
+    const cx<R> m00 = m[0], m01 = m[1], m10 = m[2], m11 = m[3];
 #pragma unroll
-  for (int g = 0; g < NR / 2; ++g) {
-    const int i = ins1<P>(g), j = i | (1 << P);
-    const cx<R> a = v[i], b = v[j];
-    const bool on = !HASC || (uint32_t(i) & cm) == cv;
-    const cx<R> na = cfma(m00, a, m01 * b), nb = cfma(m10, a, m11 * b);
-    o[i] = on ? na : a;
-    o[j] = on ? nb : b;
+    for (int g = 0; g < NR / 2; ++g) {
+      const int i = ins1<P>(g), j = i | (1 << P);
+      const cx<R> a = v[i], b = v[j];
+      const cx<R> na = cfma(m00, a, m01 * b), nb = cfma(m10, a, m11 * b);
+      if constexpr (HASC) {
+        const bool on = lane && (uint32_t(i) & cm) == cv;
+        o[i] = csel(on, na, a);
+        o[j] = csel(on, nb, b);
+      } else {
+        o[i] = na;
+        o[j] = nb;
+      }
+    }
   }
 }
 
 // Pauli-X exchange (X, CNOT on register bits): moves only.
 template <typename R, int NR, int P, bool HASC>
-__device__ __forceinline__ void reg_swap1(const cx<R>* v, cx<R>* o, const cx<R>* __restrict__,
-                                          uint32_t cm, uint32_t cv) {
+__device__ __forceinline__ void reg_swap1(const cx<R>* v, cx<R>* o, uint32_t cm, uint32_t cv, bool lane) {
   if constexpr ((1 << P) >= NR) {
     reg_copy<R, NR>(v, o);
-    return;
-  }
+  } else {
 #pragma unroll
-  for (int g = 0; g < NR / 2; ++g) {
-    const int i = ins1<P>(g), j = i | (1 << P);
-    const bool on = !HASC || (uint32_t(i) & cm) == cv;
-    o[i] = on ? v[j] : v[i];
-    o[j] = on ? v[i] : v[j];
+    for (int g = 0; g < NR / 2; ++g) {
+      const int i = ins1<P>(g), j = i | (1 << P);
+      const bool on = !HASC || (lane && (uint32_t(i) & cm) == cv);
+      o[i] = csel(on, v[j], v[i]);
+      o[j] = csel(on, v[i], v[j]);
+    }
   }
 }
 
 // Matrix index bit 0 <-> register bit A, bit 1 <-> register bit B.
 template <typename R, int NR, int A, int B, bool HASC>
 __device__ __forceinline__ void reg_dense2(const cx<R>* v, cx<R>* o, const cx<R>* __restrict__ m,
-                                           uint32_t cm, uint32_t cv) {
+                                           uint32_t cm, uint32_t cv, bool lane) {
   if constexpr ((1 << A) >= NR || (1 << B) >= NR) {
     reg_copy<R, NR>(v, o);
-    return;
-  }
-  const cx<R> k0 = m[0], k1 = m[1], k2 = m[2], k3 = m[3], k4 = m[4], k5 = m[5], k6 = m[6],
-              k7 = m[7], k8 = m[8], k9 = m[9], k10 = m[10], k11 = m[11], k12 = m[12],
-              k13 = m[13], k14 = m[14], k15 = m[15];
+  } else {
+    const cx<R> k0 = m[0], k1 = m[1], k2 = m[2], k3 = m[3], k4 = m[4], k5 = m[5], k6 = m[6],
+                k7 = m[7], k8 = m[8], k9 = m[9], k10 = m[10], k11 = m[11], k12 = m[12],
+                k13 = m[13], k14 = m[14], k15 = m[15];
 #pragma unroll
-  for (int g = 0; g < NR / 4; ++g) {
-    const int i0 = ins2<A, B>(g);
-    const int i1 = i0 | (1 << A), i2 = i0 | (1 << B), i3 = i0 | (1 << A) | (1 << B);
-    const bool on = !HASC || (uint32_t(i0) & cm) == cv;
-    const cx<R> x0 = v[i0], x1 = v[i1], x2 = v[i2], x3 = v[i3];
-    const cx<R> y0 = cfma(k3, x3, cfma(k2, x2, cfma(k1, x1, k0 * x0)));
-    const cx<R> y1 = cfma(k7, x3, cfma(k6, x2, cfma(k5, x1, k4 * x0)));
-    const cx<R> y2 = cfma(k11, x3, cfma(k10, x2, cfma(k9, x1, k8 * x0)));
-    const cx<R> y3 = cfma(k15, x3, cfma(k14, x2, cfma(k13, x1, k12 * x0)));
-    o[i0] = on ? y0 : x0;
-    o[i1] = on ? y1 : x1;
-    o[i2] = on ? y2 : x2;
-    o[i3] = on ? y3 : x3;
+    for (int g = 0; g < NR / 4; ++g) {
+      const int i0 = ins2<A, B>(g);
+      const int i1 = i0 | (1 << A), i2 = i0 | (1 << B), i3 = i0 | (1 << A) | (1 << B);
+      const bool on = !HASC || (lane && (uint32_t(i0) & cm) == cv);
+      const cx<R> x0 = v[i0], x1 = v[i1], x2 = v[i2], x3 = v[i3];
+      const cx<R> y0 = cfma(k3, x3, cfma(k2, x2, cfma(k1, x1, k0 * x0)));
+      const cx<R> y1 = cfma(k7, x3, cfma(k6, x2, cfma(k5, x1, k4 * x0)));
+      const cx<R> y2 = cfma(k11, x3, cfma(k10, x2, cfma(k9, x1, k8 * x0)));
+      const cx<R> y3 = cfma(k15, x3, cfma(k14, x2, cfma(k13, x1, k12 * x0)));
+      o[i0] = csel(on, y0, x0);
+      o[i1] = csel(on, y1, x1);
+      o[i2] = csel(on, y2, x2);
+      o[i3] = csel(on, y3, x3);
+    }
   }
 }
 
 // Diagonal factor on up to two register bits (A < B; -1: absent): the factor
 // of element i is g[(bit A of i) | (bit B of i) << 1], picked at compile time.
 template <typename R, int NR, int A, int B, bool HASC>
-__device__ __forceinline__ void reg_diag(const cx<R>* v, cx<R>* o, const cx<R>* g, uint32_t cm,
-                                         uint32_t cv) {
+__device__ __forceinline__ void reg_diag(const cx<R>* v, cx<R>* o, const cx<R>* g, uint32_t cm, uint32_t cv,
+                                         bool lane) {
   if constexpr ((A >= 0 && (1 << A) >= NR) || (B >= 0 && (1 << B) >= NR)) {
     reg_copy<R, NR>(v, o);
-    return;
-  }
+  } else {
 #pragma unroll
-  for (int i = 0; i < NR; ++i) {
-    const int idx = (A >= 0 ? (i >> A) & 1 : 0) | (B >= 0 ? ((i >> B) & 1) << 1 : 0);
-    const bool on = !HASC || (uint32_t(i) & cm) == cv;
-    o[i] = on ? g[idx] * v[i] : v[i];
+    for (int i = 0; i < NR; ++i) {
+      const int idx = (A >= 0 ? (i >> A) & 1 : 0) | (B >= 0 ? ((i >> B) & 1) << 1 : 0);
+      const bool on = !HASC || (lane && (uint32_t(i) & cm) == cv);
+      o[i] = csel(on, g[idx] * v[i], v[i]);
+    }
   }
 }
 
-// One flat switch over (op type, control presence, register bits): every case
-// writes every element of a fresh array, and a single copy follows. Keeping
-// the variants in one switch (rather than nested dispatchers) lets the
-// compiler keep the amplitude array in VGPRs. Keys: reg_key().
+// One flat switch over (op type, control presence, register bits). Keys:
+// reg_key().
 #define QSV_C1(SW, HC, P)                                                        \
   case ((SW) * 2 + (HC)) * 8 + (P):                                              \
-    if constexpr (SW) reg_swap1<R, NR, P, HC>(v, o, m, cm, cv);                  \
-    else reg_dense1<R, NR, P, HC>(v, o, m, cm, cv);                              \
+    if constexpr (SW) reg_swap1<R, NR, P, HC>(v, o, cm, cv, lane);               \
+    else reg_dense1<R, NR, P, HC>(v, o, m, cm, cv, lane);                        \
     break;
 #define QSV_C1P(SW, HC) QSV_C1(SW, HC, 0) QSV_C1(SW, HC, 1) QSV_C1(SW, HC, 2) QSV_C1(SW, HC, 3)
 #define QSV_C2(HC, A, B)                                                         \
   case 32 + (HC) * 64 + (A) * 8 + (B):                                           \
-    reg_dense2<R, NR, A, B, HC>(v, o, m, cm, cv);                                \
+    reg_dense2<R, NR, A, B, HC>(v, o, m, cm, cv, lane);                          \
     break;
 #define QSV_C2P4(HC)                                                             \
   QSV_C2(HC, 0, 1) QSV_C2(HC, 0, 2) QSV_C2(HC, 0, 3) QSV_C2(HC, 1, 0) QSV_C2(HC, 1, 2) \
@@ -231,7 +245,7 @@ __device__ __forceinline__ void reg_diag(const cx<R>* v, cx<R>* o, const cx<R>* 
   QSV_C2(HC, 4, 1) QSV_C2(HC, 4, 2) QSV_C2(HC, 4, 3)
 #define QSV_CD(HC, A, B)                                                         \
   case 160 + (HC) * 64 + ((A) + 1) * 8 + ((B) + 1):                              \
-    reg_diag<R, NR, A, B, HC>(v, o, g, cm, cv);                                  \
+    reg_diag<R, NR, A, B, HC>(v, o, g, cm, cv, lane);                            \
     break;
 #define QSV_CDP4(HC)                                                             \
   QSV_CD(HC, -1, -1) QSV_CD(HC, 0, -1) QSV_CD(HC, 1, -1) QSV_CD(HC, 2, -1)         \
@@ -250,9 +264,8 @@ __device__ __forceinline__ int reg_key(int kind, int a, int b, bool hc) {
 }
 
 template <typename R, int NR>
-__device__ __forceinline__ void reg_apply(cx<R>* v, int key, const cx<R>* m, const cx<R>* g,
-                                          uint32_t cm, uint32_t cv) {
-  cx<R> o[NR];
+__device__ __forceinline__ void reg_apply(const cx<R>* v, cx<R>* o, int key, const cx<R>* m, const cx<R>* g,
+                                          uint32_t cm, uint32_t cv, bool lane) {
   switch (key) {
     QSV_C1P(0, 0) QSV_C1P(0, 1) QSV_C1P(1, 0) QSV_C1P(1, 1)
     QSV_C2P4(0) QSV_C2P4(1)
@@ -264,18 +277,13 @@ __device__ __forceinline__ void reg_apply(cx<R>* v, int key, const cx<R>* m, con
           QSV_C2P5(0) QSV_C2P5(1)
           QSV_CDP5(0) QSV_CDP5(1)
           default:
-#pragma unroll
-            for (int i = 0; i < NR; ++i) o[i] = v[i];
-            break;
+            __builtin_unreachable();  // the planner emits only the keys above
         }
       } else {
-#pragma unroll
-        for (int i = 0; i < NR; ++i) o[i] = v[i];
+        __builtin_unreachable();
       }
       break;
   }
-#pragma unroll
-  for (int i = 0; i < NR; ++i) v[i] = o[i];
 }
 #undef QSV_C1
 #undef QSV_C1P
@@ -379,6 +387,41 @@ struct LdsMap {
   }
 };
 
+// One register-segment op: reads the register array v and writes every
+// element of o. Ops with non-local controls that do not match this tile copy;
+// ops on LDS (kind 3) go through the tile in LDS; controls on thread bits are
+// per lane.
+template <typename R, int RB, int KMAX, int TB>
+__device__ __forceinline__ void reg_step(const RegOpDev& op, const cx<R>* v, cx<R>* o, const RegSegDev& S,
+                                         uint32_t tau, uint64_t base, Swz<sizeof(R) == 4 ? 5 : 4> sw,
+                                         char* smem, const TileOpDev* __restrict__ lops,
+                                         const cx<R>* __restrict__ pool, int L) {
+  constexpr int NR = 1 << RB;
+  if ((base & op.gcm) != op.gcv) {  // non-local controls: uniform per tile
+    reg_copy<R, NR>(v, o);
+    return;
+  }
+  const cx<R>* m = pool + op.moff;
+  if (op.kind == 3) {
+    const LdsMap<R, RB, TB, Swz<sizeof(R) == 4 ? 5 : 4>> ms(S, tau, sw, nullptr);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) ms.put(smem, i, v[i]);
+    __syncthreads();
+    lds_op<R, KMAX>(reinterpret_cast<cx<R>*>(smem), lops[op.lop], pool, L, base, sw);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NR; ++i) o[i] = ms.get(smem, i);
+    __syncthreads();
+    return;
+  }
+  cx<R> g[4];
+  int a = op.p1, bb = op.p2;
+  if (op.kind == 2) diag_table<R>(op, m, tau, base, g, a, bb);
+  const bool lane = (tau & op.ti_cm) == op.ti_cv;
+  reg_apply<R, NR>(v, o, reg_key(op.kind, a, bb, op.ri_cm != 0 || op.ti_cm != 0), m, g, op.ri_cm, op.ri_cv,
+                   lane);
+}
+
 template <typename R, int RB, int KMAX, int TB>
 __global__ void __launch_bounds__(1 << TB)
     k_tile_reg(R* __restrict__ psi, const TilePassDev* __restrict__ passes, int pass_idx,
@@ -397,7 +440,7 @@ __global__ void __launch_bounds__(1 << TB)
   const uint32_t tau = threadIdx.x;
   auto gbit = [&](int p) -> uint64_t { return uint64_t(1) << (p < b ? p : P.hq[p - b]); };
 
-  cx<R> v[NR];
+  cx<R> v[NR], w[NR];
   // HBM -> registers in the first segment's layout
   const RegSegDev* S = &segs[P.seg_begin];
   uint64_t gthr = base;
@@ -452,27 +495,13 @@ __global__ void __launch_bounds__(1 << TB)
       else wave_sync();
     }
     S = Sn;
-    for (int o = 0; o < S->op_count; ++o) {
-      const RegOpDev& op = rops[S->op_begin + o];
-      if ((base & op.gcm) != op.gcv) continue;  // non-local controls: uniform per tile
-      const cx<R>* m = pool + op.moff;
-      if (op.kind == 3) {
-        const LdsMap<R, RB, TB, Swz<SB>> ms(*S, tau, sw, nullptr);
-#pragma unroll
-        for (int i = 0; i < NR; ++i) ms.put(smem, i, v[i]);
-        __syncthreads();
-        lds_op<R, KMAX>(t, lops[op.lop], pool, L, base, sw);
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < NR; ++i) v[i] = ms.get(smem, i);
-        __syncthreads();
-        continue;
-      }
-      if ((tau & op.ti_cm) != op.ti_cv) continue;  // controls on thread bits
-      cx<R> g[4];
-      int a = op.p1, bb = op.p2;
-      if (op.kind == 2) diag_table<R>(op, m, tau, base, g, a, bb);
-      reg_apply<R, NR>(v, reg_key(op.kind, a, bb, op.ri_cm != 0), m, g, op.ri_cm, op.ri_cv);
+    // ops alternate between the register arrays v and w (one op reads one and
+    // writes all of the other)
+    const int oc = S->op_count, ob = S->op_begin;
+    for (int o = 0; o < oc; o += 2) {
+      reg_step<R, RB, KMAX, TB>(rops[ob + o], v, w, *S, tau, base, sw, smem, lops, pool, L);
+      if (o + 1 < oc) reg_step<R, RB, KMAX, TB>(rops[ob + o + 1], w, v, *S, tau, base, sw, smem, lops, pool, L);
+      else reg_copy<R, 1 << RB>(w, v);
     }
   }
 
