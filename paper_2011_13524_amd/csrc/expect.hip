@@ -99,6 +99,11 @@ __device__ __forceinline__ double flip_sign(double v, uint32_t s) {
   return __hiloint2double(__double2hiint(v) ^ int(s << 31), __double2loint(v));
 }
 
+// v with its sign bit XOR-ed with bit 31 of m.
+__device__ __forceinline__ double xor_sign(double v, uint32_t m) {
+  return __hiloint2double(__double2hiint(v) ^ int(m), __double2loint(v));
+}
+
 __device__ __forceinline__ uint32_t ins0(uint32_t i, int hb) {
   return ((i >> hb) << (hb + 1)) | (i & ((1u << hb) - 1));
 }
@@ -120,16 +125,16 @@ __device__ __forceinline__ uint64_t uni(uint64_t v) {
 // workgroup b takes tiles b, b + grid, b + 2 grid, ... in that order (so its
 // partial sums have a fixed order), and the loads of its next tile are issued
 // before it computes on the current one.
-template <typename R, int NT>
+template <typename R, int NT, int LT = 0>
 struct ExpTileStream {
   static constexpr int V = sizeof(R) == 4 ? 2 : 1;
   static constexpr int NL = kExpTileMax / 2 / NT;  // at most 2048 loads (16-byte pairs or complex128)
   uint64_t xt;          // per-thread part of the element addresses
   uint64_t xk[NL];      // workgroup-uniform parts
   cx<R> buf[NL * V];
-  uint32_t TS;
+  uint32_t TS;          // tile size (a constant when LT > 0: LT tile qubits)
   __device__ __forceinline__ ExpTileStream(const ExpPassDev& P) {
-    TS = 1u << P.L;
+    TS = LT > 0 ? (1u << LT) : (1u << P.L);
     xt = exp_place(P, threadIdx.x * V);
 #pragma unroll
     for (int k = 0; k < NL; ++k) xk[k] = exp_place(P, uint32_t(k) * NT * V);
@@ -194,15 +199,34 @@ __device__ __forceinline__ void exp_stage_groups(const ExpPassDev& P, const ExpG
 __device__ __forceinline__ ExpGroupLds exp_group(const ExpPassDev& P, const ExpGroupDev* __restrict__ groups,
                                                  const ExpTermDev* __restrict__ terms, uint64_t base,
                                                  const ExpGroupLds* sg, int gi) {
-  ExpGroupLds r;
+  // (field by field: the two sources are read by separate loads, so the
+  // staged copy is read as LDS)
+  double re, im;
+  uint64_t zg;
+  uint32_t lf, zl;
+  int hbit, tb, tc;
   if (gi < kExpPreGroups) {
-    r = sg[gi];
+    re = sg[gi].re;
+    im = sg[gi].im;
+    zg = sg[gi].zg;
+    lf = sg[gi].lf;
+    zl = sg[gi].zl;
+    hbit = sg[gi].hbit;
+    tb = sg[gi].term_begin;
+    tc = sg[gi].term_count;
   } else {
     const ExpGroupDev G = groups[P.grp_begin + gi];
     const ExpTermDev T = terms[G.term_begin];
-    r = {T.re, T.im, T.zg, G.lf, T.zl, G.hbit, G.term_begin, G.term_count};
+    re = T.re;
+    im = T.im;
+    zg = T.zg;
+    lf = G.lf;
+    zl = T.zl;
+    hbit = G.hbit;
+    tb = G.term_begin;
+    tc = G.term_count;
   }
-  r = {uni(r.re), uni(r.im), uni(r.zg), uni(r.lf), uni(r.zl), uni(r.hbit), uni(r.term_begin), uni(r.term_count)};
+  ExpGroupLds r = {uni(re), uni(im), uni(zg), uni(lf), uni(zl), uni(hbit), uni(tb), uni(tc)};
   if (__popcll(base & r.zg) & 1) {
     r.re = -r.re;
     r.im = -r.im;
@@ -237,30 +261,66 @@ __device__ __forceinline__ void exp_term(const ExpTermDev* __restrict__ terms, c
   }
 }
 
+// Tile qubits of the fixed-size expectation kernel variant (32 KiB tiles).
+template <typename R>
+__host__ __device__ constexpr int exp_tile_bits() {
+  return sizeof(R) == 4 ? 12 : 11;
+}
+
+// One single-term group with flip mask lf != 0 over a tile: the sum over the
+// pairs (x, x ^ lf), x with bit hb clear, of Re (REAL) or Im of
+// conj(psi_y) psi_x with the term's local Z/Y sign, in FP64. x is the thread
+// part xt (tx = t + xt) OR-ed with a workgroup-uniform step part xs (disjoint
+// bits); likewise y = (xt ^ (lf & thread bits)) | (xs ^ lfs), so each step
+// adds a uniform offset to two per-thread LDS pointers. The sign splits the
+// same way: pt (per thread, in bit 31) XOR the uniform parity of xs & zl.
+template <typename R, bool REAL, bool FULL, int NP, int NT>
+__device__ __forceinline__ double exp_pairs(const cx<R>* tx, const cx<R>* ty, int hb, uint32_t lfs, uint32_t zl,
+                                            uint32_t pt, uint32_t TS, uint32_t tid) {
+  double sw = 0.0;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const uint32_t i0 = uint32_t(k) * NT;
+    if (i0 >= TS / 2) break;
+    if (FULL || i0 + tid < TS / 2) {
+      const uint32_t xs = uni(ins0(i0, hb));
+      const uint32_t su = uni(uint32_t(__popc(xs & zl) & 1) << 31);
+      const cx<R> a = tx[xs], b = ty[xs ^ lfs];
+      const double w = REAL ? double(b.re) * a.re + double(b.im) * a.im
+                            : double(b.re) * a.im - double(b.im) * a.re;
+      sw += xor_sign(w, pt ^ su);
+    }
+  }
+  return sw;
+}
+
 // <psi|O|psi> over the tiles of one pass. Products and sums are FP64 (the
 // product of two FP32 values is exact in FP64), so for complex64 states the
 // reduction adds no error beyond the stored amplitudes. Each workgroup sums its
 // tiles in a fixed order into partial[blockIdx.x] (added to the value of
-// earlier passes when accumulate is set). FULL: the tile has at least two
-// amplitudes per thread, so every loop below has a workgroup-uniform trip
-// count (no per-lane guards).
-template <typename R, bool FULL>
+// earlier passes when accumulate is set). MODE 0: any tile size (per-lane
+// guards); 1: the tile has at least two amplitudes per thread, so every loop
+// below has a workgroup-uniform trip count; 2: the tile has exp_tile_bits<R>()
+// qubits (trip counts known at compile time).
+template <typename R, int MODE>
 __global__ void __launch_bounds__(kExpThreadsE)
     k_expect_tile(const R* __restrict__ psi, const ExpPassDev* __restrict__ passes, int pass_idx,
                   const ExpGroupDev* __restrict__ groups, const ExpTermDev* __restrict__ terms,
                   double* __restrict__ partial, int accumulate, uint64_t ntiles) {
   constexpr int NT = kExpThreadsE;
   constexpr int NA = kExpTileMax / NT;  // amplitudes per thread, at most
+  constexpr bool FULL = MODE >= 1;
+  constexpr int LT = MODE == 2 ? exp_tile_bits<R>() : 0;
   extern __shared__ __align__(16) char smem[];
   __shared__ double red[NT / 64];
   __shared__ ExpTermLds et[kExpLdsTerms];
   __shared__ ExpGroupLds sg[kExpPreGroups];
   cx<R>* t = reinterpret_cast<cx<R>*>(smem);
   const ExpPassDev& P = passes[pass_idx];
-  const uint32_t TS = 1u << P.L;
+  const uint32_t TS = LT > 0 ? (1u << LT) : (1u << P.L);
   const uint32_t tid = threadIdx.x;
   exp_stage_groups(P, groups, terms, sg);
-  ExpTileStream<R, NT> io(P);
+  ExpTileStream<R, NT, LT> io(P);
   ExpTileRange tr(P, ntiles);
   double acc = 0.0;
   if (tr.g < tr.end) io.fetch(psi, tr.base);
@@ -283,7 +343,8 @@ __global__ void __launch_bounds__(kExpThreadsE)
       }
       if (G.lf == 0 && nt == 1) {
         // sum of +-|psi_x|^2: thread part of the sign once, uniform part per step
-        const uint32_t pt = __popc(tid & G.zl) & 1;
+        uint32_t pt = uint32_t(__popc(tid & G.zl) & 1) << 31;
+        asm volatile("" : "+v"(pt));  // keep the mask whole: one 3-way XOR per element
         double sum = 0.0;
 #pragma unroll
         for (int k = 0; k < NA; ++k) {
@@ -292,7 +353,7 @@ __global__ void __launch_bounds__(kExpThreadsE)
           if (FULL || j0 + tid < TS) {
             const cx<R> a = t[j0 + tid];
             const double p = double(a.re) * a.re + double(a.im) * a.im;
-            sum += flip_sign(p, pt ^ (__popc(j0 & G.zl) & 1));
+            sum += xor_sign(p, pt ^ uni(uint32_t(__popc(j0 & G.zl) & 1) << 31));
           }
         }
         acc += G.re * sum;
@@ -311,30 +372,20 @@ __global__ void __launch_bounds__(kExpThreadsE)
       } else {
         const int hb = G.hbit;
         const uint32_t lf = G.lf;
-        // pairs (x, x ^ lf) with bit hb of x clear: x = ins0(i) for i < TS/2,
-        // i = tid + step; ins0 places bits, so x = ins0(tid) | ins0(step)
-        const uint32_t xt = ins0(tid, hb);
         if (nt == 1) {
           // one term (the common case for random strings). A Hermitian term's
           // coefficient alpha i^nY is real (nY even) or imaginary (nY odd):
           // only Re or Im of w = conj(psi[y]) psi[x] counts
-          const uint32_t pt = __popc(xt & G.zl) & 1;
-          const bool real = G.im == 0.0;
-          double sw = 0.0;
-#pragma unroll
-          for (int k = 0; k < NA / 2; ++k) {
-            const uint32_t i0 = uint32_t(k) * NT;
-            if (i0 >= TS / 2) break;
-            if (FULL || i0 + tid < TS / 2) {
-              const uint32_t xs = ins0(i0, hb);
-              const uint32_t x = xt | xs;
-              const cx<R> a = t[x], bb = t[x ^ lf];
-              const double w = real ? double(bb.re) * a.re + double(bb.im) * a.im
-                                    : double(bb.re) * a.im - double(bb.im) * a.re;
-              sw += flip_sign(w, pt ^ (__popc(xs & G.zl) & 1));
-            }
-          }
-          acc += 2.0 * (real ? sw * G.re : -sw * G.im);
+          const uint32_t xt = ins0(tid, hb);
+          const uint32_t mt = uni(ins0(NT - 1, hb));  // local bits of the thread part
+          const cx<R>* tx = t + xt;
+          const cx<R>* ty = t + (xt ^ (lf & mt));
+          uint32_t pt = uint32_t(__popc(xt & G.zl) & 1) << 31;
+          asm volatile("" : "+v"(pt));  // keep the mask whole: one 3-way XOR per pair
+          if (G.im == 0.0)
+            acc += 2.0 * G.re * exp_pairs<R, true, FULL, NA / 2, NT>(tx, ty, hb, lf & ~mt, G.zl, pt, TS, tid);
+          else
+            acc -= 2.0 * G.im * exp_pairs<R, false, FULL, NA / 2, NT>(tx, ty, hb, lf & ~mt, G.zl, pt, TS, tid);
         } else {
           for (uint32_t i = tid; i < TS / 2; i += NT) {
             const uint32_t x = ins0(i, hb);
@@ -614,9 +665,12 @@ int expect_tiled_t(qsv_state* s, qsv_observable* o, double* out) {
   const uint64_t grid = std::min<uint64_t>(tiles, kExpGrid);
   if ((rc = ensure_reduce_scratch(s, size_t(grid) + 1))) return rc;
   const size_t lds = (size_t(1) << pl->L) * sizeof(cx<R>);
-  const bool full = (size_t(1) << pl->L) >= size_t(2 * kExpThreadsE);
-  const void* kfn = full ? reinterpret_cast<const void*>(&k_expect_tile<R, true>)
-                         : reinterpret_cast<const void*>(&k_expect_tile<R, false>);
+  // kernel variant: tile of the default size (compile-time trip counts), at
+  // least two amplitudes per thread, or any size
+  const int mode = pl->L == exp_tile_bits<R>() ? 2 : ((size_t(1) << pl->L) >= size_t(2 * kExpThreadsE) ? 1 : 0);
+  const void* kfn = mode == 2   ? reinterpret_cast<const void*>(&k_expect_tile<R, 2>)
+                    : mode == 1 ? reinterpret_cast<const void*>(&k_expect_tile<R, 1>)
+                                : reinterpret_cast<const void*>(&k_expect_tile<R, 0>);
   QSV_HIP_CHECK(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   char* d = static_cast<char*>(pl->dev);
   for (size_t pi = 0; pi < pl->passes.size(); ++pi) {
@@ -625,12 +679,15 @@ int expect_tiled_t(qsv_state* s, qsv_observable* o, double* out) {
     const auto* gd = reinterpret_cast<const ExpGroupDev*>(d + pl->off_groups);
     const auto* td = reinterpret_cast<const ExpTermDev*>(d + pl->off_terms);
     const R* psi = static_cast<const R*>(s->ptr);
-    if (full)
-      hipLaunchKernelGGL((k_expect_tile<R, true>), dim3(unsigned(grid)), dim3(kExpThreadsE), lds, s->stream,
-                         psi, pd, int(pi), gd, td, s->red, pi > 0 ? 1 : 0, tiles);
+    if (mode == 2)
+      hipLaunchKernelGGL((k_expect_tile<R, 2>), dim3(unsigned(grid)), dim3(kExpThreadsE), lds, s->stream, psi,
+                         pd, int(pi), gd, td, s->red, pi > 0 ? 1 : 0, tiles);
+    else if (mode == 1)
+      hipLaunchKernelGGL((k_expect_tile<R, 1>), dim3(unsigned(grid)), dim3(kExpThreadsE), lds, s->stream, psi,
+                         pd, int(pi), gd, td, s->red, pi > 0 ? 1 : 0, tiles);
     else
-      hipLaunchKernelGGL((k_expect_tile<R, false>), dim3(unsigned(grid)), dim3(kExpThreadsE), lds, s->stream,
-                         psi, pd, int(pi), gd, td, s->red, pi > 0 ? 1 : 0, tiles);
+      hipLaunchKernelGGL((k_expect_tile<R, 0>), dim3(unsigned(grid)), dim3(kExpThreadsE), lds, s->stream, psi,
+                         pd, int(pi), gd, td, s->red, pi > 0 ? 1 : 0, tiles);
     QSV_HIP_CHECK(hipGetLastError());
   }
   hipLaunchKernelGGL(k_exp_sum, dim3(1), dim3(kExpThreads), 0, s->stream, s->red, grid, s->red + grid);
