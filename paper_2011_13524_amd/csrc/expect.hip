@@ -40,10 +40,25 @@ struct ExpPassDev {
   int gpos[kExpMaxGlobal];
 };
 
+constexpr int kExpSteps = kExpTileMax / kExpThreadsE;  // per-thread steps over the largest tile
+
+// A flip-mask group of a pass, with its first term folded in and, for
+// expectation workgroups of kExpThreadsE threads, the workgroup-uniform parts
+// of each step's indices and signs (the same for every tile of the pass).
 struct ExpGroupDev {
-  uint32_t lf;  // flip mask in the tile's local index space
-  int hbit;     // a set bit of lf (pairs are enumerated with it clear)
+  double re, im;   // first term: alpha * i^nY
+  uint64_t zg;     // first term: sign mask on non-local qubits (global index space)
+  uint32_t lf;     // flip mask in the tile's local index space
+  uint32_t zl;     // first term: sign mask on local qubits
+  int hbit;        // a set bit of lf (pairs are enumerated with it clear)
   int term_begin, term_count;
+  uint32_t pad;
+  // lf != 0, step k (pair index k * kExpThreadsE + thread): the step part of
+  // x = ins0(pair index, hbit) and of y = x ^ lf outside the thread's bits
+  uint32_t offx[kExpSteps / 2], offy[kExpSteps / 2];
+  // bit 31: parity of (step part of x) & zl; for lf == 0 the step part of x
+  // is k * kExpThreadsE
+  uint32_t sgn[kExpSteps];
 };
 
 struct ExpTermDev {
@@ -173,61 +188,20 @@ struct ExpTileRange {
   __device__ __forceinline__ uint64_t next_base() const { return ((base | ~gmask) + 1) & gmask; }
 };
 
-// Group descriptors of a pass with the first term of each group, staged in
-// LDS once per workgroup; the sign of a term on non-local qubits (zg) is
-// applied per tile.
-constexpr int kExpPreGroups = 64;
-struct ExpGroupLds {
-  double re, im;  // first term's coefficient
-  uint64_t zg;
+// Group gi of the pass with its first term's sign for the tile at base
+// folded in (workgroup-uniform values, read through the scalar cache).
+struct ExpGroup {
+  double re, im;
   uint32_t lf, zl;
   int hbit, term_begin, term_count;
+  const ExpGroupDev* d;
 };
 
-__device__ __forceinline__ void exp_stage_groups(const ExpPassDev& P, const ExpGroupDev* __restrict__ groups,
-                                                 const ExpTermDev* __restrict__ terms, ExpGroupLds* sg) {
-  const int ng = min(P.grp_count, kExpPreGroups);
-  for (int i = threadIdx.x; i < ng; i += blockDim.x) {
-    const ExpGroupDev G = groups[P.grp_begin + i];
-    const ExpTermDev T = terms[G.term_begin];
-    sg[i] = {T.re, T.im, T.zg, G.lf, T.zl, G.hbit, G.term_begin, G.term_count};
-  }
-}
-
-// Group gi of the pass with its first term's sign for the tile at base
-// folded in, as workgroup-uniform values.
-__device__ __forceinline__ ExpGroupLds exp_group(const ExpPassDev& P, const ExpGroupDev* __restrict__ groups,
-                                                 const ExpTermDev* __restrict__ terms, uint64_t base,
-                                                 const ExpGroupLds* sg, int gi) {
-  // (field by field: the two sources are read by separate loads, so the
-  // staged copy is read as LDS)
-  double re, im;
-  uint64_t zg;
-  uint32_t lf, zl;
-  int hbit, tb, tc;
-  if (gi < kExpPreGroups) {
-    re = sg[gi].re;
-    im = sg[gi].im;
-    zg = sg[gi].zg;
-    lf = sg[gi].lf;
-    zl = sg[gi].zl;
-    hbit = sg[gi].hbit;
-    tb = sg[gi].term_begin;
-    tc = sg[gi].term_count;
-  } else {
-    const ExpGroupDev G = groups[P.grp_begin + gi];
-    const ExpTermDev T = terms[G.term_begin];
-    re = T.re;
-    im = T.im;
-    zg = T.zg;
-    lf = G.lf;
-    zl = T.zl;
-    hbit = G.hbit;
-    tb = G.term_begin;
-    tc = G.term_count;
-  }
-  ExpGroupLds r = {uni(re), uni(im), uni(zg), uni(lf), uni(zl), uni(hbit), uni(tb), uni(tc)};
-  if (__popcll(base & r.zg) & 1) {
+__device__ __forceinline__ ExpGroup exp_group(const ExpPassDev& P, const ExpGroupDev* __restrict__ groups,
+                                              uint64_t base, int gi) {
+  const ExpGroupDev& G = groups[P.grp_begin + gi];
+  ExpGroup r{G.re, G.im, G.lf, G.zl, G.hbit, G.term_begin, G.term_count, &G};
+  if (__popcll(base & G.zg) & 1) {
     r.re = -r.re;
     r.im = -r.im;
   }
@@ -235,7 +209,7 @@ __device__ __forceinline__ ExpGroupLds exp_group(const ExpPassDev& P, const ExpG
 }
 
 // Stages the terms of a multi-term group for the tile at base (sign folded in).
-__device__ __forceinline__ void exp_stage_terms(const ExpTermDev* __restrict__ terms, const ExpGroupLds& G,
+__device__ __forceinline__ void exp_stage_terms(const ExpTermDev* __restrict__ terms, const ExpGroup& G,
                                                 uint64_t base, ExpTermLds* et) {
   const int ns = min(G.term_count, kExpLdsTerms);
   for (int k = threadIdx.x; k < ns; k += blockDim.x) {
@@ -246,7 +220,7 @@ __device__ __forceinline__ void exp_stage_terms(const ExpTermDev* __restrict__ t
 }
 
 __device__ __forceinline__ void exp_term(const ExpTermDev* __restrict__ terms, const ExpTermLds* et,
-                                         const ExpGroupLds& G, uint64_t base, int k, double& re, double& im,
+                                         const ExpGroup& G, uint64_t base, int k, double& re, double& im,
                                          uint32_t& zl) {
   if (k < kExpLdsTerms) {
     re = et[k].re;
@@ -271,24 +245,23 @@ __host__ __device__ constexpr int exp_tile_bits() {
 // pairs (x, x ^ lf), x with bit hb clear, of Re (REAL) or Im of
 // conj(psi_y) psi_x with the term's local Z/Y sign, in FP64. x is the thread
 // part xt (tx = t + xt) OR-ed with a workgroup-uniform step part xs (disjoint
-// bits); likewise y = (xt ^ (lf & thread bits)) | (xs ^ lfs), so each step
-// adds a uniform offset to two per-thread LDS pointers. The sign splits the
-// same way: pt (per thread, in bit 31) XOR the uniform parity of xs & zl.
+// bits); likewise y = (xt ^ (lf & thread bits)) | (xs ^ (lf outside them)),
+// so each step adds a uniform offset to two per-thread LDS pointers. The sign
+// splits the same way: pt (per thread, in bit 31) XOR the uniform parity of
+// xs & zl. The uniform parts come precomputed with the group.
 template <typename R, bool REAL, bool FULL, int NP, int NT>
-__device__ __forceinline__ double exp_pairs(const cx<R>* tx, const cx<R>* ty, int hb, uint32_t lfs, uint32_t zl,
-                                            uint32_t pt, uint32_t TS, uint32_t tid) {
+__device__ __forceinline__ double exp_pairs(const cx<R>* tx, const cx<R>* ty, const ExpGroupDev& D, uint32_t pt,
+                                            uint32_t TS, uint32_t tid) {
   double sw = 0.0;
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
     const uint32_t i0 = uint32_t(k) * NT;
     if (i0 >= TS / 2) break;
     if (FULL || i0 + tid < TS / 2) {
-      const uint32_t xs = uni(ins0(i0, hb));
-      const uint32_t su = uni(uint32_t(__popc(xs & zl) & 1) << 31);
-      const cx<R> a = tx[xs], b = ty[xs ^ lfs];
+      const cx<R> a = tx[D.offx[k]], b = ty[D.offy[k]];
       const double w = REAL ? double(b.re) * a.re + double(b.im) * a.im
                             : double(b.re) * a.im - double(b.im) * a.re;
-      sw += xor_sign(w, pt ^ su);
+      sw += xor_sign(w, pt ^ D.sgn[k]);
     }
   }
   return sw;
@@ -314,12 +287,10 @@ __global__ void __launch_bounds__(kExpThreadsE)
   extern __shared__ __align__(16) char smem[];
   __shared__ double red[NT / 64];
   __shared__ ExpTermLds et[kExpLdsTerms];
-  __shared__ ExpGroupLds sg[kExpPreGroups];
   cx<R>* t = reinterpret_cast<cx<R>*>(smem);
   const ExpPassDev& P = passes[pass_idx];
   const uint32_t TS = LT > 0 ? (1u << LT) : (1u << P.L);
   const uint32_t tid = threadIdx.x;
-  exp_stage_groups(P, groups, terms, sg);
   ExpTileStream<R, NT, LT> io(P);
   ExpTileRange tr(P, ntiles);
   double acc = 0.0;
@@ -334,7 +305,7 @@ __global__ void __launch_bounds__(kExpThreadsE)
     }
     __syncthreads();  // tile (and, first time, the group table) in LDS
     for (int gi = 0; gi < P.grp_count; ++gi) {
-      const ExpGroupLds G = exp_group(P, groups, terms, base, sg, gi);
+      const ExpGroup G = exp_group(P, groups, base, gi);
       const int nt = G.term_count;
       if (nt > 1) {
         __syncthreads();
@@ -353,7 +324,7 @@ __global__ void __launch_bounds__(kExpThreadsE)
           if (FULL || j0 + tid < TS) {
             const cx<R> a = t[j0 + tid];
             const double p = double(a.re) * a.re + double(a.im) * a.im;
-            sum += xor_sign(p, pt ^ uni(uint32_t(__popc(j0 & G.zl) & 1) << 31));
+            sum += xor_sign(p, pt ^ G.d->sgn[k]);
           }
         }
         acc += G.re * sum;
@@ -377,15 +348,15 @@ __global__ void __launch_bounds__(kExpThreadsE)
           // coefficient alpha i^nY is real (nY even) or imaginary (nY odd):
           // only Re or Im of w = conj(psi[y]) psi[x] counts
           const uint32_t xt = ins0(tid, hb);
-          const uint32_t mt = uni(ins0(NT - 1, hb));  // local bits of the thread part
+          const uint32_t mt = ins0(NT - 1, hb);  // local bits of the thread part
           const cx<R>* tx = t + xt;
           const cx<R>* ty = t + (xt ^ (lf & mt));
           uint32_t pt = uint32_t(__popc(xt & G.zl) & 1) << 31;
           asm volatile("" : "+v"(pt));  // keep the mask whole: one 3-way XOR per pair
           if (G.im == 0.0)
-            acc += 2.0 * G.re * exp_pairs<R, true, FULL, NA / 2, NT>(tx, ty, hb, lf & ~mt, G.zl, pt, TS, tid);
+            acc += 2.0 * G.re * exp_pairs<R, true, FULL, NA / 2, NT>(tx, ty, *G.d, pt, TS, tid);
           else
-            acc -= 2.0 * G.im * exp_pairs<R, false, FULL, NA / 2, NT>(tx, ty, hb, lf & ~mt, G.zl, pt, TS, tid);
+            acc -= 2.0 * G.im * exp_pairs<R, false, FULL, NA / 2, NT>(tx, ty, *G.d, pt, TS, tid);
         } else {
           for (uint32_t i = tid; i < TS / 2; i += NT) {
             const uint32_t x = ins0(i, hb);
@@ -440,12 +411,10 @@ __global__ void __launch_bounds__(kExpThreads)
                      const ExpTermDev* __restrict__ terms, int accumulate, uint64_t ntiles) {
   extern __shared__ __align__(16) char smem[];
   __shared__ ExpTermLds et[kExpLdsTerms];
-  __shared__ ExpGroupLds sg[kExpPreGroups];
   cx<R>* t = reinterpret_cast<cx<R>*>(smem);
   const ExpPassDev& P = passes[pass_idx];
   const uint32_t TS = 1u << P.L;
   const uint32_t tid = threadIdx.x;
-  exp_stage_groups(P, groups, terms, sg);
   ExpTileStream<R, kExpThreads> io(P);
   const uint64_t yt = exp_place(P, tid);
   uint64_t yk[kObsOut];
@@ -467,7 +436,7 @@ __global__ void __launch_bounds__(kExpThreads)
     for (int k = 0; k < kObsOut; ++k) ar[k] = ai[k] = R(0);
     __syncthreads();  // tile (and, first time, the group table) in LDS
     for (int gi = 0; gi < P.grp_count; ++gi) {
-      const ExpGroupLds G = exp_group(P, groups, terms, base, sg, gi);
+      const ExpGroup G = exp_group(P, groups, base, gi);
       const int nt = G.term_count;
       if (nt > 1) {
         __syncthreads();
@@ -622,7 +591,24 @@ ExpPlan* build_exp_plan(const qsv_observable* o, qsv_dtype dt) {
           if (lpos[q] >= 0) td.zl |= 1u << lpos[q];
           else td.zg |= uint64_t(1) << q;
         }
+        if (k == G.begin) {
+          gd.re = td.re;
+          gd.im = td.im;
+          gd.zg = td.zg;
+          gd.zl = td.zl;
+        }
         p->terms.push_back(td);
+      }
+      // uniform step parts for kExpThreadsE-thread workgroups
+      auto ins0h = [](uint32_t i, int hb) { return ((i >> hb) << (hb + 1)) | (i & ((1u << hb) - 1)); };
+      const uint32_t mt = ins0h(kExpThreadsE - 1, gd.hbit);
+      for (int k = 0; k < kExpSteps; ++k) {
+        const uint32_t xs = lf ? ins0h(uint32_t(k) * kExpThreadsE, gd.hbit) : uint32_t(k) * kExpThreadsE;
+        if (lf && k < kExpSteps / 2) {
+          gd.offx[k] = xs;
+          gd.offy[k] = xs ^ (lf & ~mt);
+        }
+        if (!lf || k < kExpSteps / 2) gd.sgn[k] = uint32_t(__builtin_popcount(xs & gd.zl) & 1) << 31;
       }
       p->groups.push_back(gd);
     }
