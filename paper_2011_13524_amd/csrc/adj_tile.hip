@@ -285,9 +285,9 @@ __device__ __forceinline__ double grad_apply(const cx<R>* s, const cx<R>* l, cx<
 
 // Re-map of one state's registers through LDS (write in the old layout with
 // the folded map, read in the new one).
-template <typename R, int RB, int TB, typename SW>
-__device__ __forceinline__ void adj_remap(cx<R> (&v)[1 << RB], const LdsMap<R, RB, TB, SW>& mo,
-                                          const LdsMap<R, RB, TB, SW>& mn, bool xw, char* smem) {
+template <typename R, int RB, int TB>
+__device__ __forceinline__ void adj_remap(cx<R> (&v)[1 << RB], const LdsMap<R, RB, TB>& mo,
+                                          const LdsMap<R, RB, TB>& mn, bool xw, char* smem) {
 #pragma unroll
   for (int i = 0; i < (1 << RB); ++i) mo.put(smem, i, v[i]);
   if (xw) __syncthreads();
@@ -300,7 +300,7 @@ __device__ __forceinline__ void adj_remap(cx<R> (&v)[1 << RB], const LdsMap<R, R
 
 // A block applied through LDS to one state held in registers (v in, o out).
 template <typename R, int RB, int TB, int KMAX, typename SW>
-__device__ __forceinline__ void adj_lds_op(const cx<R>* v, cx<R>* o, const LdsMap<R, RB, TB, SW>& ms,
+__device__ __forceinline__ void adj_lds_op(const cx<R>* v, cx<R>* o, const LdsMap<R, RB, TB>& ms,
                                            char* smem, const TileOpDev& op, const cx<R>* pool, int L,
                                            uint64_t base, SW sw) {
 #pragma unroll
@@ -336,7 +336,7 @@ __device__ __forceinline__ void adj_step(const RegOpDev& op, const cx<R>* s, con
     return;
   }
   if (op.kind == 3) {
-    const LdsMap<R, RB, TB, Swz<sizeof(R) == 4 ? 5 : 4>> ms(S, tau, sw, nullptr);
+    const LdsMap<R, RB, TB> ms(S.get_reg, S.get_tcol, 0u, tau);
     adj_lds_op<R, RB, TB, KMAX>(s, os, ms, smem, lops[op.lop], pool, L, base, sw);
     adj_lds_op<R, RB, TB, KMAX>(l, ol, ms, smem, lops[op.lop], pool, L, base, sw);
     return;
@@ -417,9 +417,10 @@ __global__ void __launch_bounds__(1 << TB)
         // re-map both states through LDS (folded X / CNOT ops applied to both)
         const bool xw = Sn->xwave != 0;
         if (Sn->xwave == 2) __syncthreads();
-        const LdsMap<R, RB, TB, Swz<SB>> mo(*S, tau, sw, Sn), mn(*Sn, tau, sw, nullptr);
-        adj_remap<R, RB, TB, Swz<SB>>(vs, mo, mn, xw, smem);
-        adj_remap<R, RB, TB, Swz<SB>>(vl, mo, mn, xw, smem);
+        const LdsMap<R, RB, TB> mo(Sn->put_reg, Sn->put_tcol, Sn->put_tcst, tau);
+        const LdsMap<R, RB, TB> mn(Sn->get_reg, Sn->get_tcol, 0u, tau);
+        adj_remap<R, RB, TB>(vs, mo, mn, xw, smem);
+        adj_remap<R, RB, TB>(vl, mo, mn, xw, smem);
       }
       S = Sn;
       // ops alternate between the register arrays (vs, vl) and (ws, wl)

@@ -59,6 +59,13 @@ struct RegSegDev {
   // to position M x ^ mcst (folded X / controlled-X ops); mcol[p] = M e_p
   uint32_t mcol[kTileMaxHigh + 8];
   uint32_t mcst;
+  // LDS byte offsets, XOR-swizzled (filled by the planner for the plan's
+  // dtype): element i of the thread with index tau sits at
+  //   (tcst ^ XOR of tcol[k] over the set bits k of tau) ^ reg[i]
+  // put_*: the previous layout written through the map above (the re-map
+  // into this layout); get_*: this layout (tcst = 0).
+  uint32_t put_reg[1 << (kRegMaxBits - 1)], put_tcol[kRegMaxThreadBits], put_tcst;
+  uint32_t get_reg[1 << (kRegMaxBits - 1)], get_tcol[kRegMaxThreadBits];
 };
 
 struct RegOpDev {

@@ -614,6 +614,36 @@ int build_reg_segments(const SegCfg& cfg, const std::vector<TileOpDev>& ho, Tile
     out_segs.push_back(sd);
     d.seg_count++;
   }
+  // LDS address tables of the pass's segments: the tile's LDS index is
+  // swizzled by j ^ (j >> SB) ^ (j >> 2 SB) (low SB bits of each), linear over
+  // XOR, so the byte offset splits into a per-thread part (XOR of per-bit
+  // columns) and a per-element part
+  const int SB = c64 ? 5 : 4;
+  const uint32_t esz = c64 ? 8u : 16u;
+  auto swz = [SB](uint32_t j) {
+    const uint32_t m = (1u << SB) - 1;
+    return j ^ ((j >> SB) & m) ^ ((j >> (2 * SB)) & m);
+  };
+  for (int si = d.seg_begin; si < d.seg_begin + d.seg_count; ++si) {
+    RegSegDev& S = out_segs[size_t(si)];
+    for (int k = 0; k < TB; ++k) S.get_tcol[k] = swz(1u << S.thr[k]) * esz;
+    for (int i = 0; i < (1 << RB); ++i) {
+      uint32_t x = 0;
+      for (int k = 0; k < RB; ++k)
+        if (i >> k & 1) x |= 1u << S.reg[k];
+      S.get_reg[i] = swz(x) * esz;
+    }
+    if (si == d.seg_begin) continue;
+    const RegSegDev& O = out_segs[size_t(si) - 1];  // written through S's map
+    S.put_tcst = swz(S.mcst) * esz;
+    for (int k = 0; k < TB; ++k) S.put_tcol[k] = swz(S.mcol[O.thr[k]]) * esz;
+    for (int i = 0; i < (1 << RB); ++i) {
+      uint32_t x = 0;
+      for (int k = 0; k < RB; ++k)
+        if (i >> k & 1) x ^= S.mcol[O.reg[k]];
+      S.put_reg[i] = swz(x) * esz;
+    }
+  }
   return QSV_OK;
 }
 

@@ -341,33 +341,20 @@ __device__ __forceinline__ void wave_sync() {
 // LDS addresses of a layout. The swizzle is linear over XOR and a local index
 // is the XOR of its register part and its thread part, so the byte offset of
 // element i is the per-thread part XOR a part that depends only on i and the
-// layout (uniform across the workgroup: scalar registers). Kernels using it
-// declare no static LDS and put the tile first in their dynamic LDS, so it
-// starts at LDS address 0 and the base folds into the per-thread part: one
-// vector XOR per element remains.
-template <typename R, int RB, int TB, typename SW>
+// layout (uniform across the workgroup: a table the planner fills, read
+// through the scalar cache). Kernels using it declare no static LDS and put
+// the tile first in their dynamic LDS, so it starts at LDS address 0 and the
+// base folds into the per-thread part: one vector XOR per element remains.
+template <typename R, int RB, int TB>
 struct LdsMap {
-  uint32_t thr;       // swizzled thread part, in bytes
-  uint32_t reg[1 << RB];  // swizzled register part of element i, in bytes
-  // layout s; with map m, local index x is placed at m->mcol-image of x ^ m->mcst
-  __device__ __forceinline__ LdsMap(const RegSegDev& s, uint32_t tau, SW sw, const RegSegDev* m) {
-    uint32_t j = m ? m->mcst : 0u;
+  uint32_t thr;        // per-thread part, in bytes
+  const uint32_t* reg;  // per-element parts, in bytes (uniform)
+  __device__ __forceinline__ LdsMap(const uint32_t* regt, const uint32_t* tcol, uint32_t tcst, uint32_t tau)
+      : reg(regt) {
+    uint32_t j = tcst;
 #pragma unroll
-    for (int b = 0; b < TB; ++b)
-      if ((tau >> b) & 1) j ^= m ? m->mcol[s.thr[b]] : (1u << s.thr[b]);
-    thr = sw(j) * uint32_t(sizeof(cx<R>));
-    uint32_t basis[RB];
-#pragma unroll
-    for (int b = 0; b < RB; ++b)
-      basis[b] = sw(m ? m->mcol[s.reg[b]] : (1u << s.reg[b])) * uint32_t(sizeof(cx<R>));
-#pragma unroll
-    for (int i = 0; i < (1 << RB); ++i) {
-      uint32_t r = 0;
-#pragma unroll
-      for (int b = 0; b < RB; ++b)
-        if ((i >> b) & 1) r ^= basis[b];
-      reg[i] = r;
-    }
+    for (int b = 0; b < TB; ++b) j ^= tcol[b] & (0u - ((tau >> b) & 1));  // (branch-free)
+    thr = j;
   }
   typedef R R2 __attribute__((ext_vector_type(2)));
   typedef __attribute__((address_space(3))) R2 lds_r2;
@@ -403,7 +390,7 @@ __device__ __forceinline__ void reg_step(const RegOpDev& op, const cx<R>* v, cx<
   }
   const cx<R>* m = pool + op.moff;
   if (op.kind == 3) {
-    const LdsMap<R, RB, TB, Swz<sizeof(R) == 4 ? 5 : 4>> ms(S, tau, sw, nullptr);
+    const LdsMap<R, RB, TB> ms(S.get_reg, S.get_tcol, 0u, tau);
 #pragma unroll
     for (int i = 0; i < NR; ++i) ms.put(smem, i, v[i]);
     __syncthreads();
@@ -480,14 +467,14 @@ __global__ void __launch_bounds__(1 << TB)
       const bool xw = Sn->xwave != 0;
       if (Sn->xwave == 2) __syncthreads();
       {
-        const LdsMap<R, RB, TB, Swz<SB>> mo(*S, tau, sw, Sn);
+        const LdsMap<R, RB, TB> mo(Sn->put_reg, Sn->put_tcol, Sn->put_tcst, tau);
 #pragma unroll
         for (int i = 0; i < NR; ++i) mo.put(smem, i, v[i]);
       }
       if (xw) __syncthreads();
       else wave_sync();
       {
-        const LdsMap<R, RB, TB, Swz<SB>> mn(*Sn, tau, sw, nullptr);
+        const LdsMap<R, RB, TB> mn(Sn->get_reg, Sn->get_tcol, 0u, tau);
 #pragma unroll
         for (int i = 0; i < NR; ++i) v[i] = mn.get(smem, i);
       }
