@@ -316,12 +316,13 @@ __device__ __forceinline__ void adj_lds_op(const cx<R>* v, cx<R>* o, const LdsMa
 // One op of the reverse sweep on both states: reads (s, l) and writes every
 // element of (os, ol); gradient ops add this wavefront's share to its slot.
 template <typename R, int RB, int KMAX, int TB>
-__device__ __forceinline__ void adj_step(const RegOpDev& op, const cx<R>* s, const cx<R>* l, cx<R>* os,
+__device__ __forceinline__ void adj_step(const RegOpDev& opr, const cx<R>* s, const cx<R>* l, cx<R>* os,
                                          cx<R>* ol, const RegSegDev& S, uint32_t tau, uint64_t base,
                                          Swz<sizeof(R) == 4 ? 5 : 4> sw, char* smem,
                                          const TileOpDev* __restrict__ lops, const cx<R>* __restrict__ pool,
                                          int L, double* wslot) {
   constexpr int NR = 1 << RB;
+  const RegOpDev op = opr;  // (one burst of scalar loads)
   if ((base & op.gcm) != op.gcv) {  // non-local controls: uniform per tile
     reg_copy<R, NR>(s, os);
     reg_copy<R, NR>(l, ol);
@@ -344,10 +345,9 @@ __device__ __forceinline__ void adj_step(const RegOpDev& op, const cx<R>* s, con
   cx<R> gtab[4];
   int a = op.p1, bb = op.p2;
   if (op.kind == 2) diag_table<R>(op, m, tau, base, gtab, a, bb);
-  const int key = reg_key(op.kind, a, bb, op.ri_cm != 0 || op.ti_cm != 0);
   const bool lane = (tau & op.ti_cm) == op.ti_cv;
-  reg_apply<R, NR>(s, os, key, m, gtab, op.ri_cm, op.ri_cv, lane);
-  reg_apply<R, NR>(l, ol, key, m, gtab, op.ri_cm, op.ri_cv, lane);
+  reg_apply<R, NR>(s, os, op.key, m, gtab, op.ri_cm, op.ri_cv, lane);
+  reg_apply<R, NR>(l, ol, op.key, m, gtab, op.ri_cm, op.ri_cv, lane);
 }
 
 template <typename R, int RB, int KMAX, int TB>

@@ -81,6 +81,7 @@ struct RegOpDev {
   int moff;
   int lop;              // index of the equivalent TileOpDev (LDS execution)
   int aux;              // gradient: slot of its row in the pass
+  int key;              // kinds 0, 1, 2, 4: variant of the register op (reg_key)
 };
 
 // Register-resident layout of a tile: 2^reg_bits amplitudes per thread,

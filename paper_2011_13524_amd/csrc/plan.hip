@@ -609,6 +609,19 @@ int build_reg_segments(const SegCfg& cfg, const std::vector<TileOpDev>& ho, Tile
       } else {
         r.kind = 3;
       }
+      if (r.kind == 0 || r.kind == 1 || r.kind == 4) {
+        r.key = reg_key(r.kind, r.p1, r.p2, r.ri_cm != 0 || r.ti_cm != 0);
+      } else if (r.kind == 2) {
+        // register-bit targets of the diagonal, ascending (-1: absent)
+        int a = -1, b = -1;
+        for (int j = 0; j < o.k; ++j) {
+          if (r.dsrc[j] != 0) continue;
+          if (a < 0) a = r.dbit[j];
+          else b = r.dbit[j];
+        }
+        if (b >= 0 && b < a) std::swap(a, b);
+        r.key = reg_key(2, a, b, r.ri_cm != 0 || r.ti_cm != 0);
+      }
       out_rops.push_back(r);
     }
     out_segs.push_back(sd);

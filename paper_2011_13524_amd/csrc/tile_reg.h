@@ -256,7 +256,7 @@ __device__ __forceinline__ void reg_diag(const cx<R>* v, cx<R>* o, const cx<R>* 
 
 // kind 0 dense one-qubit, 1 dense two-qubit, 2 diagonal, 4 Pauli-X exchange;
 // a, b: register bits (diagonal: -1 when absent, a < b)
-__device__ __forceinline__ int reg_key(int kind, int a, int b, bool hc) {
+__host__ __device__ __forceinline__ int reg_key(int kind, int a, int b, bool hc) {
   const int h = hc ? 1 : 0;
   if (kind == 1) return 32 + h * 64 + a * 8 + b;
   if (kind == 2) return 160 + h * 64 + (a + 1) * 8 + (b + 1);
@@ -303,7 +303,9 @@ __device__ __forceinline__ void diag_table(const RegOpDev& op, const cx<R>* __re
   int fixed = 0, ja = 0, jb = 0;
   a = -1;
   b = -1;
-  for (int j = 0; j < op.k; ++j) {
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {  // (k <= 2)
+    if (j >= op.k) break;
     if (op.dsrc[j] == 1) fixed |= int((tau >> op.dbit[j]) & 1) << j;
     else if (op.dsrc[j] == 2) fixed |= int((base >> op.dbit[j]) & 1) << j;
     else if (a < 0) {
@@ -379,11 +381,12 @@ struct LdsMap {
 // ops on LDS (kind 3) go through the tile in LDS; controls on thread bits are
 // per lane.
 template <typename R, int RB, int KMAX, int TB>
-__device__ __forceinline__ void reg_step(const RegOpDev& op, const cx<R>* v, cx<R>* o, const RegSegDev& S,
+__device__ __forceinline__ void reg_step(const RegOpDev& opr, const cx<R>* v, cx<R>* o, const RegSegDev& S,
                                          uint32_t tau, uint64_t base, Swz<sizeof(R) == 4 ? 5 : 4> sw,
                                          char* smem, const TileOpDev* __restrict__ lops,
                                          const cx<R>* __restrict__ pool, int L) {
   constexpr int NR = 1 << RB;
+  const RegOpDev op = opr;  // (one burst of scalar loads)
   if ((base & op.gcm) != op.gcv) {  // non-local controls: uniform per tile
     reg_copy<R, NR>(v, o);
     return;
@@ -405,8 +408,7 @@ __device__ __forceinline__ void reg_step(const RegOpDev& op, const cx<R>* v, cx<
   int a = op.p1, bb = op.p2;
   if (op.kind == 2) diag_table<R>(op, m, tau, base, g, a, bb);
   const bool lane = (tau & op.ti_cm) == op.ti_cv;
-  reg_apply<R, NR>(v, o, reg_key(op.kind, a, bb, op.ri_cm != 0 || op.ti_cm != 0), m, g, op.ri_cm, op.ri_cv,
-                   lane);
+  reg_apply<R, NR>(v, o, op.key, m, g, op.ri_cm, op.ri_cv, lane);
 }
 
 template <typename R, int RB, int KMAX, int TB>
