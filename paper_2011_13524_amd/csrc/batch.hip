@@ -24,6 +24,9 @@
 namespace qsv {
 
 constexpr int kBatchThreads = 512;
+constexpr int kBatchMaxQ = 24;    // qubits per item
+constexpr int kBatchRows = 64;    // gradient rows per reverse pass (LDS slots)
+constexpr size_t kBatchStateLds = 65536;  // psi + lambda (whole states or tiles)
 
 enum BatchOpKind { BO_ROT = 0, BO_CZ = 1, BO_CNOT = 2, BO_DENSE1 = 3 };
 
@@ -41,6 +44,30 @@ struct BatchItem {
   int grp_begin, grp_count;
   int theta_off, grad_off, nparams;
   uint64_t psi_off, lam_off;  // amplitude offsets into the state buffer (global items)
+  // items whose states live in device memory run tile passes: forward passes
+  // [fp_begin, +fp_count), reverse passes [rp_begin, +rp_count); the 2x2
+  // matrices of the item's ops are computed per run into mats[mat_off + op]
+  int fp_begin, fp_count, rp_begin, rp_count;
+  int mat_off;
+};
+
+// A tile pass of a device-memory item: L local qubits (the low b ones and
+// hq[]), the others (gpos[], ascending) index the tiles.
+struct BatchPass {
+  int L, b, nh, ng;
+  int hq[kBatchMaxQ];
+  int gpos[kBatchMaxQ];
+  int op_begin, op_count, row_count;
+};
+
+// An op inside a tile pass. p0/p1: local positions of q0/q1 (-1: not local,
+// then the bit is read from the tile base at g0/g1). Dense targets are local.
+struct BTOp {
+  int kind;
+  int p0, p1, g0, g1;
+  int pauli, slot;  // ROT
+  int bop;          // index of the op in the item's op list (its matrix)
+  int row;          // reverse passes: gradient row in the pass (-1: none)
 };
 
 struct BatchGroup {
@@ -62,6 +89,9 @@ struct BatchArgs {
   double* grads;
   void* states;
   size_t lds_state_bytes;  // dynamic LDS available for psi + lambda
+  const BatchPass* passes;
+  const BTOp* tops;
+  void* mats;              // M2<R> per op of the device-memory items
 };
 
 __device__ __forceinline__ double wg_sum(double v, double* red) {
@@ -139,6 +169,213 @@ __device__ __forceinline__ void wg_apply_op(cx<R>* s, int n, const BatchOp& op, 
   __syncthreads();
 }
 
+// ---------------------------------------------------------------- tiled items
+//
+// Items whose psi and lambda do not fit in LDS together run the library's
+// tile-pass scheme inside their workgroup: a pass keeps L qubits local, the
+// workgroup streams the item's state through an LDS tile (psi, and lambda in
+// the reverse sweep) tile by tile and applies every op of the pass to it. The
+// planner puts ops into passes so that dense targets are local; CZ and CNOT
+// controls may be anywhere (a non-local bit is a constant of the tile). One
+// pass moves the state once, instead of once per gate.
+
+__device__ __forceinline__ uint32_t bt_bit(int p, int g, uint32_t j, uint32_t base) {
+  return p >= 0 ? (j >> p) & 1u : (base >> g) & 1u;
+}
+
+// Global index of local index j in the tile at base.
+__device__ __forceinline__ uint32_t bt_addr(const BatchPass& P, uint32_t base, uint32_t j) {
+  uint32_t x = base | (j & ((1u << P.b) - 1));
+  const uint32_t h = j >> P.b;
+  for (int i = 0; i < P.nh; ++i) x |= ((h >> i) & 1u) << P.hq[i];
+  return x;
+}
+
+__device__ __forceinline__ uint32_t bt_base(const BatchPass& P, uint32_t g) {
+  uint32_t base = 0;
+  for (int j = 0; j < P.ng; ++j) base |= ((g >> j) & 1u) << P.gpos[j];
+  return base;
+}
+
+template <typename R>
+__device__ __forceinline__ M2<R> m2_dag(const M2<R>& u) {
+  return {{u.m00.re, -u.m00.im}, {u.m10.re, -u.m10.im}, {u.m01.re, -u.m01.im}, {u.m11.re, -u.m11.im}};
+}
+
+template <typename R>
+__device__ __forceinline__ void bt_pair(cx<R>* t, int p, const M2<R>& u, uint32_t TS) {
+  const uint32_t bit = 1u << p;
+  for (uint32_t i = threadIdx.x; i < TS / 2; i += blockDim.x) {
+    const uint32_t x0 = ((i >> p) << (p + 1)) | (i & (bit - 1));
+    const cx<R> x = t[x0], y = t[x0 | bit];
+    t[x0] = cfma(u.m00, x, u.m01 * y);
+    t[x0 | bit] = cfma(u.m10, x, u.m11 * y);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void bt_cz(cx<R>* t, const BTOp& op, uint32_t TS, uint32_t base) {
+  for (uint32_t j = threadIdx.x; j < TS; j += blockDim.x)
+    if (bt_bit(op.p0, op.g0, j, base) & bt_bit(op.p1, op.g1, j, base)) t[j] = {-t[j].re, -t[j].im};
+}
+
+// CNOT: control q0 (anywhere), target q1 (local).
+template <typename R>
+__device__ __forceinline__ void bt_cnot(cx<R>* t, const BTOp& op, uint32_t TS, uint32_t base) {
+  const int p = op.p1;
+  const uint32_t bit = 1u << p;
+  for (uint32_t i = threadIdx.x; i < TS / 2; i += blockDim.x) {
+    const uint32_t x0 = ((i >> p) << (p + 1)) | (i & (bit - 1));
+    if (bt_bit(op.p0, op.g0, x0, base)) {
+      const cx<R> x = t[x0];
+      t[x0] = t[x0 | bit];
+      t[x0 | bit] = x;
+    }
+  }
+}
+
+// Reverse-sweep op on both tiles; returns this thread's share of the
+// gradient term -Im<lambda|P|psi> when the op is a parametric rotation.
+template <typename R>
+__device__ __forceinline__ double bt_rev(cx<R>* ps, cx<R>* la, const BTOp& op, const M2<R>* mats, uint32_t TS,
+                                         uint32_t base) {
+  if (op.kind == BO_CZ) {
+    bt_cz(ps, op, TS, base);
+    bt_cz(la, op, TS, base);
+    return 0.0;
+  }
+  if (op.kind == BO_CNOT) {
+    bt_cnot(ps, op, TS, base);
+    bt_cnot(la, op, TS, base);
+    return 0.0;
+  }
+  const M2<R> u = m2_dag(mats[op.bop]);
+  const int p = op.p0;
+  if (op.row < 0) {
+    bt_pair(ps, p, u, TS);
+    bt_pair(la, p, u, TS);
+    return 0.0;
+  }
+  double acc = 0.0;
+  if (op.pauli == 3) {
+    for (uint32_t j = threadIdx.x; j < TS; j += blockDim.x) {
+      const cx<R> x = ps[j], l = la[j];
+      const bool one = (j >> p) & 1;
+      const double im = double(l.re) * x.im - double(l.im) * x.re;
+      acc -= one ? -im : im;
+      const cx<R> f = one ? u.m11 : u.m00;
+      ps[j] = f * x;
+      la[j] = f * l;
+    }
+    return acc;
+  }
+  const uint32_t bit = 1u << p;
+  for (uint32_t i = threadIdx.x; i < TS / 2; i += blockDim.x) {
+    const uint32_t x0 = ((i >> p) << (p + 1)) | (i & (bit - 1));
+    const uint32_t x1 = x0 | bit;
+    const cx<R> a0 = ps[x0], a1 = ps[x1], l0 = la[x0], l1 = la[x1];
+    const double a0r = a0.re, a0i = a0.im, a1r = a1.re, a1i = a1.im;
+    const double l0r = l0.re, l0i = l0.im, l1r = l1.re, l1i = l1.im;
+    const double im = op.pauli == 1 ? (l0r * a1i - l0i * a1r) + (l1r * a0i - l1i * a0r)
+                                    : -(l0r * a1r + l0i * a1i) + (l1r * a0r + l1i * a0i);
+    acc -= im;
+    ps[x0] = cfma(u.m00, a0, u.m01 * a1);
+    ps[x1] = cfma(u.m10, a0, u.m11 * a1);
+    la[x0] = cfma(u.m00, l0, u.m01 * l1);
+    la[x1] = cfma(u.m10, l0, u.m11 * l1);
+  }
+  return acc;
+}
+
+// Forward passes of a device-memory item: psi = U |0...0>.
+template <typename R>
+__device__ void bt_forward(const BatchArgs& a, const BatchItem& I, cx<R>* psi, M2<R>* mats, char* smem) {
+  const double* theta = a.theta + I.theta_off;
+  for (int o = threadIdx.x; o < I.op_count; o += blockDim.x) {
+    const BatchOp op = a.ops[I.op_begin + o];
+    if (op.kind == BO_ROT)
+      mats[o] = op.slot >= 0 ? rot2<R>(op.pauli, theta[op.slot]) : pool2<R>(a.pool + op.moff, false);
+    else if (op.kind == BO_DENSE1)
+      mats[o] = pool2<R>(a.pool + op.moff, false);
+  }
+  const uint32_t N = 1u << I.n;
+  for (uint32_t x = threadIdx.x; x < N; x += blockDim.x) psi[x] = {R(x == 0 ? 1 : 0), R(0)};
+  cx<R>* t = reinterpret_cast<cx<R>*>(smem);
+  for (int pi = 0; pi < I.fp_count; ++pi) {
+    const BatchPass& P = a.passes[I.fp_begin + pi];
+    const uint32_t TS = 1u << P.L, tiles = 1u << P.ng;
+    for (uint32_t g = 0; g < tiles; ++g) {
+      const uint32_t base = bt_base(P, g);
+      __syncthreads();  // the tile buffer is free; earlier device-memory writes are visible
+      for (uint32_t j = threadIdx.x; j < TS; j += blockDim.x) t[j] = psi[bt_addr(P, base, j)];
+      __syncthreads();
+      for (int o = 0; o < P.op_count; ++o) {
+        const BTOp op = a.tops[P.op_begin + o];
+        if (op.kind == BO_CZ) bt_cz(t, op, TS, base);
+        else if (op.kind == BO_CNOT) bt_cnot(t, op, TS, base);
+        else bt_pair(t, op.p0, mats[op.bop], TS);
+        __syncthreads();
+      }
+      for (uint32_t j = threadIdx.x; j < TS; j += blockDim.x) psi[bt_addr(P, base, j)] = t[j];
+    }
+  }
+  __syncthreads();
+}
+
+// Reverse passes of a device-memory item: uncomputes psi and lambda and adds
+// the gradient terms into grad[] (per-wavefront LDS slots, fixed order).
+template <typename R>
+__device__ void bt_reverse(const BatchArgs& a, const BatchItem& I, cx<R>* psi, cx<R>* lam, const M2<R>* mats,
+                           double* grad, char* smem) {
+  constexpr int NW = kBatchThreads / 64;
+  cx<R>* ts = reinterpret_cast<cx<R>*>(smem);
+  cx<R>* tl = ts + kBatchStateLds / 2 / sizeof(cx<R>);
+  double* slot = reinterpret_cast<double*>(smem + kBatchStateLds);
+  const int wave = int(threadIdx.x >> 6);
+  for (int pi = 0; pi < I.rp_count; ++pi) {
+    const BatchPass& P = a.passes[I.rp_begin + pi];
+    const uint32_t TS = 1u << P.L, tiles = 1u << P.ng;
+    __syncthreads();
+    for (int r = threadIdx.x; r < P.row_count * NW; r += blockDim.x) slot[r] = 0.0;
+    for (uint32_t g = 0; g < tiles; ++g) {
+      const uint32_t base = bt_base(P, g);
+      __syncthreads();
+      for (uint32_t j = threadIdx.x; j < TS; j += blockDim.x) {
+        const uint32_t x = bt_addr(P, base, j);
+        ts[j] = psi[x];
+        tl[j] = lam[x];
+      }
+      __syncthreads();
+      for (int o = 0; o < P.op_count; ++o) {
+        const BTOp op = a.tops[P.op_begin + o];
+        double acc = bt_rev(ts, tl, op, mats, TS, base);
+        if (op.row >= 0) {
+#pragma unroll
+          for (int sft = 32; sft > 0; sft >>= 1) acc += __shfl_xor(acc, sft, 64);
+          if ((threadIdx.x & 63) == 0) slot[op.row * NW + wave] += acc;
+        }
+        __syncthreads();
+      }
+      for (uint32_t j = threadIdx.x; j < TS; j += blockDim.x) {
+        const uint32_t x = bt_addr(P, base, j);
+        psi[x] = ts[j];
+        lam[x] = tl[j];
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // rows in order (a parameter may own several rows)
+      for (int o = 0; o < P.op_count; ++o) {
+        const BTOp op = a.tops[P.op_begin + o];
+        if (op.row < 0) continue;
+        double sum = 0.0;
+        for (int w = 0; w < NW; ++w) sum += slot[op.row * NW + w];
+        grad[op.slot] += sum;
+      }
+    }
+  }
+  __syncthreads();
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchArgs a) {
   extern __shared__ __align__(16) char smem[];
@@ -163,11 +400,17 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchArgs a) {
       lam = reinterpret_cast<cx<R>*>(a.states) + I.lam_off;
     }
     const double* theta = a.theta + I.theta_off;
-    // |0...0>
-    for (uint32_t x = threadIdx.x; x < N; x += blockDim.x) psi[x] = {R(x == 0 ? 1 : 0), R(0)};
-    __syncthreads();
-    // forward
-    for (int o = 0; o < I.op_count; ++o) wg_apply_op<R>(psi, n, a.ops[I.op_begin + o], theta, a.pool, false);
+    const bool tiled = I.fp_count > 0;
+    M2<R>* mats = reinterpret_cast<M2<R>*>(a.mats) + I.mat_off;
+    if (tiled) {
+      bt_forward<R>(a, I, psi, mats, smem);
+    } else {
+      // |0...0>
+      for (uint32_t x = threadIdx.x; x < N; x += blockDim.x) psi[x] = {R(x == 0 ? 1 : 0), R(0)};
+      __syncthreads();
+      // forward
+      for (int o = 0; o < I.op_count; ++o) wg_apply_op<R>(psi, n, a.ops[I.op_begin + o], theta, a.pool, false);
+    }
     // lambda = H psi
     for (uint32_t y = threadIdx.x; y < N; y += blockDim.x) {
       double ar = 0.0, ai = 0.0;
@@ -197,6 +440,10 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchArgs a) {
     double* grad = a.grads + I.grad_off;
     for (int i = threadIdx.x; i < I.nparams; i += blockDim.x) grad[i] = 0.0;
     __syncthreads();
+    if (tiled) {
+      bt_reverse<R>(a, I, psi, lam, mats, grad, smem);
+      continue;
+    }
     // reverse sweep
     for (int o = I.op_count - 1; o >= 0; --o) {
       const BatchOp op = a.ops[I.op_begin + o];
@@ -251,7 +498,8 @@ struct qsv_batch {
   void* d_tables = nullptr;
   size_t tables_bytes = 0;
   size_t off_items = 0, off_order = 0, off_queue = 0, off_ops = 0, off_pool = 0, off_groups = 0,
-         off_terms = 0, off_theta = 0, off_energy = 0, off_grads = 0;
+         off_terms = 0, off_theta = 0, off_energy = 0, off_grads = 0, off_passes = 0, off_tops = 0,
+         off_mats = 0;
   int total_params = 0;
   size_t lds_bytes = 0;
   int grid = 0;
@@ -263,6 +511,86 @@ namespace {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Tile passes of one item's op list (in order, or reversed for the reverse
+// sweep), greedy like the library's planners: an op joins the current pass
+// when its dense target fits the pass's local set (at most L qubits, the low
+// b always included) and no op deferred before it shares a qubit with it;
+// reverse passes hold at most kBatchRows gradient rows.
+void schedule_item(int n, int L, int b, const BatchOp* ops, int count, bool reverse,
+                   std::vector<BatchPass>& passes, std::vector<BTOp>& tops, int& pbegin, int& pcount) {
+  std::vector<int> rem(static_cast<size_t>(count));
+  for (int i = 0; i < count; ++i) rem[size_t(i)] = reverse ? count - 1 - i : i;
+  pbegin = int(passes.size());
+  pcount = 0;
+  const uint64_t low = (uint64_t(1) << b) - 1;
+  auto qubits = [&](const BatchOp& o) {
+    uint64_t m = uint64_t(1) << o.q0;
+    if (o.kind == BO_CZ || o.kind == BO_CNOT) m |= uint64_t(1) << o.q1;
+    return m;
+  };
+  while (!rem.empty()) {
+    uint64_t local = low, blocked = 0;
+    std::vector<int> take, deferred;
+    int nrow = 0;
+    for (int oi : rem) {
+      const BatchOp& o = ops[oi];
+      const uint64_t qs = qubits(o);
+      if (qs & blocked) {
+        deferred.push_back(oi);
+        blocked |= qs;
+        continue;
+      }
+      const uint64_t dense =
+          o.kind == BO_CZ ? 0 : (o.kind == BO_CNOT ? uint64_t(1) << o.q1 : uint64_t(1) << o.q0);
+      const bool grad = reverse && o.kind == BO_ROT && o.slot >= 0;
+      const uint64_t need = dense & ~local;
+      if (!(grad && nrow >= kBatchRows) && __builtin_popcountll(local | need) <= L) {
+        local |= need;
+        take.push_back(oi);
+        if (grad) ++nrow;
+      } else {
+        deferred.push_back(oi);
+        blocked |= qs;
+      }
+    }
+    for (int q = 0; q < n && __builtin_popcountll(local) < L; ++q) local |= uint64_t(1) << q;
+    BatchPass P{};
+    P.L = L;
+    P.b = b;
+    P.nh = L - b;
+    std::vector<int> lpos(64, -1), loc;
+    for (int q = 0; q < n; ++q)
+      if (local >> q & 1) {
+        lpos[size_t(q)] = int(loc.size());
+        loc.push_back(q);
+      }
+    for (int i = 0; i < P.nh; ++i) P.hq[i] = loc[size_t(b + i)];
+    P.ng = 0;
+    for (int q = 0; q < n; ++q)
+      if (!(local >> q & 1)) P.gpos[P.ng++] = q;
+    P.op_begin = int(tops.size());
+    P.op_count = int(take.size());
+    P.row_count = 0;
+    for (int oi : take) {
+      const BatchOp& o = ops[oi];
+      BTOp t{};
+      t.kind = o.kind;
+      t.p0 = lpos[size_t(o.q0)];
+      t.g0 = o.q0;
+      t.p1 = (o.kind == BO_CZ || o.kind == BO_CNOT) ? lpos[size_t(o.q1)] : -1;
+      t.g1 = o.q1;
+      t.pauli = o.pauli;
+      t.slot = o.slot;
+      t.bop = oi;
+      t.row = (reverse && o.kind == BO_ROT && o.slot >= 0) ? P.row_count++ : -1;
+      tops.push_back(t);
+    }
+    passes.push_back(P);
+    ++pcount;
+    rem.swap(deferred);
+  }
+}
+
 int build_device(qsv_batch* b, qsv_dtype dt) {
   const size_t S = amp_bytes(dt);
   std::vector<BatchItem> items(b->items.size());
@@ -271,8 +599,14 @@ int build_device(qsv_batch* b, qsv_dtype dt) {
   std::vector<BatchGroup> groups;
   std::vector<GTerm> terms;
   std::vector<double> theta;
-  // LDS for psi + lambda: 64 KiB keeps two workgroups per CU
-  const size_t lds = 65536;
+  // LDS for psi + lambda (whole states, or tiles): 64 KiB keeps two
+  // workgroups per CU
+  const size_t lds = kBatchStateLds;
+  const int Lt = dt == QSV_C64 ? 12 : 11;  // tile qubits: psi + lambda tiles fill the 64 KiB
+  const int bt = dt == QSV_C64 ? 4 : 3;    // 128-byte contiguous runs
+  std::vector<BatchPass> passes;
+  std::vector<BTOp> tops;
+  int mat_elems = 0;
   size_t state_elems = 0;
   int grad_off = 0;
   for (size_t i = 0; i < b->items.size(); ++i) {
@@ -348,12 +682,18 @@ int build_device(qsv_batch* b, qsv_dtype dt) {
     I.grad_off = grad_off;
     grad_off += it.c.nparams;
     const uint64_t N = dim(I.n);
+    I.fp_begin = I.fp_count = I.rp_begin = I.rp_count = 0;
+    I.mat_off = 0;
     if (2 * N * S <= lds) {
       I.psi_off = I.lam_off = 0;
     } else {
       I.psi_off = state_elems;
       I.lam_off = state_elems + N;
       state_elems += 2 * N;
+      schedule_item(I.n, Lt, bt, ops.data() + I.op_begin, I.op_count, false, passes, tops, I.fp_begin, I.fp_count);
+      schedule_item(I.n, Lt, bt, ops.data() + I.op_begin, I.op_count, true, passes, tops, I.rp_begin, I.rp_count);
+      I.mat_off = mat_elems;
+      mat_elems += I.op_count;
     }
   }
   // largest items first
@@ -372,6 +712,9 @@ int build_device(qsv_batch* b, qsv_dtype dt) {
   b->off_theta = off; off = align_up(off + std::max<size_t>(1, theta.size()) * sizeof(double), 256);
   b->off_energy = off; off = align_up(off + items.size() * sizeof(double), 256);
   b->off_grads = off; off = align_up(off + std::max<int>(1, grad_off) * sizeof(double), 256);
+  b->off_passes = off; off = align_up(off + std::max<size_t>(1, passes.size()) * sizeof(BatchPass), 256);
+  b->off_tops = off; off = align_up(off + std::max<size_t>(1, tops.size()) * sizeof(BTOp), 256);
+  b->off_mats = off; off = align_up(off + std::max<size_t>(1, size_t(mat_elems)) * sizeof(M2<double>), 256);
   if (hipMalloc(&b->d_tables, off) != hipSuccess) return fail(QSV_ENOMEM, "batch table allocation failed");
   b->tables_bytes = off;
   if (state_elems && hipMalloc(&b->d_states, state_elems * S) != hipSuccess)
@@ -388,9 +731,11 @@ int build_device(qsv_batch* b, qsv_dtype dt) {
   if ((rc = put(b->off_pool, pool.data(), pool.size() * sizeof(double)))) return rc;
   if ((rc = put(b->off_groups, groups.data(), groups.size() * sizeof(BatchGroup)))) return rc;
   if ((rc = put(b->off_terms, terms.data(), terms.size() * sizeof(GTerm)))) return rc;
+  if ((rc = put(b->off_passes, passes.data(), passes.size() * sizeof(BatchPass)))) return rc;
+  if ((rc = put(b->off_tops, tops.data(), tops.size() * sizeof(BTOp)))) return rc;
   b->state_elems = state_elems;
   b->total_params = grad_off;
-  b->lds_bytes = lds;
+  b->lds_bytes = lds + size_t(kBatchRows) * (kBatchThreads / 64) * sizeof(double);  // + gradient slots
   b->dev_dtype = int(dt);
   return QSV_OK;
 }
@@ -426,7 +771,10 @@ int run_t(qsv_batch* b, hipStream_t st, double* energies, double* grads) {
   a.energies = reinterpret_cast<double*>(d + b->off_energy);
   a.grads = reinterpret_cast<double*>(d + b->off_grads);
   a.states = b->d_states;
-  a.lds_state_bytes = b->lds_bytes;
+  a.lds_state_bytes = kBatchStateLds;
+  a.passes = reinterpret_cast<const BatchPass*>(d + b->off_passes);
+  a.tops = reinterpret_cast<const BTOp*>(d + b->off_tops);
+  a.mats = d + b->off_mats;
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, a.queue);
   {
     ProfScope ps("batch", 0.0, st);

@@ -75,3 +75,27 @@ def test_hea_items_mixed_sizes(dt):
     scale = sum(abs(c) for c, _ in it["obs"])
     ref = O.param_shift_grad(12, it["gates"], it["theta"], it["obs"], slots=range(0, 192, 17))
     assert np.max(np.abs(g[twelve[0]][0:192:17] - ref)) <= TOL[dt] * scale
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_device_memory_items_cnot_and_fixed_gates(dt):
+    # items too large for LDS run tile passes: CNOT rings (controls on
+    # non-local qubits), fixed one-qubit gates and rotations, random Pauli
+    # observables; against the single-item adjoint path
+    items = []
+    for i, n in enumerate((13, 14, 15)):
+        gates, npar = W.ry_rz_cnot_ring(n, 3)
+        gates = [{"op": "h", "q": [n - 1]}] + gates + [{"op": "rx", "q": [n - 2], "angle": 0.7},
+                                                      {"op": "cz", "q": [0, n - 1]}]
+        obs = W.random_pauli_observable(n, 20, (1, 4), seed_key=(9, i))
+        items.append((n, gates, W.uniform_angles(npar, (9, i, 2)), obs))
+    b = Batch()
+    for n, gates, theta, obs in items:
+        b.add(Circuit.from_records(n, gates), Observable(n, obs), theta)
+    e, g = b.run(dt)
+    for i, (n, gates, theta, obs) in enumerate(items):
+        psi, lam = State(n, dt), State(n, dt)
+        e1, g1 = adjoint_gradient(Circuit.from_records(n, gates), theta, Observable(n, obs), psi, lam)
+        scale = sum(abs(c) for c, _ in obs)
+        assert abs(e[i] - e1) <= TOL[dt] * scale, (i, n)
+        assert np.max(np.abs(g[i] - g1)) <= TOL[dt] * scale, (i, n)
