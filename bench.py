@@ -225,7 +225,8 @@ def batch_leg(Q, W, count):
         circs.append((c, o))
         b.add(c, o, it["theta"])
     for dt in ("c64", "c128"):
-        b.run(dt)  # builds device tables
+        shape = b.autotune(dt, reps=1)  # launch shape by measurement (outside the timed runs)
+        b.run(dt)  # builds device tables, captures the launch graph
         reps = 3
         t0 = time.perf_counter()
         for _ in range(reps):
@@ -246,7 +247,7 @@ def batch_leg(Q, W, count):
             e1, g1 = Q.adjoint_gradient(c, items[i]["theta"], o, psi, lam)
             t_pc += time.perf_counter() - t0
         per_item = t_pc / len(sample)
-        out[dt] = {"batch_s": t_b, "items_per_s": count / t_b,
+        out[dt] = {"batch_s": t_b, "items_per_s": count / t_b, "launch_shape": shape,
                    "grads_per_s": out["params_total"] / t_b,
                    "per_circuit_items_per_s": 1.0 / per_item,
                    "speedup_vs_per_circuit": (count / t_b) * per_item}

@@ -287,7 +287,9 @@ int qsv_adjoint_gradient(const qsv_circuit* c, qsv_plan* forward_plan, const dou
  * each workgroup takes items from a device work queue (largest first) and runs
  * forward pass, lambda = O psi, energy and reverse sweep for its item with the
  * item's states in LDS when psi and lambda fit in 64 KiB, else in device
- * memory. This serves the regime the paper motivates -- small circuits
+ * memory streamed through LDS tiles in passes (several gates per pass, as in
+ * qsv_plan_fused). The launch is captured once as a HIP graph and replayed
+ * by later runs (qsv_batch_set_graph). This serves the regime the paper motivates -- small circuits
  * evaluated many times, where per-call overhead dominates (section 5.1) --
  * with a design of this library's own. Items take 2..24 qubits; their gates
  * must be one-qubit gates, rotations, CZ or CNOT (other gates: QSV_EINVAL at
@@ -308,6 +310,24 @@ int qsv_batch_info(const qsv_batch* b, int* items, int* total_params);
  * circuit's nparams entries). Device buffers are built on the first run for a
  * dtype and reused. Synchronises the stream. */
 int qsv_batch_run(qsv_batch* b, qsv_dtype dtype, void* stream, double* energies, double* grads);
+
+/* Launch-shape autotuner for the batch: times `reps` (1..100) runs of the
+ * batch on `stream` for each candidate -- LDS for psi + lambda per workgroup
+ * of 64 KiB (complex64 items up to 12 qubits held in LDS, 2^12-amplitude
+ * tiles otherwise) or 32 KiB (2^11 tiles, more workgroups per CU) times 512 or
+ * 256 threads per workgroup -- after one untimed run each, and keeps the
+ * fastest for later runs. choice (may be NULL) receives int[2]: LDS KiB and
+ * threads. Results do not depend on the shape beyond rounding order. Errors:
+ * QSV_EINVAL (null or empty batch, reps out of range), QSV_EDTYPE, and those of
+ * qsv_batch_run. */
+int qsv_batch_autotune(qsv_batch* b, qsv_dtype dtype, void* stream, int reps, int* choice);
+
+/* enable != 0 (the default): qsv_batch_run captures its launch (work-queue
+ * reset kernel + persistent kernel) into a HIP graph on its first run for a
+ * dtype and replays that graph afterwards; 0: plain launches every run (and
+ * the captured graph is released). Parameter uploads and result copies stay
+ * outside the graph. Results are identical either way. */
+int qsv_batch_set_graph(qsv_batch* b, int enable);
 
 #ifdef __cplusplus
 }

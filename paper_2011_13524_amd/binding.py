@@ -71,6 +71,8 @@ _SIGS = {
     "qsv_batch_set_theta": (_c.c_int, [_vp, _c.c_int, _dp]),
     "qsv_batch_info": (_c.c_int, [_vp, _ip, _ip]),
     "qsv_batch_run": (_c.c_int, [_vp, _c.c_int, _vp, _dp, _dp]),
+    "qsv_batch_set_graph": (_c.c_int, [_vp, _c.c_int]),
+    "qsv_batch_autotune": (_c.c_int, [_vp, _c.c_int, _vp, _c.c_int, _ip]),
     "qsv_prof_enable": (_c.c_int, [_c.c_int]),
     "qsv_prof_read": (_c.c_int, [_c.c_char_p, _ip, _dp, _dp]),
 }
@@ -399,6 +401,17 @@ class Batch:
     def set_theta(self, item: int, theta):
         keep, tp = _theta_ptr(theta)
         check(lib().qsv_batch_set_theta(self.h, item, tp))
+
+    def autotune(self, dtype: str = "c64", stream=None, reps: int = 2) -> dict:
+        """Pick the launch shape (LDS per workgroup, threads) by timing runs."""
+        ch = (_c.c_int * 2)()
+        check(lib().qsv_batch_autotune(self.h, QSV_C64 if dtype == "c64" else QSV_C128,
+                                       _stream_handle(stream), reps, ch))
+        return {"lds_kib": ch[0], "threads": ch[1]}
+
+    def set_graph(self, enable: bool):
+        """Replay the launch as a captured HIP graph (default) or launch plainly."""
+        check(lib().qsv_batch_set_graph(self.h, 1 if enable else 0))
 
     def run(self, dtype: str = "c64", stream=None):
         """Returns (energies ndarray, list of per-item gradient ndarrays)."""

@@ -14,6 +14,7 @@
 // sizes this targets). Every workgroup leaves the loop once the queue is
 // exhausted, so the grid always drains.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 
 #include "circuit.h"
@@ -23,10 +24,10 @@
 
 namespace qsv {
 
-constexpr int kBatchThreads = 512;
+constexpr int kBatchThreads = 512;  // default workgroup size (256 also instantiated)
 constexpr int kBatchMaxQ = 24;    // qubits per item
 constexpr int kBatchRows = 64;    // gradient rows per reverse pass (LDS slots)
-constexpr size_t kBatchStateLds = 65536;  // psi + lambda (whole states or tiles)
+constexpr size_t kBatchStateLds = 65536;  // default LDS for psi + lambda (whole states or tiles)
 
 enum BatchOpKind { BO_ROT = 0, BO_CZ = 1, BO_CNOT = 2, BO_DENSE1 = 3 };
 
@@ -327,10 +328,10 @@ __device__ void bt_forward(const BatchArgs& a, const BatchItem& I, cx<R>* psi, M
 template <typename R>
 __device__ void bt_reverse(const BatchArgs& a, const BatchItem& I, cx<R>* psi, cx<R>* lam, const M2<R>* mats,
                            double* grad, char* smem) {
-  constexpr int NW = kBatchThreads / 64;
+  const int NW = int(blockDim.x >> 6);
   cx<R>* ts = reinterpret_cast<cx<R>*>(smem);
-  cx<R>* tl = ts + kBatchStateLds / 2 / sizeof(cx<R>);
-  double* slot = reinterpret_cast<double*>(smem + kBatchStateLds);
+  cx<R>* tl = ts + a.lds_state_bytes / 2 / sizeof(cx<R>);
+  double* slot = reinterpret_cast<double*>(smem + a.lds_state_bytes);
   const int wave = int(threadIdx.x >> 6);
   for (int pi = 0; pi < I.rp_count; ++pi) {
     const BatchPass& P = a.passes[I.rp_begin + pi];
@@ -376,10 +377,10 @@ __device__ void bt_reverse(const BatchArgs& a, const BatchItem& I, cx<R>* psi, c
   __syncthreads();
 }
 
-template <typename R>
-__global__ void __launch_bounds__(kBatchThreads) k_batch(BatchArgs a) {
+template <typename R, int NT>
+__global__ void __launch_bounds__(NT) k_batch(BatchArgs a) {
   extern __shared__ __align__(16) char smem[];
-  __shared__ double red[kBatchThreads / 64];
+  __shared__ double red[NT / 64];
   __shared__ int s_item;
   while (true) {
     __syncthreads();
@@ -503,6 +504,15 @@ struct qsv_batch {
   int total_params = 0;
   size_t lds_bytes = 0;
   int grid = 0;
+  // launch shape (qsv_batch_autotune): LDS bytes for psi + lambda per
+  // workgroup (whole states, or the tiles of device-memory items) and threads
+  size_t cfg_lds = qsv::kBatchStateLds;
+  int cfg_threads = qsv::kBatchThreads;
+  // the launch (queue reset + persistent kernel) captured once as a HIP graph
+  // and replayed by later runs
+  bool use_graph = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
 };
 
 namespace qsv {
@@ -599,11 +609,12 @@ int build_device(qsv_batch* b, qsv_dtype dt) {
   std::vector<BatchGroup> groups;
   std::vector<GTerm> terms;
   std::vector<double> theta;
-  // LDS for psi + lambda (whole states, or tiles): 64 KiB keeps two
-  // workgroups per CU
-  const size_t lds = kBatchStateLds;
-  const int Lt = dt == QSV_C64 ? 12 : 11;  // tile qubits: psi + lambda tiles fill the 64 KiB
-  const int bt = dt == QSV_C64 ? 4 : 3;    // 128-byte contiguous runs
+  // LDS for psi + lambda (whole states, or tiles): 64 KiB by default (two
+  // workgroups per CU); tiles of device-memory items fill it
+  const size_t lds = b->cfg_lds;
+  int Lt = 0;
+  while ((size_t(2) << (Lt + 1)) * S <= lds) ++Lt;  // 2 * 2^Lt * S <= lds
+  const int bt = std::min(Lt, dt == QSV_C64 ? 4 : 3);  // 128-byte contiguous runs
   std::vector<BatchPass> passes;
   std::vector<BTOp> tops;
   int mat_elems = 0;
@@ -735,7 +746,7 @@ int build_device(qsv_batch* b, qsv_dtype dt) {
   if ((rc = put(b->off_tops, tops.data(), tops.size() * sizeof(BTOp)))) return rc;
   b->state_elems = state_elems;
   b->total_params = grad_off;
-  b->lds_bytes = lds + size_t(kBatchRows) * (kBatchThreads / 64) * sizeof(double);  // + gradient slots
+  b->lds_bytes = lds + size_t(kBatchRows) * (b->cfg_threads / 64) * sizeof(double);  // + gradient slots
   b->dev_dtype = int(dt);
   return QSV_OK;
 }
@@ -748,14 +759,15 @@ int run_t(qsv_batch* b, hipStream_t st, double* energies, double* grads) {
   if (!theta.empty())
     QSV_HIP_CHECK(hipMemcpyAsync(d + b->off_theta, theta.data(), theta.size() * sizeof(double),
                                  hipMemcpyHostToDevice, st));
+  const int NT = b->cfg_threads;
+  auto kfn = NT == 256 ? &k_batch<R, 256> : &k_batch<R, 512>;
   if (b->grid == 0) {
     int dev = 0, cus = 0, per = 0;
     QSV_HIP_CHECK(hipGetDevice(&dev));
     QSV_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    QSV_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch<R>),
+    QSV_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(b->lds_bytes)));
-    QSV_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<R>, kBatchThreads,
-                                                               b->lds_bytes));
+    QSV_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kfn, NT, b->lds_bytes));
     b->grid = std::max(1, cus * std::max(1, per));
   }
   BatchArgs a;
@@ -771,16 +783,37 @@ int run_t(qsv_batch* b, hipStream_t st, double* energies, double* grads) {
   a.energies = reinterpret_cast<double*>(d + b->off_energy);
   a.grads = reinterpret_cast<double*>(d + b->off_grads);
   a.states = b->d_states;
-  a.lds_state_bytes = kBatchStateLds;
+  a.lds_state_bytes = b->cfg_lds;
   a.passes = reinterpret_cast<const BatchPass*>(d + b->off_passes);
   a.tops = reinterpret_cast<const BTOp*>(d + b->off_tops);
   a.mats = d + b->off_mats;
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, a.queue);
-  {
-    ProfScope ps("batch", 0.0, st);
-    hipLaunchKernelGGL((k_batch<R>), dim3(b->grid), dim3(kBatchThreads), b->lds_bytes, st, a);
+  if (b->use_graph && !b->graph_exec) {
+    // capture on a private stream (the caller's may be the legacy default
+    // stream, which cannot be captured); the queue reset is a kernel, not a
+    // memset node
+    hipStream_t cs = nullptr;
+    QSV_HIP_CHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, cs, a.queue);
+      hipLaunchKernelGGL(kfn, dim3(b->grid), dim3(NT), b->lds_bytes, cs, a);
+      e = hipStreamEndCapture(cs, &b->graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->graph_exec, b->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return fail(QSV_EHIP, "batch graph capture failed: %s", hipGetErrorString(e));
   }
-  QSV_HIP_CHECK(hipGetLastError());
+  if (b->use_graph) {
+    ProfScope ps("batch", 0.0, st);
+    QSV_HIP_CHECK(hipGraphLaunch(b->graph_exec, st));
+  } else {
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, a.queue);
+    {
+      ProfScope ps("batch", 0.0, st);
+      hipLaunchKernelGGL(kfn, dim3(b->grid), dim3(NT), b->lds_bytes, st, a);
+    }
+    QSV_HIP_CHECK(hipGetLastError());
+  }
   QSV_HIP_CHECK(hipMemcpyAsync(energies, a.energies, b->items.size() * sizeof(double),
                                hipMemcpyDeviceToHost, st));
   if (grads && b->total_params)
@@ -790,7 +823,15 @@ int run_t(qsv_batch* b, hipStream_t st, double* energies, double* grads) {
   return QSV_OK;
 }
 
+void release_graph(qsv_batch* b) {
+  if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->graph_exec = nullptr;
+  b->graph = nullptr;
+}
+
 void release_device(qsv_batch* b) {
+  release_graph(b);
   if (b->d_tables) (void)hipFree(b->d_tables);
   if (b->d_states) (void)hipFree(b->d_states);
   b->d_tables = b->d_states = nullptr;
@@ -853,6 +894,75 @@ int qsv_batch_info(const qsv_batch* b, int* items, int* total_params) {
   for (const auto& it : b->items) tp += it.c.nparams;
   if (items) *items = int(b->items.size());
   if (total_params) *total_params = tp;
+  return QSV_OK;
+}
+
+int qsv_batch_autotune(qsv_batch* b, qsv_dtype dtype, void* stream, int reps, int* choice) {
+  clear_error();
+  if (!b) return fail(QSV_EINVAL, "null batch");
+  if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_EDTYPE, "unknown dtype");
+  if (reps < 1 || reps > 100) return fail(QSV_EINVAL, "reps must be in 1..100");
+  if (b->items.empty()) return fail(QSV_EINVAL, "empty batch");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int tp = 0;
+  for (const auto& it : b->items) tp += it.c.nparams;
+  std::vector<double> en(b->items.size()), gr(size_t(std::max(tp, 1)));
+  // candidates: LDS bytes for psi + lambda (64 KiB: 12-qubit complex64 items
+  // in LDS, 2^12 tiles; 32 KiB: more workgroups per CU), threads per workgroup
+  const size_t ldsc[2] = {65536, 32768};
+  const int thr[2] = {512, 256};
+  double best_s = 0.0;
+  size_t best_lds = 0;
+  int best_thr = 0;
+  for (size_t li = 0; li < 2; ++li) {
+    for (int ti = 0; ti < 2; ++ti) {
+      release_device(b);
+      b->cfg_lds = ldsc[li];
+      b->cfg_threads = thr[ti];
+      int rc = build_device(b, dtype);
+      auto run = [&]() {
+        return dtype == QSV_C64 ? run_t<float>(b, st, en.data(), gr.data())
+                                : run_t<double>(b, st, en.data(), gr.data());
+      };
+      if (!rc) rc = run();  // warm-up (and graph capture)
+      if (rc) {
+        release_device(b);
+        if (rc == QSV_ENOMEM) {  // a shape that does not fit is skipped
+          clear_error();
+          continue;
+        }
+        return rc;
+      }
+      const auto t0 = std::chrono::steady_clock::now();
+      for (int r = 0; r < reps && !rc; ++r) rc = run();
+      const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (rc) {
+        release_device(b);
+        return rc;
+      }
+      if (best_thr == 0 || sec < best_s) {
+        best_s = sec;
+        best_lds = ldsc[li];
+        best_thr = thr[ti];
+      }
+    }
+  }
+  release_device(b);
+  if (best_thr == 0) return fail(QSV_ENOMEM, "autotune: no launch shape fits");
+  b->cfg_lds = best_lds;
+  b->cfg_threads = best_thr;
+  if (choice) {
+    choice[0] = int(best_lds / 1024);
+    choice[1] = best_thr;
+  }
+  return QSV_OK;
+}
+
+int qsv_batch_set_graph(qsv_batch* b, int enable) {
+  clear_error();
+  if (!b) return fail(QSV_EINVAL, "null batch");
+  b->use_graph = enable != 0;
+  if (!b->use_graph) release_graph(b);
   return QSV_OK;
 }
 

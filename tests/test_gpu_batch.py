@@ -99,3 +99,51 @@ def test_device_memory_items_cnot_and_fixed_gates(dt):
         scale = sum(abs(c) for c, _ in obs)
         assert abs(e[i] - e1) <= TOL[dt] * scale, (i, n)
         assert np.max(np.abs(g[i] - g1)) <= TOL[dt] * scale, (i, n)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_graph_replays_match_plain_launches(dt):
+    # the captured launch replayed several times, with other GPU work and
+    # synchronisations in between, gives the plain launch's results exactly
+    items = W.batch_items(12, seed=5)
+    def build():
+        b = Batch()
+        for it in items:
+            b.add(Circuit.from_records(it["n"], it["gates"]), Observable(it["n"], it["obs"]), it["theta"])
+        return b
+    plain = build()
+    plain.set_graph(False)
+    e0, g0 = plain.run(dt)
+    b = build()
+    b.set_graph(True)
+    other = State(14, dt)
+    for rep in range(3):
+        e, g = b.run(dt)
+        assert np.array_equal(e, e0), rep
+        for gi, gr in zip(g, g0):
+            assert np.array_equal(gi, gr), rep
+        other.set_basis(rep)  # eager work between replays
+        other.norm2()
+        e1, _ = plain.run(dt)  # and a plain launch of the same kernel
+        assert np.array_equal(e1, e0)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_autotuned_launch_shape_matches_default(dt):
+    # every candidate shape (LDS per workgroup, threads) runs the same items;
+    # the one kept gives the default shape's results up to rounding order
+    items = W.batch_items(16, seed=7)
+    def build():
+        b = Batch()
+        for it in items:
+            b.add(Circuit.from_records(it["n"], it["gates"]), Observable(it["n"], it["obs"]), it["theta"])
+        return b
+    e0, g0 = build().run(dt)
+    b = build()
+    ch = b.autotune(dt, reps=1)
+    assert ch["lds_kib"] in (64, 32) and ch["threads"] in (512, 256)
+    e, g = b.run(dt)
+    for i, it in enumerate(items):
+        scale = sum(abs(c) for c, _ in it["obs"])
+        assert abs(e[i] - e0[i]) <= TOL[dt] * scale, (i, ch)
+        assert np.max(np.abs(g[i] - g0[i])) <= TOL[dt] * scale, (i, ch)
