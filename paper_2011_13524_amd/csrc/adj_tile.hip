@@ -636,6 +636,7 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
     d.ng = 0;
     for (int q = 0; q < n; ++q)
       if (!(local >> q & 1)) d.gpos[d.ng++] = q;
+    pass_runs(d);
     d.op_begin = int(ho.size());
     d.op_count = int(pass_ops[pi].size());
     d.row_begin = int(prow.size());

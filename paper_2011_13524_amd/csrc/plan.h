@@ -38,6 +38,10 @@ struct TilePassDev {
   int row_begin, row_count;  // reverse sweep: gradient rows of the pass (slot s -> rows[row_begin + s])
   int hq[kTileMaxHigh];      // qubits of local bits b..L-1
   int gpos[kTileMaxGlobal];  // non-local qubits, ascending
+  // the same map from tile index to tile base as runs of consecutive
+  // non-local qubits: base = OR over r of ((g >> rsrc[r]) & (2^rlen[r] - 1)) << rdst[r]
+  int nrun;
+  int rsrc[kTileMaxHigh + 1], rdst[kTileMaxHigh + 1], rlen[kTileMaxHigh + 1];
 };
 
 // Register-resident tiles: the 2^L tile is spread over 2^TB threads holding
@@ -66,6 +70,9 @@ struct RegSegDev {
   // into this layout); get_*: this layout (tcst = 0).
   uint32_t put_reg[1 << (kRegMaxBits - 1)], put_tcol[kRegMaxThreadBits], put_tcst;
   uint32_t get_reg[1 << (kRegMaxBits - 1)], get_tcol[kRegMaxThreadBits];
+  // global index bit of thread-index bit k and of register-index bit k in this
+  // layout (HBM addresses of the first and last segments of a pass)
+  uint64_t gcol_t[kRegMaxThreadBits], gcol_r[kRegMaxBits];
 };
 
 struct RegOpDev {
@@ -94,6 +101,9 @@ struct SegCfg {
 // Splits the ops of pass d (ho[d.op_begin ..]) into register segments,
 // appending them to segs / rops; d.seg_count is incremented per segment (the
 // caller sets d.seg_begin = segs.size() and d.seg_count = 0 first).
+// Fills the run-length form of d.gpos (d.nrun, rsrc, rdst, rlen).
+void pass_runs(TilePassDev& d);
+
 int build_reg_segments(const SegCfg& cfg, const std::vector<TileOpDev>& ho, TilePassDev& d,
                        std::vector<RegSegDev>& segs, std::vector<RegOpDev>& rops);
 

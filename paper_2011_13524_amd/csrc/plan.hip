@@ -327,6 +327,20 @@ static int build_plan(qsv_plan* p) {
 // (thread-index bits above the 64 lanes) are chosen so that consecutive
 // segments share them where possible: a re-map between two such layouts
 // moves data only within each wavefront and needs no workgroup barrier.
+void pass_runs(TilePassDev& d) {
+  d.nrun = 0;
+  for (int j = 0; j < d.ng; ++j) {
+    if (j > 0 && d.gpos[j] == d.gpos[j - 1] + 1) {
+      ++d.rlen[d.nrun - 1];
+      continue;
+    }
+    d.rsrc[d.nrun] = j;
+    d.rdst[d.nrun] = d.gpos[j];
+    d.rlen[d.nrun] = 1;
+    ++d.nrun;
+  }
+}
+
 int build_reg_segments(const SegCfg& cfg, const std::vector<TileOpDev>& ho, TilePassDev& d,
                        std::vector<RegSegDev>& out_segs, std::vector<RegOpDev>& out_rops) {
   const int RB = cfg.reg_bits, TB = cfg.thread_bits, L = d.L;
@@ -637,8 +651,11 @@ int build_reg_segments(const SegCfg& cfg, const std::vector<TileOpDev>& ho, Tile
     const uint32_t m = (1u << SB) - 1;
     return j ^ ((j >> SB) & m) ^ ((j >> (2 * SB)) & m);
   };
+  auto gbit = [&](int p) { return uint64_t(1) << (p < d.b ? p : d.hq[p - d.b]); };
   for (int si = d.seg_begin; si < d.seg_begin + d.seg_count; ++si) {
     RegSegDev& S = out_segs[size_t(si)];
+    for (int k = 0; k < TB; ++k) S.gcol_t[k] = gbit(S.thr[k]);
+    for (int k = 0; k < RB; ++k) S.gcol_r[k] = gbit(S.reg[k]);
     for (int k = 0; k < TB; ++k) S.get_tcol[k] = swz(1u << S.thr[k]) * esz;
     for (int i = 0; i < (1 << RB); ++i) {
       uint32_t x = 0;
@@ -685,6 +702,7 @@ static int upload_tables(qsv_plan* p, std::vector<int>& moffs, size_t& pool_elem
     d.ng = 0;
     for (int q = 0; q < n; ++q)
       if (!(lm >> q & 1)) d.gpos[d.ng++] = q;
+    pass_runs(d);
     d.op_begin = int(ho.size());
     d.op_count = int(P.blocks.size());
     std::vector<int> lpos(64, -1);

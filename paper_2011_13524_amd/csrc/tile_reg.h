@@ -425,19 +425,18 @@ __global__ void __launch_bounds__(1 << TB)
   const int L = P.L, b = P.b;
   const uint64_t g = blockIdx.x;
   uint64_t base = 0;
-  for (int j = 0; j < P.ng; ++j) base |= ((g >> j) & 1) << P.gpos[j];
+  for (int r = 0; r < P.nrun; ++r) base |= ((g >> P.rsrc[r]) & ((uint64_t(1) << P.rlen[r]) - 1)) << P.rdst[r];
   const uint32_t tau = threadIdx.x;
-  auto gbit = [&](int p) -> uint64_t { return uint64_t(1) << (p < b ? p : P.hq[p - b]); };
 
   cx<R> v[NR], w[NR];
   // HBM -> registers in the first segment's layout
   const RegSegDev* S = &segs[P.seg_begin];
   uint64_t gthr = base;
-  for (int k = 0; k < TB; ++k)
-    if ((tau >> k) & 1) gthr |= gbit(S->thr[k]);
+#pragma unroll
+  for (int k = 0; k < TB; ++k) gthr |= S->gcol_t[k] & (uint64_t(0) - ((tau >> k) & 1));  // (branch-free)
   uint64_t greg[RB];
 #pragma unroll
-  for (int k = 0; k < RB; ++k) greg[k] = gbit(S->reg[k]);
+  for (int k = 0; k < RB; ++k) greg[k] = S->gcol_r[k];
   const bool vec = sizeof(R) == 4 && S->reg[0] == 0;
   if (vec) {
 #pragma unroll
@@ -496,10 +495,10 @@ __global__ void __launch_bounds__(1 << TB)
 
   // registers -> HBM in the last segment's layout
   gthr = base;
-  for (int k = 0; k < TB; ++k)
-    if ((tau >> k) & 1) gthr |= gbit(S->thr[k]);
 #pragma unroll
-  for (int k = 0; k < RB; ++k) greg[k] = gbit(S->reg[k]);
+  for (int k = 0; k < TB; ++k) gthr |= S->gcol_t[k] & (uint64_t(0) - ((tau >> k) & 1));
+#pragma unroll
+  for (int k = 0; k < RB; ++k) greg[k] = S->gcol_r[k];
   if (sizeof(R) == 4 && S->reg[0] == 0) {
 #pragma unroll
     for (int i = 0; i < NR; i += 2) {
