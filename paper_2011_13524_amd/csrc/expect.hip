@@ -75,8 +75,10 @@ struct ExpTermLds {
   uint32_t zl;
 };
 constexpr int kExpLdsTerms = 128;
-// persistent workgroups per observable pass: 4 per compute unit
-constexpr int kExpGrid = 1024;
+// persistent workgroups per observable pass: 8 per compute unit, 4 of them
+// resident at a time (LDS); measured at 30 qubits complex64: 2048 beats 1024
+// by 3.5% (shorter ranges even out the tail); QSV_EXPECT_GRID overrides
+constexpr int kExpGrid = 2048;
 
 struct ExpPlan {
   int n = 0, L = 0, b = 0;
@@ -648,7 +650,9 @@ int expect_tiled_t(qsv_state* s, qsv_observable* o, double* out) {
   int rc = upload_exp_plan(pl, s->device);
   if (rc) return rc;
   const uint64_t tiles = dim(s->n - pl->L);
-  const uint64_t grid = std::min<uint64_t>(tiles, kExpGrid);
+  uint64_t gmax = kExpGrid;
+  if (const char* e = std::getenv("QSV_EXPECT_GRID")) gmax = uint64_t(std::max(1, std::atoi(e)));  // tuning
+  const uint64_t grid = std::min<uint64_t>(tiles, gmax);
   if ((rc = ensure_reduce_scratch(s, size_t(grid) + 1))) return rc;
   const size_t lds = (size_t(1) << pl->L) * sizeof(cx<R>);
   // kernel variant: tile of the default size (compile-time trip counts), at
