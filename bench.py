@@ -19,10 +19,14 @@ Extra legs (same JSON line):
                 differences on the same kernels (FD timed on a sample of
                 parameters; both reported as gradient components per second)
   batch_vqe     512 hardware-efficient-ansatz items of 12..18 qubits: one
-                persistent launch vs one adjoint call per item
-  random_26q    26-qubit Haar-1q + random-CZ circuit, fused vs unfused
+                persistent launch (graph replay, launch shape autotuned
+                beforehand) vs one adjoint call per item
+  random_26q    26-qubit Haar-1q + random-CZ circuit, fused vs unfused, and
+                the plan the autotuner picks (fusion width, tile shape)
   adjoint_32q   32-qubit complex64 forward + adjoint pass (1920 gates, 1280
                 parameters), one gradient component checked by the shift rule
+  autotune_30q  the headline circuit's plan picked by the autotuner vs the
+                default plan
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode fused|unfused]
                        [--quick] [--no-cpu] [--leg NAME]
@@ -91,7 +95,8 @@ def traffic_from_profile(kernel_prefix):
 
 
 def sync(Q, state):
-    state.norm2()  # a reduction that synchronises the state's stream
+    import torch
+    torch.cuda.synchronize()  # device-wide: covers the stream the state's kernels run on
 
 
 def read_families(Q, steps):
