@@ -84,6 +84,67 @@ __global__ void __launch_bounds__(256) k_pair_adj(float* __restrict__ psi, const
   }
 }
 
+// One-qubit gate on qubit t, streamed: wavefront w reads and writes the
+// contiguous 16-byte vectors 64 w .. 64 w + 63 (one amplitude pair for
+// complex64, one amplitude for complex128 per vector), so every access
+// instruction covers whole cache lines. Dense / exchange gates on a low qubit
+// (the pair partner within the same wavefront: lane XOR dl) take the
+// partner's values by a lane shuffle; diagonal gates need no partner and run
+// on any qubit. Amplitudes whose index does not match the controls
+// (index & cm) == cv keep their value (both members of a pair agree: controls
+// are not the target). nvec (the vector count) is a multiple of 64.
+template <typename R, int KIND>
+__global__ void __launch_bounds__(256) k_pair_lane(R* __restrict__ psi, const PairArgs<R> a, int t, uint64_t nvec,
+                                                   uint64_t cm, uint64_t cv) {
+  constexpr int V = sizeof(R) == 4 ? 2 : 1;  // amplitudes per vector
+  const int dl = KIND == PK_DIAG ? 0 : (1 << t) / V;
+  const bool upper = (threadIdx.x & 63) & dl;  // this lane holds the bit-t = 1 members
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < nvec; v += stride) {
+    cx<R> x[V];
+    AmpIO<R, V>::load(psi, v * V, x);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const uint64_t idx = v * V + k;
+      const bool on = (idx & cm) == cv;
+      cx<R> r;
+      if constexpr (KIND == PK_DIAG) {
+        r = (((idx >> t) & 1) ? a.u.m11 : a.u.m00) * x[k];
+      } else {
+        const cx<R> y{__shfl_xor(x[k].re, dl, 64), __shfl_xor(x[k].im, dl, 64)};
+        if constexpr (KIND == PK_DENSE) {
+          r = upper ? cfma(a.u.m10, y, a.u.m11 * x[k]) : cfma(a.u.m00, x[k], a.u.m01 * y);
+        } else {
+          r = y;
+        }
+      }
+      x[k] = {on ? r.re : x[k].re, on ? r.im : x[k].im};
+    }
+    AmpIO<R, V>::store(psi, v * V, x);
+  }
+}
+
+// One-entry phase (x *= c where (x & mask) == pattern) streamed over every
+// 16-byte vector: for masks with a low bit, whose strided accesses would
+// touch every line anyway. nvec is a multiple of 64 (whole wavefronts).
+template <typename R>
+__global__ void __launch_bounds__(256) k_scale_lane(R* __restrict__ psi, cx<R> c, uint64_t mask, uint64_t pattern,
+                                                    uint64_t nvec) {
+  constexpr int V = sizeof(R) == 4 ? 2 : 1;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < nvec; v += stride) {
+    cx<R> x[V];
+    AmpIO<R, V>::load(psi, v * V, x);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const cx<R> r = c * x[k];
+      const bool on = ((v * V + k) & mask) == pattern;
+      x[k] = {on ? r.re : x[k].re, on ? r.im : x[k].im};
+    }
+    AmpIO<R, V>::store(psi, v * V, x);
+  }
+}
+
 template <typename R>
 struct ScaleArgs {
   uint64_t nthreads;
@@ -203,7 +264,9 @@ int lowest_bit(uint64_t mask) {
 // number of B0 elements.
 int pick_vec(qsv_dtype dt, int lowest, int free_bits) {
   int v = 1;
-  const int maxlog = dt == QSV_C64 ? 2 : 1;
+  // one 16-byte vector per member and thread: a wavefront's access covers
+  // 1 KiB of whole lines once the pair distance reaches a line
+  const int maxlog = dt == QSV_C64 ? 1 : 0;
   int lg = std::min(std::min(lowest, maxlog), free_bits);
   if (lg < 0) lg = 0;
   v = 1 << lg;
@@ -227,6 +290,36 @@ int launch_pair_t(qsv_state* s, uint64_t ins_mask, uint64_t or_mask, uint64_t of
   R* psi = static_cast<R*>(s->ptr);
   dim3 grid;
   int rc;
+  // no controls: streamed 16-byte vectors -- diagonal gates on any qubit,
+  // dense and exchange gates on the low qubits whose pair partner sits in the
+  // same wavefront (complex64: qubits 1..6, complex128: 0..5)
+  // and (one control) gates on those low qubits, whose strided pair accesses
+  // would waste most of each line
+  {
+    constexpr int V = sizeof(R) == 4 ? 2 : 1;
+    const bool pairs = offA == 0 && offB != 0 && (offB & (offB - 1)) == 0 && (ins_mask & offB) &&
+                       (or_mask & ~(ins_mask & ~offB)) == 0;
+    const int t = pairs ? __builtin_ctzll(offB) : -1;
+    const uint64_t cmask = pairs ? ins_mask & ~offB : 0;
+    const int nctrl = __builtin_popcountll(cmask);
+    const uint64_t nvec = (uint64_t(1) << s->n) / V;
+    const bool low = sizeof(R) == 4 ? (t >= 1 && t <= 6) : (t >= 0 && t <= 5);
+    if (pairs && nvec % 64 == 0 && ((nctrl == 0 && (kind == PK_DIAG || low)) || (nctrl == 1 && low))) {
+      if ((rc = launch_grid(nvec, &grid))) return rc;
+      ProfScope ps("pair", 4.0 * sizeof(R) * 2 * double(uint64_t(1) << free_bits), s->stream);
+      if (kind == PK_DENSE)
+        hipLaunchKernelGGL((k_pair_lane<R, PK_DENSE>), grid, dim3(256), 0, s->stream, psi, a, t, nvec, cmask,
+                           or_mask);
+      else if (kind == PK_DIAG)
+        hipLaunchKernelGGL((k_pair_lane<R, PK_DIAG>), grid, dim3(256), 0, s->stream, psi, a, t, nvec, cmask,
+                           or_mask);
+      else
+        hipLaunchKernelGGL((k_pair_lane<R, PK_SWAP>), grid, dim3(256), 0, s->stream, psi, a, t, nvec, cmask,
+                           or_mask);
+      QSV_HIP_CHECK(hipGetLastError());
+      return QSV_OK;
+    }
+  }
   // complex64, gate on qubit 0 (offsets 0 and 1): one 16-byte vector per pair
   if constexpr (sizeof(R) == 4) {
     if (offA == 0 && offB == 1) {
@@ -276,6 +369,22 @@ int launch_pair(qsv_state* s, uint64_t ins_mask, uint64_t or_mask, uint64_t offA
 
 template <typename R>
 int launch_scale_t(qsv_state* s, uint64_t mask, uint64_t pattern, cd c) {
+  {
+    // a low mask bit: stream whole lines instead of strided 8- / 16-byte accesses
+    constexpr int V = sizeof(R) == 4 ? 2 : 1;
+    const uint64_t nvec = (uint64_t(1) << s->n) / V;
+    if (mask && __builtin_ctzll(mask) < (sizeof(R) == 4 ? 3 : 2) && nvec % 64 == 0) {
+      dim3 grid;
+      int rc;
+      if ((rc = launch_grid(nvec, &grid))) return rc;
+      const int m = __builtin_popcountll(mask);
+      ProfScope ps("scale", 2.0 * sizeof(R) * 2 * double(uint64_t(1) << (s->n - m)), s->stream);
+      hipLaunchKernelGGL((k_scale_lane<R>), grid, dim3(256), 0, s->stream, static_cast<R*>(s->ptr), to_dev<R>(c),
+                         mask, pattern, nvec);
+      QSV_HIP_CHECK(hipGetLastError());
+      return QSV_OK;
+    }
+  }
   ScaleArgs<R> a{};
   InsertPos ip;
   sort_positions(mask, &ip);

@@ -88,8 +88,9 @@ def test_named_one_qubit(dt, name):
 
 @pytest.mark.parametrize("dt", DTYPES)
 def test_two_qubit_named_all_pairs(dt):
+    # (8 qubits: the streamed kernels for low targets and low phase masks)
     rng = np.random.default_rng(8)
-    for n in (2, 3, 6):
+    for n in (2, 3, 6, 8):
         psi = rand_state(rng, n)
         for a, b in itertools.permutations(range(n), 2):
             for name in ("cnot", "cz", "swap"):
