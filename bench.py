@@ -95,8 +95,7 @@ def traffic_from_profile(kernel_prefix):
 
 
 def sync(Q, state):
-    import torch
-    torch.cuda.synchronize()  # device-wide: covers the stream the state's kernels run on
+    state.sync()  # the stream every kernel of the step runs on
 
 
 def read_families(Q, steps):

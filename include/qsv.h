@@ -98,6 +98,9 @@ int qsv_state_free(qsv_state* s);
 /* Report qubit count, dtype and device pointer (any out pointer may be NULL). */
 int qsv_state_info(const qsv_state* s, int* n, int* dtype, void** dev_ptr);
 
+/* Wait for all work enqueued on the state's stream (QSV_EHIP if it failed). */
+int qsv_state_sync(const qsv_state* s);
+
 /* Set the state to the computational basis state |k> (section 4.2.1). */
 int qsv_set_basis(qsv_state* s, uint64_t k);
 

@@ -36,6 +36,7 @@ _SIGS = {
     "qsv_state_wrap": (_c.c_int, [_vp, _c.c_int, _c.c_int, _vp, _c.POINTER(_vp)]),
     "qsv_state_free": (_c.c_int, [_vp]),
     "qsv_state_info": (_c.c_int, [_vp, _ip, _ip, _c.POINTER(_vp)]),
+    "qsv_state_sync": (_c.c_int, [_vp]),
     "qsv_set_basis": (_c.c_int, [_vp, _c.c_uint64]),
     "qsv_load": (_c.c_int, [_vp, _dp]),
     "qsv_store": (_c.c_int, [_vp, _dp]),
@@ -201,6 +202,10 @@ class State:
     def apply_named(self, name: str, qubits, theta: float = 0.0):
         q = _ints(qubits)
         check(lib().qsv_apply_named(self.h, GATE[name], _iptr(q), len(qubits), float(theta)))
+
+    def sync(self):
+        """Wait for the work enqueued on the state's stream."""
+        check(lib().qsv_state_sync(self.h))
 
     def norm2(self) -> float:
         out = _c.c_double()

@@ -370,24 +370,30 @@ __global__ void __launch_bounds__(1 << TB)
   const uint32_t tau = threadIdx.x;
   const int wave = int(tau >> 6);
   for (int i = int(tau); i < kAdjMaxRows * NW; i += blockDim.x) slot[i / NW][i % NW] = 0.0;
-  auto gbit = [&](int p) -> uint64_t { return uint64_t(1) << (p < b ? p : P.hq[p - b]); };
   // tiles of this workgroup: a contiguous range (fixed order of its partial sums)
   uint64_t gmask = 0;
-  for (int j = 0; j < P.ng; ++j) gmask |= uint64_t(1) << P.gpos[j];
+  for (int r = 0; r < P.nrun; ++r) gmask |= ((uint64_t(1) << P.rlen[r]) - 1) << P.rdst[r];
   const uint64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
   const uint64_t g0 = uint64_t(blockIdx.x) * per;
   const uint64_t gend = g0 + per < ntiles ? g0 + per : ntiles;
   uint64_t base = 0;
-  for (int j = 0; j < P.ng; ++j) base |= ((g0 >> j) & 1) << P.gpos[j];
+  for (int r = 0; r < P.nrun; ++r) base |= ((g0 >> P.rsrc[r]) & ((uint64_t(1) << P.rlen[r]) - 1)) << P.rdst[r];
   const RegSegDev* S0 = &segs[P.seg_begin];
   const RegSegDev* SL = &segs[P.seg_begin + P.seg_count - 1];
-  auto addr = [&](const RegSegDev& s, uint64_t bs, int i) -> uint64_t {
-    uint64_t x = bs;
-    for (int k = 0; k < TB; ++k)
-      if ((tau >> k) & 1) x |= gbit(s.thr[k]);
+  // HBM address parts of the first and last layouts: per thread (fixed for
+  // the kernel) and per register element (uniform columns)
+  uint64_t th0 = 0, thL = 0;
+#pragma unroll
+  for (int k = 0; k < TB; ++k) {
+    const uint64_t on = uint64_t(0) - ((tau >> k) & 1);
+    th0 |= S0->gcol_t[k] & on;
+    thL |= SL->gcol_t[k] & on;
+  }
+  auto addr = [&](const RegSegDev& s, uint64_t th, uint64_t bs, int i) -> uint64_t {
+    uint64_t x = bs | th;
 #pragma unroll
     for (int k = 0; k < RB; ++k)
-      if ((i >> k) & 1) x |= gbit(s.reg[k]);
+      if ((i >> k) & 1) x |= s.gcol_r[k];
     return x;
   };
   cx<R> vs[NR], vl[NR], ws[NR], wl[NR];
@@ -397,14 +403,14 @@ __global__ void __launch_bounds__(1 << TB)
     if (sizeof(R) == 4 && S0->reg[0] == 0) {
 #pragma unroll
       for (int i = 0; i < NR; i += 2) {
-        const uint64_t x = addr(*S0, base, i);
+        const uint64_t x = addr(*S0, th0, base, i);
         AmpIO<R, 2>::load(psi, x, &vs[i]);
         AmpIO<R, 2>::load(lam, x, &vl[i]);
       }
     } else {
 #pragma unroll
       for (int i = 0; i < NR; ++i) {
-        const uint64_t x = addr(*S0, base, i);
+        const uint64_t x = addr(*S0, th0, base, i);
         AmpIO<R, 1>::load(psi, x, &vs[i]);
         AmpIO<R, 1>::load(lam, x, &vl[i]);
       }
@@ -441,14 +447,14 @@ __global__ void __launch_bounds__(1 << TB)
     if (sizeof(R) == 4 && SL->reg[0] == 0) {
 #pragma unroll
       for (int i = 0; i < NR; i += 2) {
-        const uint64_t x = addr(*SL, base, i);
+        const uint64_t x = addr(*SL, thL, base, i);
         AmpIO<R, 2>::store(psi, x, &vs[i]);
         AmpIO<R, 2>::store(lam, x, &vl[i]);
       }
     } else {
 #pragma unroll
       for (int i = 0; i < NR; ++i) {
-        const uint64_t x = addr(*SL, base, i);
+        const uint64_t x = addr(*SL, thL, base, i);
         AmpIO<R, 1>::store(psi, x, &vs[i]);
         AmpIO<R, 1>::store(lam, x, &vl[i]);
       }

@@ -243,6 +243,14 @@ int qsv_state_info(const qsv_state* s, int* n, int* dtype, void** dev_ptr) {
   return QSV_OK;
 }
 
+int qsv_state_sync(const qsv_state* s) {
+  clear_error();
+  int rc = check_state(s);
+  if (rc) return rc;
+  QSV_HIP_CHECK(hipStreamSynchronize(s->stream));
+  return QSV_OK;
+}
+
 int qsv_set_basis(qsv_state* s, uint64_t k) {
   clear_error();
   int rc = check_state(s);
