@@ -64,6 +64,10 @@ def lib():
         L.orc_expectation.restype = ctypes.c_int
         L.orc_apply_observable.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, dp, ip, ip, ip]
         L.orc_apply_observable.restype = ctypes.c_int
+        L.orc_pauli_rotation.argtypes = [dp, ctypes.c_int, ctypes.c_int, ip, ip, ctypes.c_double]
+        L.orc_pauli_rotation.restype = ctypes.c_int
+        L.orc_transition.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, dp, ip, ip, ip, dp, dp]
+        L.orc_transition.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -128,7 +132,20 @@ def gate_matrix_and_qubits(g, theta=None):
     raise ValueError(op)
 
 
+def pauli_rotation(psi: np.ndarray, qubits, paulis, theta: float) -> None:
+    """psi <- exp(+i theta P / 2) psi for the Pauli string P (ids 1..3 on qubits)."""
+    n = int(psi.size).bit_length() - 1
+    q = np.asarray(qubits, dtype=np.int32)
+    p = np.asarray(paulis, dtype=np.int32)
+    if lib().orc_pauli_rotation(_dp(psi), n, len(q), _ip(q), _ip(p), float(theta)) != 0:
+        raise ValueError("oracle rejected Pauli rotation")
+
+
 def apply_gate(psi, g, theta=None):
+    if g["op"] == "pauli_rot":
+        ang = theta[g["slot"]] if "slot" in g else g["angle"]
+        pauli_rotation(psi, g["q"], g["paulis"], ang)
+        return
     m, t, c, v = gate_matrix_and_qubits(g, theta)
     apply_matrix(psi, m, t, c, v)
 
@@ -164,6 +181,19 @@ def expectation_complex(psi: np.ndarray, obs) -> complex:
 
 def expectation(psi: np.ndarray, obs) -> float:
     return expectation_complex(psi, obs).real
+
+
+def transition_amplitude(a: np.ndarray, b: np.ndarray, obs) -> complex:
+    """<a|O|b> (complex)."""
+    n = int(a.size).bit_length() - 1
+    coefs, lens, qs, ps = _encode_obs(obs)
+    re = ctypes.c_double()
+    im = ctypes.c_double()
+    rc = lib().orc_transition(_dp(a), _dp(b), n, len(obs), _dp(coefs), _ip(lens), _ip(qs), _ip(ps),
+                              ctypes.byref(re), ctypes.byref(im))
+    if rc != 0:
+        raise ValueError("oracle rejected observable")
+    return complex(re.value, im.value)
 
 
 def apply_observable(psi: np.ndarray, obs) -> np.ndarray:

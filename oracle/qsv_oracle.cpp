@@ -13,6 +13,10 @@
 // Parity status of each entry point (what pins it is in the test suite):
 //   orc_set_basis, orc_apply_matrix, orc_named_matrix, orc_expectation,
 //   orc_norm2, orc_inner: pinned (closed forms, brute force, printed fixture).
+//   orc_pauli_rotation: pinned (one-qubit case = RX/RY/RZ matrices, matrix
+//   exponential of the Kronecker-product string for n <= 4, ZZ phases on basis
+//   states). orc_transition: pinned (a = b gives orc_expectation's value,
+//   brute-force a^dagger O b for n <= 4).
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -279,6 +283,84 @@ int orc_apply_observable(const double* psi, double* out, int n, int nterms, cons
     }
     off += w;
   }
+  return 0;
+}
+
+// Multi-qubit Pauli rotation exp(+i theta P / 2) (section 4.3.3, Pauli
+// rotation; the factor 1/2 follows the one-qubit rotations of Table 1), P a
+// Pauli string on w distinct qubits (ids 1..3; 0 = identity on that qubit).
+// Since P^2 = I, exp(i theta P/2) = cos(theta/2) I + i sin(theta/2) P; P psi is
+// formed from the matrix elements as in orc_apply_observable. Returns -1 on a
+// bad qubit / pauli id or a repeated qubit.
+int orc_pauli_rotation(double* psi, int n, int w, const int* qubits, const int* paulis, double theta) {
+  static const cplx kPauli[4][2][2] = {
+      {{1.0, 0.0}, {0.0, 1.0}},
+      {{0.0, 1.0}, {1.0, 0.0}},
+      {{0.0, cplx(0.0, -1.0)}, {cplx(0.0, 1.0), 0.0}},
+      {{1.0, 0.0}, {0.0, -1.0}},
+  };
+  const uint64_t N = uint64_t(1) << n;
+  uint64_t flip = 0, seen = 0;
+  for (int j = 0; j < w; ++j) {
+    if (qubits[j] < 0 || qubits[j] >= n || paulis[j] < 0 || paulis[j] > 3) return -1;
+    if (seen >> qubits[j] & 1) return -1;
+    seen |= uint64_t(1) << qubits[j];
+    if (paulis[j] == 1 || paulis[j] == 2) flip |= uint64_t(1) << qubits[j];
+  }
+  cplx* v = as_c(psi);
+  std::vector<cplx> pv(N);
+  for (uint64_t x = 0; x < N; ++x) {
+    const uint64_t y = x ^ flip;  // the one nonzero column of row y
+    cplx elem = 1.0;
+    for (int j = 0; j < w; ++j) elem *= kPauli[paulis[j]][(y >> qubits[j]) & 1][(x >> qubits[j]) & 1];
+    pv[y] = elem * v[x];
+  }
+  const double c = std::cos(0.5 * theta), s = std::sin(0.5 * theta);
+  for (uint64_t x = 0; x < N; ++x) v[x] = c * v[x] + cplx(0.0, s) * pv[x];
+  return 0;
+}
+
+// Transition amplitude <a|O|b> = sum_k alpha_k sum_{x,y} conj(a_y) (P_k)_{y,x} b_x
+// (section 4.5, get_transition_amplitude), complex, same term encoding as
+// orc_expectation.
+int orc_transition(const double* a, const double* b, int n, int nterms, const double* coefs,
+                   const int* term_len, const int* qubits, const int* paulis, double* out_re,
+                   double* out_im) {
+  static const cplx kPauli[4][2][2] = {
+      {{1.0, 0.0}, {0.0, 1.0}},
+      {{0.0, 1.0}, {1.0, 0.0}},
+      {{0.0, cplx(0.0, -1.0)}, {cplx(0.0, 1.0), 0.0}},
+      {{1.0, 0.0}, {0.0, -1.0}},
+  };
+  const uint64_t N = uint64_t(1) << n;
+  const cplx* va = as_c(a);
+  const cplx* vb = as_c(b);
+  Neumaier re, im;
+  int off = 0;
+  for (int t = 0; t < nterms; ++t) {
+    const int w = term_len[t];
+    uint64_t flip = 0;
+    for (int j = 0; j < w; ++j) {
+      if (qubits[off + j] < 0 || qubits[off + j] >= n || paulis[off + j] < 0 || paulis[off + j] > 3)
+        return -1;
+      if (paulis[off + j] == 1 || paulis[off + j] == 2) flip |= uint64_t(1) << qubits[off + j];
+    }
+    Neumaier tre, tim;
+    for (uint64_t x = 0; x < N; ++x) {
+      const uint64_t y = x ^ flip;
+      cplx elem = 1.0;
+      for (int j = 0; j < w; ++j)
+        elem *= kPauli[paulis[off + j]][(y >> qubits[off + j]) & 1][(x >> qubits[off + j]) & 1];
+      const cplx c = std::conj(va[y]) * elem * vb[x];
+      tre.add(c.real());
+      tim.add(c.imag());
+    }
+    re.add(coefs[t] * tre.value());
+    im.add(coefs[t] * tim.value());
+    off += w;
+  }
+  *out_re = re.value();
+  *out_im = im.value();
   return 0;
 }
 

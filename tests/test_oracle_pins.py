@@ -381,3 +381,74 @@ def test_oracle_rejects_bad_gates():
         O.apply_matrix(psi, np.eye(4), [1, 1])
     with pytest.raises(ValueError):
         O.apply_matrix(psi, np.eye(2), [0], [0], [1])
+
+
+# ---------------------------------------------------------------- Pauli rotations, transition amplitudes
+
+_PAULI = [np.eye(2), np.array([[0, 1], [1, 0]]), np.array([[0, -1j], [1j, 0]]), np.array([[1, 0], [0, -1]])]
+
+
+def _string_matrix(n, qubits, paulis):
+    # qubit 0 is the right-most Kronecker factor (index x = sum x_q 2^q)
+    mats = [np.eye(2)] * n
+    for q, p in zip(qubits, paulis):
+        mats[q] = _PAULI[p]
+    full = np.array(mats[n - 1], dtype=complex)
+    for q in range(n - 2, -1, -1):
+        full = np.kron(full, mats[q])
+    return full
+
+
+def test_pauli_rotation_one_qubit_is_the_named_rotation():
+    rng = np.random.default_rng(41)
+    for p, name in ((1, "rx"), (2, "ry"), (3, "rz")):
+        for q in range(3):
+            psi = rng.standard_normal(8) + 1j * rng.standard_normal(8)
+            th = rng.uniform(0, 6.3)
+            a = psi.copy()
+            O.pauli_rotation(a, [q], [p], th)
+            b = psi.copy()
+            O.apply_matrix(b, O.named_matrix(name, th), [q])
+            assert np.max(np.abs(a - b)) <= 1e-14
+
+
+def test_pauli_rotation_is_the_matrix_exponential():
+    from scipy.linalg import expm
+    rng = np.random.default_rng(42)
+    for n in (2, 3, 4):
+        for _ in range(6):
+            w = int(rng.integers(1, n + 1))
+            qs = [int(q) for q in rng.choice(n, size=w, replace=False)]
+            ps = [int(p) for p in rng.integers(1, 4, size=w)]
+            th = rng.uniform(-6.3, 6.3)
+            psi = rng.standard_normal(2 ** n) + 1j * rng.standard_normal(2 ** n)
+            ref = expm(0.5j * th * _string_matrix(n, qs, ps)) @ psi
+            got = psi.copy()
+            O.pauli_rotation(got, qs, ps, th)
+            assert np.max(np.abs(got - ref)) <= 1e-13
+
+
+def test_zz_rotation_phases_on_basis_states():
+    th = 0.83
+    for k in range(16):
+        psi = O.basis_state(4, k)
+        O.pauli_rotation(psi, [1, 3], [3, 3], th)
+        s = 1 - 2 * (((k >> 1) & 1) ^ ((k >> 3) & 1))
+        assert abs(psi[k] - np.exp(0.5j * th * s)) <= 1e-15
+        assert np.sum(np.abs(psi) > 0) == 1
+
+
+def test_transition_amplitude_pins():
+    rng = np.random.default_rng(43)
+    n = 4
+    obs = [(float(rng.standard_normal()), [(int(q), int(p)) for q, p in
+                                           zip(rng.choice(n, size=2, replace=False), rng.integers(1, 4, size=2))])
+           for _ in range(5)] + [(0.3, [])]
+    a = rng.standard_normal(16) + 1j * rng.standard_normal(16)
+    b = rng.standard_normal(16) + 1j * rng.standard_normal(16)
+    # <a|a> form equals the expectation
+    assert abs(O.transition_amplitude(a, a, obs) - O.expectation_complex(a, obs)) <= 1e-13
+    # brute force a^dagger O b
+    full = sum(c * _string_matrix(n, [q for q, _ in t], [p for _, p in t]) for c, t in obs)
+    ref = np.vdot(a, full @ b)
+    assert abs(O.transition_amplitude(a, b, obs) - ref) <= 1e-12
