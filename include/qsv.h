@@ -162,8 +162,28 @@ int qsv_circuit_add_named(qsv_circuit* c, int kind, const int* qubits, int nq, d
  * circuit's parameter count becomes at least param_slot + 1. */
 int qsv_circuit_add_rotation(qsv_circuit* c, int pauli_id, int qubit, int param_slot);
 
+/* Append a multi-qubit Pauli rotation exp(+i theta P / 2) (section 4.3.3,
+ * Pauli rotation; the factor 1/2 as in Table 1's one-qubit rotations, so a
+ * one-qubit string is RX/RY/RZ), P = prod_j sigma_{pauli_ids[j]} on qubits[j]
+ * (ids 0..3 = I, X, Y, Z; distinct qubits, 1 <= w <= n). param_slot >= 0:
+ * theta = theta[param_slot] at apply time (the circuit's parameter count grows
+ * to param_slot + 1); param_slot < 0: the fixed angle `theta`. Fused plans take
+ * strings of up to 5 non-identity factors (a dense block; pure-Z strings are
+ * diagonal); qsv_adjoint_gradient takes them with the per-gate reverse sweep;
+ * batches reject them (QSV_EINVAL). Errors: QSV_EINVAL, QSV_ERANGE, QSV_EDUP. */
+int qsv_circuit_add_pauli_rotation(qsv_circuit* c, const int* qubits, const int* pauli_ids, int w,
+                                   int param_slot, double theta);
+
 /* Qubit count, gate count and parameter count (any out pointer may be NULL). */
 int qsv_circuit_info(const qsv_circuit* c, int* n, int* gates, int* nparams);
+
+/* psi <- exp(+i theta P / 2) psi for the Pauli string P = prod_j
+ * sigma_{pauli_ids[j]} on qubits[j] (section 4.3.3; ids 0..3, distinct qubits,
+ * 0 <= w <= n): one sweep over the amplitude pairs (x, x ^ F), F the X/Y
+ * qubits (P's one nonzero per column is i^nY (-1)^|x & z|, z the Z/Y qubits).
+ * Asynchronous on the state's stream. Errors: QSV_EINVAL (bad id or length,
+ * null lists), QSV_ERANGE (qubit out of range), QSV_EDUP (repeated qubit). */
+int qsv_apply_pauli_rotation(qsv_state* s, const int* qubits, const int* pauli_ids, int w, double theta);
 
 /* Apply every gate in order, one kernel launch per gate (section 4.4,
  * update_quantum_state). theta: the parameter vector (may be NULL when the
@@ -248,6 +268,14 @@ int qsv_observable_add_term(qsv_observable* o, double coef, const int* qubits,
 /* Number of qubits, terms and distinct flip masks (X/Y positions); any out
  * pointer may be NULL. Terms sharing a flip mask share one pass over the state. */
 int qsv_observable_info(const qsv_observable* o, int* n, int* terms, int* groups);
+
+/* Transition amplitude <bra|O|ket> = sum_k alpha_k <bra|P_k|ket> (section
+ * 4.5, get_transition_amplitude), complex, accumulated in FP64 (one sweep of
+ * both states per term; per-block partials summed in a fixed order). Both
+ * states have the observable's qubit count and one dtype. Synchronises.
+ * Errors: QSV_EINVAL (null arguments), QSV_ERANGE, QSV_EDTYPE. */
+int qsv_transition_amplitude(const qsv_state* bra, const qsv_observable* o, const qsv_state* ket,
+                             double* re, double* im);
 
 /* Number of state passes an expectation (or qsv_apply_observable) of this
  * observable takes for states of dtype `dtype`: its flip masks packed into

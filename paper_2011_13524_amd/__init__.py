@@ -3,4 +3,5 @@
 package as a thin ctypes binding."""
 from .binding import (LIB_PATH, Batch, Circuit, Observable, Plan, QsvError, State,  # noqa: F401
                       adjoint_gradient, apply_circuit, apply_fused, apply_observable,
-                      apply_record, expectation, lib, prof_enable, prof_read)
+                      apply_pauli_rotation, apply_record, expectation, lib, prof_enable, prof_read,
+                      transition_amplitude)

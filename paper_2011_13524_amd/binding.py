@@ -56,6 +56,9 @@ _SIGS = {
     "qsv_circuit_add_gate": (_c.c_int, [_vp, _dp, _ip, _c.c_int, _ip, _ip, _c.c_int]),
     "qsv_circuit_add_named": (_c.c_int, [_vp, _c.c_int, _ip, _c.c_int, _c.c_double]),
     "qsv_circuit_add_rotation": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int]),
+    "qsv_circuit_add_pauli_rotation": (_c.c_int, [_vp, _ip, _ip, _c.c_int, _c.c_int, _c.c_double]),
+    "qsv_apply_pauli_rotation": (_c.c_int, [_vp, _ip, _ip, _c.c_int, _c.c_double]),
+    "qsv_transition_amplitude": (_c.c_int, [_vp, _vp, _vp, _dp, _dp]),
     "qsv_circuit_info": (_c.c_int, [_vp, _ip, _ip, _ip]),
     "qsv_apply_circuit": (_c.c_int, [_vp, _vp, _dp]),
     "qsv_plan_fused": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.POINTER(_vp)]),
@@ -285,6 +288,10 @@ class Circuit:
             q = _ints(g["q"])
             check(lib().qsv_circuit_add_named(self.h, GATE[op], _iptr(q), len(g["q"]),
                                               float(g.get("angle", 0.0))))
+        elif op == "pauli_rot":
+            q, p = _ints(g["q"]), _ints(g["paulis"])
+            check(lib().qsv_circuit_add_pauli_rotation(self.h, _iptr(q), _iptr(p), len(g["q"]),
+                                                       int(g.get("slot", -1)), float(g.get("angle", 0.0))))
         elif op == "dense":
             m = np.ascontiguousarray(np.asarray(g["mat"], dtype=np.complex128))
             t = _ints(g["q"])
@@ -462,5 +469,21 @@ def apply_record(state: State, g, theta=None):
         state.apply_named(op, g["q"])
     elif op == "dense":
         state.apply_gate(g["mat"], g["q"], g.get("controls", ()), g.get("ctrl_vals", ()))
+    elif op == "pauli_rot":
+        ang = theta[g["slot"]] if "slot" in g else g["angle"]
+        apply_pauli_rotation(state, g["q"], g["paulis"], ang)
     else:
         raise ValueError(op)
+
+
+def apply_pauli_rotation(state: State, qubits, paulis, theta: float):
+    """psi <- exp(+i theta P / 2) psi (qsv_apply_pauli_rotation)."""
+    q, p = _ints(qubits), _ints(paulis)
+    check(lib().qsv_apply_pauli_rotation(state.h, _iptr(q), _iptr(p), len(qubits), float(theta)))
+
+
+def transition_amplitude(bra: State, obs: "Observable", ket: State) -> complex:
+    """<bra|O|ket> (qsv_transition_amplitude)."""
+    re, im = _c.c_double(), _c.c_double()
+    check(lib().qsv_transition_amplitude(bra.h, obs.h, ket.h, _c.byref(re), _c.byref(im)))
+    return complex(re.value, im.value)

@@ -137,14 +137,17 @@ int adjoint_t(const qsv_circuit* c, qsv_plan* plan, const double* theta, const q
   *energy = re;
   // backward
   int nrot = 0;
-  for (const Gate& g : c->gates)
-    if (g.kind == Gate::ROTATION && g.slot >= 0) ++nrot;
+  bool pauli = false;  // multi-qubit Pauli rotations: per-gate sweep only
+  for (const Gate& g : c->gates) {
+    if ((g.kind == Gate::ROTATION || g.kind == Gate::PAULI) && g.slot >= 0) ++nrot;
+    if (g.kind == Gate::PAULI) pauli = true;
+  }
   // large states: reverse sweep by tile passes (both states streamed once per
   // pass); small states keep one launch per gate, which spreads better
   const int Ltile = sizeof(R) == 4 ? 12 : 11;
   int tiled_min = Ltile + 8;
   if (const char* e = std::getenv("QSV_ADJOINT_TILED_MIN")) tiled_min = std::atoi(e);  // testing
-  if (n >= tiled_min) {
+  if (n >= tiled_min && !pauli) {
     std::vector<int> rs;
     std::vector<double> rv;
     if ((rc = adjoint_backward_tiled<R>(c, theta, psi, lam, rs, rv))) return rc;
@@ -161,6 +164,20 @@ int adjoint_t(const qsv_circuit* c, qsv_plan* plan, const double* theta, const q
   std::vector<cd> m;
   for (int gi = int(c->gates.size()) - 1; gi >= 0; --gi) {
     const Gate& g = c->gates[gi];
+    if (g.kind == Gate::PAULI) {
+      const double t = g.slot >= 0 ? theta[g.slot] : g.fixed_angle;
+      if (g.slot >= 0) {
+        // gradient -Im<lambda|P|psi> and the uncompute in one sweep
+        --row;
+        row_slot[row] = g.slot;
+        if ((rc = adjoint_pauli_step(psi, lam, g, t, partial + size_t(row) * B, B))) return rc;
+      } else {
+        const int w = int(g.targets.size());
+        if ((rc = pauli_rotation_impl(psi, g.targets.data(), g.paulis.data(), w, -t))) return rc;
+        if ((rc = pauli_rotation_impl(lam, g.targets.data(), g.paulis.data(), w, -t))) return rc;
+      }
+      continue;
+    }
     if (g.kind == Gate::ROTATION && g.slot >= 0) {
       --row;
       row_slot[row] = g.slot;

@@ -627,6 +627,8 @@ int build_device(qsv_batch* b, qsv_dtype dt) {
     I.op_begin = int(ops.size());
     for (const Gate& g : it.c.gates) {
       BatchOp op{};
+      if (g.kind == Gate::PAULI)
+        return fail(QSV_EINVAL, "batched items support one-qubit gates, rotations, CZ and CNOT");
       if (g.kind == Gate::ROTATION) {
         op.kind = BO_ROT;
         op.q0 = g.targets[0];

@@ -10,7 +10,7 @@
 namespace qsv {
 
 struct Gate {
-  enum Kind { MATRIX = 0, ROTATION = 1 };
+  enum Kind { MATRIX = 0, ROTATION = 1, PAULI = 2 };
   int kind = MATRIX;
   std::vector<int> targets;
   std::vector<int> controls;
@@ -21,7 +21,18 @@ struct Gate {
   int pauli = 0;
   int slot = -1;
   double fixed_angle = 0.0;
+  // PAULI: exp(+i angle P / 2) for the Pauli string paulis[j] (1..3) on
+  // targets[j] (identity factors dropped); angle as for ROTATION
+  std::vector<int> paulis;
 };
+
+// psi <- exp(+i t P / 2) psi for a Pauli string (ids 0..3 on distinct qubits).
+int pauli_rotation_impl(qsv_state* s, const int* qubits, const int* ids, int w, double t);
+
+// Reverse-sweep step of a parametric PAULI gate at angle t: B partials of its
+// gradient -Im<lam|P|psi> into partial_row (grid of B workgroups), then psi
+// and lam uncomputed.
+int adjoint_pauli_step(qsv_state* psi, qsv_state* lam, const Gate& g, double t, double* partial_row, int B);
 
 // Gate matrix of a gate for the given parameters (row-major, 2^k x 2^k).
 void gate_matrix(const Gate& g, const double* theta, std::vector<cd>& out);

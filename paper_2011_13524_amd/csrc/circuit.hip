@@ -23,6 +23,28 @@ void gate_matrix(const Gate& g, const double* theta, std::vector<cd>& out) {
     out.resize(4);
     const double t = g.slot >= 0 ? theta[g.slot] : g.fixed_angle;
     rotation_matrix(g.pauli, t, out.data());
+  } else if (g.kind == Gate::PAULI) {
+    // c I + i s P on the targets (matrix index bit j <-> targets[j]); one
+    // nonzero of P per column: row r = col ^ F, value prod_j sigma_j[r_j][c_j]
+    const int w = int(g.targets.size());
+    const int D = 1 << w;
+    const double t = g.slot >= 0 ? theta[g.slot] : g.fixed_angle;
+    const double c = std::cos(t / 2), s = std::sin(t / 2);
+    out.assign(size_t(D) * D, cd{0, 0});
+    int F = 0;
+    for (int j = 0; j < w; ++j)
+      if (g.paulis[j] == 1 || g.paulis[j] == 2) F |= 1 << j;
+    for (int col = 0; col < D; ++col) {
+      const int row = col ^ F;
+      cd v{1, 0};
+      for (int j = 0; j < w; ++j) {
+        const int rb = (row >> j) & 1;
+        if (g.paulis[j] == 2) v = cmul(v, rb ? cd{0, 1} : cd{0, -1});  // Y[r][c], c = 1 - r
+        else if (g.paulis[j] == 3 && rb) v = {-v.re, -v.im};           // Z[r][r]
+      }
+      out[size_t(row) * D + col] = cadd(out[size_t(row) * D + col], cmul(cd{0, s}, v));
+      out[size_t(col) * D + col] = cadd(out[size_t(col) * D + col], cd{c, 0});
+    }
   } else {
     out = g.mat;
   }
@@ -31,6 +53,12 @@ void gate_matrix(const Gate& g, const double* theta, std::vector<cd>& out) {
 int circuit_apply_unfused(qsv_state* s, const qsv_circuit* c, const double* theta) {
   std::vector<cd> m;
   for (const Gate& g : c->gates) {
+    if (g.kind == Gate::PAULI) {
+      const double t = g.slot >= 0 ? theta[g.slot] : g.fixed_angle;
+      int rc = pauli_rotation_impl(s, g.targets.data(), g.paulis.data(), int(g.targets.size()), t);
+      if (rc) return rc;
+      continue;
+    }
     gate_matrix(g, theta, m);
     int rc = apply_gate_impl(s, m.data(), g.targets.data(), int(g.targets.size()),
                              g.controls.data(), g.ctrl_vals.data(), int(g.controls.size()));
@@ -128,6 +156,32 @@ int qsv_circuit_add_rotation(qsv_circuit* c, int pauli_id, int qubit, int param_
   g.targets = {qubit};
   c->gates.push_back(std::move(g));
   if (param_slot + 1 > c->nparams) c->nparams = param_slot + 1;
+  return QSV_OK;
+}
+
+int qsv_circuit_add_pauli_rotation(qsv_circuit* c, const int* qubits, const int* pauli_ids, int w,
+                                   int param_slot, double theta) {
+  clear_error();
+  if (!c) return fail(QSV_EINVAL, "null circuit");
+  if (w < 1 || w > c->n) return fail(QSV_EINVAL, "string length %d outside [1, n]", w);
+  if (!qubits || !pauli_ids) return fail(QSV_EINVAL, "null qubit or pauli list");
+  if (param_slot >= (1 << 24)) return fail(QSV_ERANGE, "bad parameter slot");
+  Gate g;
+  g.kind = Gate::PAULI;
+  uint64_t seen = 0;
+  for (int j = 0; j < w; ++j) {
+    if (qubits[j] < 0 || qubits[j] >= c->n) return fail(QSV_ERANGE, "qubit %d out of range", qubits[j]);
+    if (pauli_ids[j] < 0 || pauli_ids[j] > 3) return fail(QSV_EINVAL, "pauli id %d not in 0..3", pauli_ids[j]);
+    if (seen >> qubits[j] & 1) return fail(QSV_EDUP, "qubit %d repeated", qubits[j]);
+    seen |= uint64_t(1) << qubits[j];
+    if (pauli_ids[j] == 0) continue;  // identity factor
+    g.targets.push_back(qubits[j]);
+    g.paulis.push_back(pauli_ids[j]);
+  }
+  g.slot = param_slot < 0 ? -1 : param_slot;
+  g.fixed_angle = theta;
+  c->gates.push_back(std::move(g));
+  if (param_slot >= 0 && param_slot + 1 > c->nparams) c->nparams = param_slot + 1;
   return QSV_OK;
 }
 

@@ -111,6 +111,9 @@ GateInfo analyse(const Gate& g) {
   if (g.kind == Gate::ROTATION) {
     gi.targets = g.targets;
     gi.diagonal = (g.pauli == 3);
+  } else if (g.kind == Gate::PAULI) {
+    gi.targets = g.targets;
+    gi.diagonal = std::all_of(g.paulis.begin(), g.paulis.end(), [](int p) { return p == 3; });
   } else {
     std::vector<cd> m = g.mat;
     std::vector<int> tq = g.targets;
@@ -141,7 +144,7 @@ GateInfo analyse(const Gate& g) {
 
 // Target matrix of a gate in its extracted form, for the given parameters.
 void extracted_matrix(const Gate& g, const GateInfo& gi, const double* theta, std::vector<cd>& m) {
-  if (g.kind == Gate::ROTATION) {
+  if (g.kind == Gate::ROTATION || g.kind == Gate::PAULI) {
     gate_matrix(g, theta, m);
   } else {
     m = gi.mat;
@@ -262,7 +265,7 @@ static int build_plan(qsv_plan* p) {
       B.controls.clear();
       B.ctrl_vals.clear();
     }
-    if (!B.diagonal && B.targets.size() > size_t(5)) return fail(QSV_EINVAL, "block wider than 5 qubits");
+    if (B.targets.size() > size_t(5)) return fail(QSV_EINVAL, "block wider than 5 qubits");
   }
 
   // stage 3: passes

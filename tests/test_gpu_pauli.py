@@ -1,0 +1,137 @@
+"""GPU parity of multi-qubit Pauli rotations exp(i theta P/2), circuits and
+adjoint gradients that contain them, and transition amplitudes <a|O|b>,
+against the CPU oracle (whose Pauli rotation is pinned to the matrix
+exponential of the Kronecker string and to the named one-qubit rotations).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2011_13524_amd import (Batch, Circuit, Observable, Plan, QsvError, State, adjoint_gradient,
+                                  apply_circuit, apply_fused, apply_pauli_rotation, transition_amplitude)
+from paper_2011_13524_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+AMP = {"c128": 1e-12, "c64": 1e-5}
+RED = {"c128": 1e-11, "c64": 2e-5}
+
+
+def rand_state(rng, n):
+    v = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    return v / np.linalg.norm(v)
+
+
+def rand_string(rng, n, wmax, identities=True):
+    w = int(rng.integers(1, min(n, wmax) + 1))
+    qs = [int(q) for q in rng.choice(n, size=w, replace=False)]
+    ps = [int(p) for p in rng.integers(0 if identities else 1, 4, size=w)]
+    return qs, ps
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_pauli_rotation_vs_oracle(dt):
+    rng = np.random.default_rng(61)
+    for n in (1, 3, 8, 11):
+        for _ in range(8):
+            qs, ps = rand_string(rng, n, 7)
+            th = rng.uniform(-6.3, 6.3)
+            psi = rand_state(rng, n)
+            ref = psi.astype(np.complex64).astype(np.complex128) if dt == "c64" else psi.copy()
+            O.pauli_rotation(ref, qs, ps, th)
+            s = State(n, dt)
+            s.load(psi)
+            apply_pauli_rotation(s, qs, ps, th)
+            assert np.max(np.abs(s.store() - ref)) <= AMP[dt], (n, qs, ps)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_pauli_rotation_special_strings(dt):
+    rng = np.random.default_rng(62)
+    n = 9
+    for qs, ps in (([0, 4, 8], [3, 3, 3]), ([2, 5], [0, 0]), ([1, 3, 6], [2, 2, 2]), ([0, 8], [1, 2])):
+        psi = rand_state(rng, n)
+        ref = psi.astype(np.complex64).astype(np.complex128) if dt == "c64" else psi.copy()
+        O.pauli_rotation(ref, qs, ps, 1.1)
+        s = State(n, dt)
+        s.load(psi)
+        apply_pauli_rotation(s, qs, ps, 1.1)
+        assert np.max(np.abs(s.store() - ref)) <= AMP[dt], (qs, ps)
+
+
+def pauli_circuit(n, layers, seed):
+    rng = np.random.default_rng(seed)
+    gates, slot = [], 0
+    for _ in range(layers):
+        for q in range(n):
+            gates.append({"op": "ry", "q": [q], "slot": slot})
+            slot += 1
+        for _ in range(3):
+            qs, ps = rand_string(rng, n, 4, identities=False)
+            gates.append({"op": "pauli_rot", "q": qs, "paulis": ps, "slot": slot})
+            slot += 1
+        qs, ps = rand_string(rng, n, 3)
+        gates.append({"op": "pauli_rot", "q": qs, "paulis": ps, "angle": float(rng.uniform(0, 6))})
+        gates.append({"op": "cnot", "q": [0, n - 1]})
+    return gates, slot
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_circuits_with_pauli_rotations(dt):
+    n = 10
+    gates, npar = pauli_circuit(n, 3, 63)
+    theta = W.uniform_angles(npar, (6, 3))
+    ref = O.run_circuit(n, gates, theta)
+    c = Circuit.from_records(n, gates)
+    s = State(n, dt)
+    apply_circuit(s, c, theta)
+    assert np.max(np.abs(s.store() - ref)) <= AMP[dt]
+    for kw in (dict(max_k=2), dict(max_k=4, tile_qubits=7, low_qubits=2), dict(max_k=5)):
+        s = State(n, dt)
+        apply_fused(s, Plan(c, dt, **kw), theta)
+        assert np.max(np.abs(s.store() - ref)) <= AMP[dt], kw
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("fused", [False, True])
+def test_adjoint_with_pauli_rotations_vs_shift_rule(dt, fused):
+    n = 7
+    gates, npar = pauli_circuit(n, 2, 64)
+    theta = W.uniform_angles(npar, (6, 4))
+    obs = W.random_pauli_observable(n, 15, (1, 4), seed_key=(6, 5)) + [(0.2, [])]
+    c = Circuit.from_records(n, gates)
+    plan = Plan(c, dt, max_k=4, tile_qubits=6, low_qubits=1) if fused else None
+    psi, lam = State(n, dt), State(n, dt)
+    e, g = adjoint_gradient(c, theta, Observable(n, obs), psi, lam, plan)
+    scale = sum(abs(cf) for cf, _ in obs)
+    assert abs(e - O.energy(n, gates, theta, obs)) <= RED[dt] * scale
+    g_ref = O.param_shift_grad(n, gates, theta, obs)
+    assert np.max(np.abs(g - g_ref)) <= RED[dt] * scale, np.max(np.abs(g - g_ref))
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_transition_amplitude_vs_oracle(dt):
+    rng = np.random.default_rng(65)
+    n = 9
+    obs = W.random_pauli_observable(n, 12, (1, 5), seed_key=(6, 6)) + [(0.4, [])]
+    a, b = rand_state(rng, n), rand_state(rng, n)
+    sa, sb = State(n, dt), State(n, dt)
+    sa.load(a)
+    sb.load(b)
+    if dt == "c64":
+        a, b = (v.astype(np.complex64).astype(np.complex128) for v in (a, b))
+    o = Observable(n, obs)
+    scale = sum(abs(cf) for cf, _ in obs)
+    got = transition_amplitude(sa, o, sb)
+    assert abs(got - O.transition_amplitude(a, b, obs)) <= RED[dt] * scale
+    # <a|O|a> is the expectation
+    assert abs(transition_amplitude(sa, o, sa) - O.expectation_complex(a, obs)) <= RED[dt] * scale
+
+
+def test_batch_rejects_pauli_rotations():
+    n = 4
+    gates = [{"op": "pauli_rot", "q": [0, 1], "paulis": [1, 1], "slot": 0}]
+    b = Batch()
+    b.add(Circuit.from_records(n, gates), Observable(n, [(1.0, [(0, 3)])]), [0.3])
+    with pytest.raises(QsvError):
+        b.run("c64")
