@@ -27,6 +27,8 @@ Extra legs (same JSON line):
                 parameters), one gradient component checked by the shift rule
   autotune_30q  the headline circuit's plan picked by the autotuner vs the
                 default plan
+  pauli_30q     multi-qubit Pauli rotations and transition amplitudes at 30
+                qubits (GB/s of the state sweeps)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode fused|unfused]
                        [--quick] [--no-cpu] [--leg NAME]
@@ -65,7 +67,7 @@ def parse():
     ap.add_argument("--fd-params", type=int, default=6)
     ap.add_argument("--batch-items", type=int, default=512)
     ap.add_argument("--leg", choices=["adjoint_24q", "batch_vqe", "random_26q", "adjoint_32q",
-                                      "autotune_30q"],
+                                      "autotune_30q", "pauli_30q"],
                     help="run only this extra leg and print its JSON (for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also copy the state once (a device copy of known size, used to "
@@ -286,6 +288,40 @@ def random_leg(Q, W):
     return out
 
 
+def pauli_leg(Q, W, n=30):
+    """Multi-qubit Pauli rotations and transition amplitudes at 30 qubits (complex64)."""
+    rng = np.random.default_rng(91)
+    s = Q.State(n, "c64")
+    s.set_basis(0)
+    N, S = 1 << n, 8
+    out = {"workload": f"{n}-qubit complex64: exp(i t P/2) for random weight-4 strings (with X/Y) "
+                       "and a weight-4 Z string; <a|O|b> for 8 random weight-4 strings"}
+    rows = []
+    for kind in ("xy", "xy", "z"):
+        qs = [int(q) for q in rng.choice(n, size=4, replace=False)]
+        ps = [int(p) for p in (rng.integers(1, 4, size=4) if kind == "xy" else [3] * 4)]
+        if kind == "xy" and all(p == 3 for p in ps):
+            ps[0] = 1
+        Q.apply_pauli_rotation(s, qs, ps, 0.3)
+        sync(Q, s)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            Q.apply_pauli_rotation(s, qs, ps, 0.3)
+        sync(Q, s)
+        t = (time.perf_counter() - t0) / 3
+        rows.append({"qubits": qs, "paulis": ps, "ms": t * 1e3, "gbps": 2 * N * S / t / 1e9})
+    out["rotations"] = rows
+    other = Q.State(n, "c64")
+    other.set_basis(3)
+    obs = Q.Observable(n, W.random_pauli_observable(n, 8, 4, seed_key=(9, 1)))
+    Q.transition_amplitude(s, obs, other)
+    t0 = time.perf_counter()
+    Q.transition_amplitude(s, obs, other)
+    t = time.perf_counter() - t0
+    out["transition"] = {"terms": 8, "ms": t * 1e3, "gbps": 8 * 2 * N * S / t / 1e9}
+    return out
+
+
 def autotune_leg(Q, W, n=30):
     """The headline circuit's plan picked by the autotuner vs the default plan."""
     gates = W.layered_rx_rz_cnot(n, 10, seed_key=(2,))
@@ -318,7 +354,7 @@ def main():
         legs = {"adjoint_24q": lambda: adjoint_leg(Q, W, args.fd_params),
                 "batch_vqe": lambda: batch_leg(Q, W, args.batch_items),
                 "random_26q": lambda: random_leg(Q, W), "adjoint_32q": lambda: adjoint32_leg(Q, W),
-                "autotune_30q": lambda: autotune_leg(Q, W)}
+                "autotune_30q": lambda: autotune_leg(Q, W), "pauli_30q": lambda: pauli_leg(Q, W)}
         print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
         return
 
@@ -422,6 +458,7 @@ def main():
         out["random_26q"] = random_leg(Q, W)
         out["adjoint_32q"] = adjoint32_leg(Q, W)
         out["autotune_30q"] = autotune_leg(Q, W)
+        out["pauli_30q"] = pauli_leg(Q, W)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, gates, args.cpu_seconds)
     print(json.dumps(out), flush=True)

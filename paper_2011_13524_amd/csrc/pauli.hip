@@ -34,6 +34,40 @@ __device__ __forceinline__ cx<R> pr_sgn(bool neg, cx<R> v) {
   return neg ? cx<R>{-v.re, -v.im} : v;
 }
 
+// complex64 with qubit 0 outside F: amplitudes x, x + 1 (x even) pair with
+// x ^ F, (x ^ F) + 1, so each side of two pairs is one 16-byte vector; count
+// = N / 4 (F != 0) or N / 2 (F = 0) vector steps.
+__global__ void __launch_bounds__(kPauliThreads)
+    k_pauli_rot_v2(float* __restrict__ psi, uint64_t count, uint64_t flip, uint64_t z, int hb, float c,
+                   cx<float> g) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) {
+    cx<float> a[2], b[2];
+    if (flip == 0) {
+      const uint64_t x = 2 * i;
+      AmpIO<float, 2>::load(psi, x, a);
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const cx<float> f = pr_sgn(pr_odd(x + k, z), g);
+        a[k] = cx<float>{c + f.re, f.im} * a[k];
+      }
+      AmpIO<float, 2>::store(psi, x, a);
+      continue;
+    }
+    const uint64_t x = pr_ins0(2 * i, hb), y = x ^ flip;
+    AmpIO<float, 2>::load(psi, x, a);
+    AmpIO<float, 2>::load(psi, y, b);
+    cx<float> na[2], nb[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      na[k] = cfma(pr_sgn(pr_odd(y + k, z), g), b[k], cx<float>{c * a[k].re, c * a[k].im});
+      nb[k] = cfma(pr_sgn(pr_odd(x + k, z), g), a[k], cx<float>{c * b[k].re, c * b[k].im});
+    }
+    AmpIO<float, 2>::store(psi, x, na);
+    AmpIO<float, 2>::store(psi, y, nb);
+  }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kPauliThreads)
     k_pauli_rot(R* __restrict__ psi, uint64_t count, uint64_t flip, uint64_t z, int hb, R c, cx<R> g) {
@@ -170,8 +204,15 @@ cd ipow(int k) {
   }
 }
 
+// reductions: a bounded number of per-block partials
 int pr_blocks(uint64_t work) {
   return int(std::max<uint64_t>(1, std::min<uint64_t>((work + kPauliThreads - 1) / kPauliThreads, kPauliBlocks)));
+}
+
+// element-wise sweeps: one step per thread (a one-shot grid streams faster
+// than a few thousand grid-striding workgroups), at most 2^22 workgroups
+int pr_grid(uint64_t work) {
+  return int(std::max<uint64_t>(1, std::min<uint64_t>((work + kPauliThreads - 1) / kPauliThreads, uint64_t(1) << 22)));
 }
 
 template <typename R>
@@ -181,7 +222,17 @@ int pauli_rotation_t(qsv_state* s, const PauliMasks& m, double t) {
   const double c = std::cos(0.5 * t), sn = std::sin(0.5 * t);
   const cd g = cmul(cd{0, sn}, ipow(m.ny));
   ProfScope ps("pair", 2.0 * sizeof(cx<R>) * double(N), s->stream);
-  hipLaunchKernelGGL((k_pauli_rot<R>), dim3(pr_blocks(count)), dim3(kPauliThreads), 0, s->stream,
+  if constexpr (sizeof(R) == 4) {
+    if (!(m.flip & 1) && s->n >= 2) {  // 16-byte vectors: qubit 0 is not flipped
+      const uint64_t vcount = count / 2;
+      hipLaunchKernelGGL(k_pauli_rot_v2, dim3(pr_grid(vcount)), dim3(kPauliThreads), 0, s->stream,
+                         static_cast<float*>(s->ptr), vcount, m.flip, m.z, m.hb, float(c),
+                         cx<float>{float(g.re), float(g.im)});
+      QSV_HIP_CHECK(hipGetLastError());
+      return QSV_OK;
+    }
+  }
+  hipLaunchKernelGGL((k_pauli_rot<R>), dim3(pr_grid(count)), dim3(kPauliThreads), 0, s->stream,
                      static_cast<R*>(s->ptr), count, m.flip, m.z, m.hb, R(c), cx<R>{R(g.re), R(g.im)});
   QSV_HIP_CHECK(hipGetLastError());
   return QSV_OK;
