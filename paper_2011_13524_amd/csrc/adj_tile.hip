@@ -363,9 +363,8 @@ __global__ void __launch_bounds__(1 << TB)
   // one dynamic LDS block: the tile (first, at LDS address 0, as the re-map
   // addressing requires) then the gradient slots [row][wave]
   extern __shared__ __align__(16) char smem[];
-  cx<R>* t = reinterpret_cast<cx<R>*>(smem);
   const TilePassDev& P = passes[pass_idx];
-  const int L = P.L, b = P.b;
+  const int L = P.L;
   double(*slot)[NW] = reinterpret_cast<double(*)[NW]>(smem + (size_t(1) << L) * sizeof(cx<R>));
   const uint32_t tau = threadIdx.x;
   const int wave = int(tau >> 6);

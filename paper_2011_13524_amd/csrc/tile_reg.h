@@ -420,9 +420,8 @@ __global__ void __launch_bounds__(1 << TB)
   constexpr int SB = sizeof(R) == 4 ? 5 : 4;
   const Swz<SB> sw;
   extern __shared__ __align__(16) char smem[];
-  cx<R>* t = reinterpret_cast<cx<R>*>(smem);
   const TilePassDev& P = passes[pass_idx];
-  const int L = P.L, b = P.b;
+  const int L = P.L;
   const uint64_t g = blockIdx.x;
   uint64_t base = 0;
   for (int r = 0; r < P.nrun; ++r) base |= ((g >> P.rsrc[r]) & ((uint64_t(1) << P.rlen[r]) - 1)) << P.rdst[r];
