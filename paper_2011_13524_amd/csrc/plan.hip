@@ -277,14 +277,21 @@ static int build_plan(qsv_plan* p) {
   while (!rem.empty()) {
     qsv_plan::Pass P;
     uint64_t local = low;
-    uint64_t blocked = 0;
+    // qubits of the blocks deferred so far, and of the non-diagonal ones: a
+    // block may run ahead of deferred blocks it commutes with -- those on
+    // other qubits, and for a diagonal block also diagonal ones on its qubits
+    uint64_t blocked = 0, blocked_dense = 0;
     std::vector<int> deferred;
+    auto defer = [&](int bi) {
+      deferred.push_back(bi);
+      blocked |= bq[bi];
+      if (!blocks[bi].diagonal) blocked_dense |= bq[bi];
+    };
     for (int bi : rem) {
       const Block& B = blocks[bi];
       const uint64_t all = bq[bi];
-      if (all & blocked) {
-        deferred.push_back(bi);
-        blocked |= all;
+      if (all & (B.diagonal ? blocked_dense : blocked)) {
+        defer(bi);
         continue;
       }
       const uint64_t dense = B.diagonal ? 0 : qmask(B.targets);
@@ -293,8 +300,7 @@ static int build_plan(qsv_plan* p) {
         local |= need;
         P.blocks.push_back(bi);
       } else {
-        deferred.push_back(bi);
-        blocked |= all;
+        defer(bi);
       }
     }
     if (P.blocks.empty()) return fail(QSV_EINVAL, "planner made no progress (tile too small)");

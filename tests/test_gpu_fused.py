@@ -192,3 +192,25 @@ def test_autotune_rejects_mismatched_state():
     c = Circuit.from_records(8, [{"op": "h", "q": [0]}])
     with pytest.raises(QsvError):
         Plan.autotune(c, State(9, "c64"))
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_commuting_diagonal_blocks_run_ahead(dt):
+    # QAOA-like layers (two-qubit diagonal phases on a random graph, then RX
+    # on every qubit) with small tiles: diagonal blocks may pass deferred
+    # diagonal blocks on shared qubits; the result is the circuit's
+    rng = np.random.default_rng(17)
+    n = 12
+    edges = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.uniform() < 0.3]
+    gates = []
+    for _ in range(3):
+        for i, j in edges:
+            ph = float(rng.uniform(0, 3))
+            gates.append({"op": "dense", "q": [i, j], "mat": np.diag(np.exp(1j * ph * np.array([1, -1, -1, 1])))})
+        for q in range(n):
+            gates.append({"op": "rx", "q": [q], "angle": float(rng.uniform(0, 3))})
+    ref = O.run_circuit(n, gates)
+    for kw in (dict(max_k=2, tile_qubits=6, low_qubits=2), dict(max_k=1, tile_qubits=8, low_qubits=3)):
+        got, info = fused_state(n, gates, dt, **kw)
+        assert info["passes"] > 1
+        assert np.max(np.abs(got - ref)) <= AMP_TOL[dt], (kw, info)
