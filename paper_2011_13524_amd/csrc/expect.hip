@@ -406,7 +406,33 @@ __global__ void __launch_bounds__(kExpThreads) k_zero_amps(R* __restrict__ a, ui
 // summed per pass in the amplitude precision (that of lambda itself); the
 // first pass writes lambda, later passes add to it.
 constexpr int kObsOut = 8;  // outputs per thread: 2^12 / 512
-template <typename R>
+
+// One single-term group's contribution to this thread's outputs: lambda_y +=
+// c psi_{y ^ F} (REAL) or i c psi_{y ^ F} with c = +-coefficient, the sign of
+// (-1)^|x & z| split into a per-thread bit (pt) and a per-step bit.
+template <typename R, bool REAL, bool FIXED>
+__device__ __forceinline__ void obs_single(const cx<R>* t, uint32_t tid, uint32_t lf, uint32_t zl, uint32_t pt,
+                                           R cm, uint32_t TS, R* ar, R* ai) {
+#pragma unroll
+  for (int k = 0; k < kObsOut; ++k) {
+    const uint32_t y = tid + uint32_t(k) * kExpThreads;
+    if (FIXED || y < TS) {
+      const cx<R> v = t[y ^ lf];
+      const R c = (pt ^ (__popc((uint32_t(k) * kExpThreads) & zl) & 1)) ? -cm : cm;
+      if constexpr (REAL) {
+        ar[k] += c * v.re;
+        ai[k] += c * v.im;
+      } else {
+        ar[k] += -c * v.im;
+        ai[k] += c * v.re;
+      }
+    }
+  }
+}
+
+// FIXED: the tile has exp_tile_bits<R>() qubits and every thread's outputs
+// exist (complex64: 2^12 = 8 x 512).
+template <typename R, bool FIXED>
 __global__ void __launch_bounds__(kExpThreads)
     k_apply_obs_tile(const R* __restrict__ psi, R* __restrict__ lam, const ExpPassDev* __restrict__ passes,
                      int pass_idx, const ExpGroupDev* __restrict__ groups,
@@ -415,7 +441,7 @@ __global__ void __launch_bounds__(kExpThreads)
   __shared__ ExpTermLds et[kExpLdsTerms];
   cx<R>* t = reinterpret_cast<cx<R>*>(smem);
   const ExpPassDev& P = passes[pass_idx];
-  const uint32_t TS = 1u << P.L;
+  const uint32_t TS = FIXED ? (1u << exp_tile_bits<R>()) : (1u << P.L);
   const uint32_t tid = threadIdx.x;
   ExpTileStream<R, kExpThreads> io(P);
   const uint64_t yt = exp_place(P, tid);
@@ -449,18 +475,10 @@ __global__ void __launch_bounds__(kExpThreads)
       if (nt == 1) {
         // alpha i^nY is real or imaginary: lambda += c psi or i c psi
         const uint32_t pt = (__popc((tid ^ lf) & G.zl) & 1);
-        const bool real = G.im == 0.0;
-        const double cm = real ? G.re : G.im;
-#pragma unroll
-        for (int k = 0; k < kObsOut; ++k) {
-          const uint32_t y = tid + uint32_t(k) * kExpThreads;
-          if (y < TS) {
-            const cx<R> v = t[y ^ lf];
-            const R c = R(flip_sign(cm, pt ^ (__popc((uint32_t(k) * kExpThreads) & G.zl) & 1)));
-            ar[k] += real ? c * v.re : -c * v.im;
-            ai[k] += real ? c * v.im : c * v.re;
-          }
-        }
+        if (G.im == 0.0)
+          obs_single<R, true, FIXED>(t, tid, lf, G.zl, pt, R(G.re), TS, ar, ai);
+        else
+          obs_single<R, false, FIXED>(t, tid, lf, G.zl, pt, R(G.im), TS, ar, ai);
       } else {
 #pragma unroll
         for (int k = 0; k < kObsOut; ++k) {
@@ -485,7 +503,7 @@ __global__ void __launch_bounds__(kExpThreads)
     }
 #pragma unroll
     for (int k = 0; k < kObsOut; ++k) {
-      if (tid + uint32_t(k) * kExpThreads >= TS) continue;
+      if (!FIXED && tid + uint32_t(k) * kExpThreads >= TS) continue;
       cx<R> r;
       if (accumulate) {
         const cx<R> old = load1(lam, base | yt | yk[k]);
@@ -705,16 +723,26 @@ int apply_obs_tiled_t(const qsv_state* in, qsv_observable* o, qsv_state* out) {
   if (rc) return rc;
   const uint64_t tiles = dim(in->n - pl->L);
   const size_t lds = (size_t(1) << pl->L) * sizeof(cx<R>);
-  QSV_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_obs_tile<R>),
+  // compile-time output count when every thread has kObsOut outputs
+  const bool fixed = pl->L == exp_tile_bits<R>() && (size_t(1) << pl->L) == size_t(kObsOut) * kExpThreads;
+  QSV_HIP_CHECK(hipFuncSetAttribute(fixed ? reinterpret_cast<const void*>(&k_apply_obs_tile<R, true>)
+                                          : reinterpret_cast<const void*>(&k_apply_obs_tile<R, false>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   char* d = static_cast<char*>(pl->dev);
   for (size_t pi = 0; pi < pl->passes.size(); ++pi) {
     ProfScope ps("apply_obs", double(sizeof(cx<R>)) * double(N) * (pi > 0 ? 3.0 : 2.0), in->stream);
-    hipLaunchKernelGGL((k_apply_obs_tile<R>), dim3(unsigned(std::min<uint64_t>(tiles, kExpGrid))),
-                       dim3(kExpThreads), lds, in->stream, static_cast<const R*>(in->ptr),
-                       static_cast<R*>(out->ptr), reinterpret_cast<const ExpPassDev*>(d), int(pi),
-                       reinterpret_cast<const ExpGroupDev*>(d + pl->off_groups),
-                       reinterpret_cast<const ExpTermDev*>(d + pl->off_terms), pi > 0 ? 1 : 0, tiles);
+    const dim3 grid(unsigned(std::min<uint64_t>(tiles, kExpGrid)));
+    const auto* pd = reinterpret_cast<const ExpPassDev*>(d);
+    const auto* gd = reinterpret_cast<const ExpGroupDev*>(d + pl->off_groups);
+    const auto* td = reinterpret_cast<const ExpTermDev*>(d + pl->off_terms);
+    if (fixed)
+      hipLaunchKernelGGL((k_apply_obs_tile<R, true>), grid, dim3(kExpThreads), lds, in->stream,
+                         static_cast<const R*>(in->ptr), static_cast<R*>(out->ptr), pd, int(pi), gd, td,
+                         pi > 0 ? 1 : 0, tiles);
+    else
+      hipLaunchKernelGGL((k_apply_obs_tile<R, false>), grid, dim3(kExpThreads), lds, in->stream,
+                         static_cast<const R*>(in->ptr), static_cast<R*>(out->ptr), pd, int(pi), gd, td,
+                         pi > 0 ? 1 : 0, tiles);
     QSV_HIP_CHECK(hipGetLastError());
   }
   return QSV_OK;
