@@ -13,6 +13,10 @@ gradients:
                      parametric gate is exp(+i t P / 2) with P^2 = I, so
                      dE/dt = [E(t + pi/2) - E(t - pi/2)] / 2
   fd_grad            central finite differences (cross-check of the above)
+  marginal_probability  probability of a Z-basis outcome on a subset of the
+                     qubits, the others left unmeasured (section 4.2.2)
+  sample             Z-basis samples by inverse CDF over the cumulative
+                     distribution of |psi_x|^2 (section 4.2.2)
 
 Parity status: every function here is pinned by tests/test_oracle_pins.py.
 """
@@ -250,3 +254,40 @@ def fd_grad(n, gates, theta, obs, h=1e-5, slots=None) -> np.ndarray:
         tm[s] -= h
         g[i] = (energy(n, gates, tp, obs) - energy(n, gates, tm, obs)) / (2 * h)
     return g
+
+
+def marginal_probability(psi: np.ndarray, values) -> float:
+    """Sum of |psi_x|^2 over the basis indices x whose bit q equals values[q]
+    for every qubit q with values[q] in {0, 1}; values[q] == 2 leaves qubit q
+    unmeasured (section 4.2.2, the marginal-probability utility: one list
+    entry per qubit, entry q for qubit q, 2 a wild card). Plain definition,
+    FP64, no normalisation."""
+    n = int(psi.size).bit_length() - 1
+    if len(values) != n:
+        raise ValueError("one value per qubit")
+    p = np.abs(np.asarray(psi, dtype=np.complex128)) ** 2
+    x = np.arange(psi.size, dtype=np.uint64)
+    keep = np.ones(psi.size, dtype=bool)
+    for q, v in enumerate(values):
+        if v == 2:
+            continue
+        if v not in (0, 1):
+            raise ValueError("values must be 0, 1 or 2")
+        keep &= ((x >> np.uint64(q)) & np.uint64(1)) == np.uint64(v)
+    return float(p[keep].sum())
+
+
+def sample(psi: np.ndarray, u) -> np.ndarray:
+    """Z-basis samples (section 4.2.2: sampling goes through the cumulative
+    distribution of the outcome probabilities). For each uniform u_i in
+    [0, 1) the sample is the smallest index x with C(x) > u_i * C(N - 1),
+    C(x) = sum_{y <= x} |psi_y|^2 accumulated in order in FP64; the uniforms
+    are inputs, drawn by the caller."""
+    p = np.abs(np.asarray(psi, dtype=np.complex128)) ** 2
+    c = np.cumsum(p)
+    u = np.asarray(u, dtype=np.float64)
+    if np.any(~(u >= 0.0)) or np.any(~(u < 1.0)):
+        raise ValueError("uniforms must lie in [0, 1)")
+    if c[-1] <= 0.0:
+        raise ValueError("zero-norm state")
+    return np.searchsorted(c, u * c[-1], side="right").astype(np.int64)

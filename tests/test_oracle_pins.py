@@ -452,3 +452,80 @@ def test_transition_amplitude_pins():
     full = sum(c * _string_matrix(n, [q for q, _ in t], [p for _, p in t]) for c, t in obs)
     ref = np.vdot(a, full @ b)
     assert abs(O.transition_amplitude(a, b, obs) - ref) <= 1e-12
+
+
+# ------------------------------------------------- marginals and sampling (4.2.2)
+
+def test_marginal_worked_example_wildcard_pattern():
+    # Section 4.2.2 example: values [1, 2, 0] on 3 qubits (entry q for qubit q,
+    # 2 a wild card) is the outcome written |0?1> with qubit 0 rightmost, i.e.
+    # the indices 0b001 and 0b011.
+    p = np.arange(1, 9, dtype=np.float64)
+    p /= p.sum()
+    psi = np.sqrt(p) * np.exp(1j * np.arange(8))
+    assert O.marginal_probability(psi, [1, 2, 0]) == pytest.approx(p[1] + p[3], abs=1e-15)
+    assert O.marginal_probability(psi, [2, 2, 2]) == pytest.approx(1.0, abs=1e-14)
+    for x in range(8):
+        bits = [(x >> q) & 1 for q in range(3)]
+        assert O.marginal_probability(psi, bits) == pytest.approx(p[x], abs=1e-15)
+
+
+def test_marginal_product_state_closed_form():
+    # prod_q (cos a_q |0> + e^{i b_q} sin a_q |1>): the marginal of any pattern
+    # is the product of cos^2 / sin^2 over the measured qubits.
+    rng = np.random.default_rng(11)
+    n = 6
+    a, b = rng.uniform(0, np.pi, n), rng.uniform(0, 2 * np.pi, n)
+    psi = np.ones(1, dtype=np.complex128)
+    for q in range(n):
+        psi = np.kron(np.array([np.cos(a[q]), np.exp(1j * b[q]) * np.sin(a[q])]), psi)
+    for _ in range(20):
+        vals = [int(v) for v in rng.integers(0, 3, n)]
+        want = 1.0
+        for q, v in enumerate(vals):
+            if v != 2:
+                want *= np.cos(a[q]) ** 2 if v == 0 else np.sin(a[q]) ** 2
+        assert O.marginal_probability(psi, vals) == pytest.approx(want, rel=1e-12, abs=1e-15)
+    with pytest.raises(ValueError):
+        O.marginal_probability(psi, [0, 1, 3, 2, 2, 2])
+
+
+def test_sample_inverse_cdf_pins():
+    # probabilities 1/4 on the even indices (exact in binary); the sample is
+    # the first index whose running sum exceeds u, so u on a boundary goes up
+    psi = np.array([0.5, 0, 0.5, 0, 0.5j, 0, -0.5, 0], dtype=np.complex128)
+    u = [0.0, 0.2499, 0.25, 0.5, 0.74, 0.75, 0.9999999]
+    assert [int(v) for v in O.sample(psi, u)] == [0, 0, 2, 4, 4, 6, 6]
+    # a basis state is always sampled as itself; scaling the state changes nothing
+    e = np.zeros(16, dtype=np.complex128)
+    e[11] = 1j
+    assert set(O.sample(e, np.linspace(0, 0.999, 50))) == {11}
+    rng = np.random.default_rng(5)
+    s = rng.normal(size=32) + 1j * rng.normal(size=32)
+    uu = rng.uniform(size=200)
+    assert np.array_equal(O.sample(s, uu), O.sample(3.0 * s, uu))
+    with pytest.raises(ValueError):
+        O.sample(psi, [1.0])
+    with pytest.raises(ValueError):
+        O.sample(np.zeros(4, dtype=np.complex128), [0.5])
+
+
+def test_sample_matches_linear_scan_and_frequencies():
+    rng = np.random.default_rng(9)
+    psi = rng.normal(size=16) + 1j * rng.normal(size=16)
+    psi[[3, 7]] = 0.0
+    p = np.abs(psi) ** 2
+    u = rng.uniform(size=4000)
+    got = O.sample(psi, u)
+    for ui, g in zip(u[:300], got[:300]):
+        acc, pick = 0.0, None
+        for x in range(16):  # brute force: first x whose running sum passes u * total
+            acc += p[x]
+            if acc > ui * p.sum():
+                pick = x
+                break
+        assert g == pick
+    assert not np.isin(got, [3, 7]).any()
+    freq = np.bincount(got, minlength=16) / got.size
+    sigma = np.sqrt(p / p.sum() * (1 - p / p.sum()) / got.size)
+    assert np.all(np.abs(freq - p / p.sum()) <= 5 * sigma + 1e-12)
