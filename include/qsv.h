@@ -142,6 +142,29 @@ int qsv_norm2(const qsv_state* s, double* out);
  * dtype. */
 int qsv_inner(const qsv_state* bra, const qsv_state* ket, double* re, double* im);
 
+/* Marginal probability of a Z-basis outcome (section 4.2.2, the marginal-
+ * probability utility). values: host array of n ints, values[q] for qubit q:
+ * 0 or 1 for a measured qubit, 2 for one left unmeasured. *out = sum of
+ * |psi_x|^2 over the basis indices x whose measured bits equal the values,
+ * visiting only those 2^(n - m) amplitudes (m measured), FP64 accumulation
+ * with per-block partials summed in a fixed order. The state is not
+ * normalised first. Synchronises.
+ * Errors: QSV_EINVAL (null arguments, a value outside {0, 1, 2}). */
+int qsv_marginal_probability(const qsv_state* s, const int* values, double* out);
+
+/* Z-basis sampling (section 4.2.2: sampling through a cumulative distribution
+ * built first, which needs an extra 2^n-long array). u: host array of `count`
+ * uniforms in [0, 1), drawn by the caller; out: host array of `count` basis
+ * indices, out[i] = the smallest x with C(x) > u[i] * C(2^n - 1), C the
+ * inclusive cumulative sum of |psi|^2 in FP64 (unnormalised states are
+ * sampled from |psi|^2 / <psi|psi>). An index of probability zero is never
+ * returned. The call allocates a temporary FP64 table of 2^n entries
+ * (8 bytes per amplitude) plus 2^(n-12) for the chunk totals, frees it before
+ * returning, and synchronises. count == 0 only builds the table.
+ * Errors: QSV_EINVAL (null arguments, count < 0, a state of zero norm),
+ * QSV_ERANGE (a uniform outside [0, 1) or NaN, count > 2^31), QSV_ENOMEM. */
+int qsv_sample(const qsv_state* s, const double* u, int64_t count, int64_t* out);
+
 /* ---------------------------------------------------------------- circuits */
 
 /* A circuit is an ordered host-side list of basic gates (section 4.4,

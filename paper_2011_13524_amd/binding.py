@@ -59,6 +59,8 @@ _SIGS = {
     "qsv_circuit_add_pauli_rotation": (_c.c_int, [_vp, _ip, _ip, _c.c_int, _c.c_int, _c.c_double]),
     "qsv_apply_pauli_rotation": (_c.c_int, [_vp, _ip, _ip, _c.c_int, _c.c_double]),
     "qsv_transition_amplitude": (_c.c_int, [_vp, _vp, _vp, _dp, _dp]),
+    "qsv_marginal_probability": (_c.c_int, [_vp, _ip, _dp]),
+    "qsv_sample": (_c.c_int, [_vp, _dp, _c.c_int64, _c.POINTER(_c.c_int64)]),
     "qsv_circuit_info": (_c.c_int, [_vp, _ip, _ip, _ip]),
     "qsv_apply_circuit": (_c.c_int, [_vp, _vp, _dp]),
     "qsv_plan_fused": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.POINTER(_vp)]),
@@ -214,6 +216,24 @@ class State:
         out = _c.c_double()
         check(lib().qsv_norm2(self.h, _c.byref(out)))
         return out.value
+
+    def marginal_probability(self, values) -> float:
+        """Probability of the outcome `values` (one entry per qubit: 0, 1, or 2
+        for unmeasured) (qsv_marginal_probability)."""
+        if len(values) != self.n:
+            raise ValueError("one value per qubit")
+        v = (_c.c_int * len(values))(*[int(x) for x in values])
+        out = _c.c_double()
+        check(lib().qsv_marginal_probability(self.h, v, _c.byref(out)))
+        return out.value
+
+    def sample(self, u) -> np.ndarray:
+        """Basis indices for the uniforms `u` in [0, 1) (qsv_sample)."""
+        u = np.ascontiguousarray(np.asarray(u, dtype=np.float64).ravel())
+        out = np.empty(u.size, dtype=np.int64)
+        check(lib().qsv_sample(self.h, u.ctypes.data_as(_dp), int(u.size),
+                               out.ctypes.data_as(_c.POINTER(_c.c_int64))))
+        return out
 
     def inner(self, ket: "State") -> complex:
         re, im = _c.c_double(), _c.c_double()

@@ -127,6 +127,30 @@ __global__ void __launch_bounds__(kRedThreads)
   if (threadIdx.x == 0) out[0] = r;
 }
 
+// Marginal probability (section 4.2.2): sum of |psi_x|^2 over the 2^(n - m)
+// indices x whose m measured bits are fixed. Index j of the free bits becomes
+// x by inserting a zero at each measured position (ascending), then OR-ing the
+// requested values; partial[blockIdx.x] = this workgroup's FP64 share.
+template <typename R>
+__global__ void __launch_bounds__(kRedThreads)
+    k_marginal(const R* __restrict__ psi, uint64_t work, InsertPos ins, uint64_t vals,
+               double* __restrict__ partial) {
+  __shared__ double sh[kRedThreads / 64];
+  double acc = 0.0;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t j = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < work; j += stride) {
+    uint64_t x = j;
+    for (int k = 0; k < ins.m; ++k) {
+      const int q = ins.pos[k];
+      x = ((x >> q) << (q + 1)) | (x & ((uint64_t(1) << q) - 1));
+    }
+    const cx<double> a = ld(psi, x | vals);
+    acc += a.re * a.re + a.im * a.im;
+  }
+  const double r = block_reduce_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
 namespace {
 
 int red_blocks(uint64_t work) {
@@ -220,6 +244,26 @@ int inner_t(const qsv_state* bra, const qsv_state* ket, qsv_state* scratch_owner
   return QSV_OK;
 }
 
+template <typename R>
+int marginal_t(qsv_state* s, const InsertPos& ins, uint64_t vals, double* out) {
+  const uint64_t work = dim(s->n - ins.m);
+  const int nb = red_blocks(work);
+  int rc = ensure_reduce_scratch(s, size_t(nb + 1));
+  if (rc) return rc;
+  double* partial = s->red;
+  hipLaunchKernelGGL((k_marginal<R>), dim3(nb), dim3(kRedThreads), 0, s->stream,
+                     static_cast<const R*>(s->ptr), work, ins, vals, partial);
+  QSV_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kRedThreads), 0, s->stream, partial, nb, 1,
+                     partial + nb);
+  QSV_HIP_CHECK(hipGetLastError());
+  QSV_HIP_CHECK(hipMemcpyAsync(s->red_host, partial + nb, sizeof(double), hipMemcpyDeviceToHost,
+                               s->stream));
+  QSV_HIP_CHECK(hipStreamSynchronize(s->stream));
+  *out = s->red_host[0];
+  return QSV_OK;
+}
+
 }  // namespace
 
 int expectation_impl(qsv_state* s, const qsv_observable* o, double* out) {
@@ -242,6 +286,24 @@ int qsv_norm2(const qsv_state* s_in, double* out) {
   id.n = s->n;
   id.terms.push_back({1.0, 0, 0, 0});
   return expectation_impl(s, &id, out);
+}
+
+int qsv_marginal_probability(const qsv_state* s_in, const int* values, double* out) {
+  clear_error();
+  int rc = check_state(s_in);
+  if (rc) return rc;
+  if (!values || !out) return fail(QSV_EINVAL, "null argument");
+  InsertPos ins;
+  uint64_t vals = 0;
+  for (int q = 0; q < s_in->n; ++q) {
+    if (values[q] == 2) continue;
+    if (values[q] != 0 && values[q] != 1) return fail(QSV_EINVAL, "values must be 0, 1 or 2");
+    ins.pos[ins.m++] = q;  // ascending
+    vals |= uint64_t(values[q]) << q;
+  }
+  qsv_state* s = const_cast<qsv_state*>(s_in);  // scratch only; amplitudes untouched
+  return s->dtype == QSV_C64 ? marginal_t<float>(s, ins, vals, out)
+                             : marginal_t<double>(s, ins, vals, out);
 }
 
 int qsv_inner(const qsv_state* bra, const qsv_state* ket, double* re, double* im) {

@@ -113,6 +113,11 @@ def test_validation_before_any_launch_on_wrapped_memory():
     o = Q.Observable(5)
     out = ctypes.c_double()
     assert L.qsv_expectation(s.h, o.h, ctypes.byref(out)) == ERANGE
+    assert _code(s.marginal_probability, [0, 1, 3, 2]) == EINVAL
+    assert _code(s.sample, [0.5, 1.0]) == ERANGE
+    assert _code(s.sample, [float("nan")]) == ERANGE
+    assert _code(s.sample, [-0.25]) == ERANGE
+    assert L.qsv_sample(s.h, None, -1, None) == EINVAL
     np.testing.assert_array_equal(buf, 0.0)
 
 
