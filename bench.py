@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--fd-params", type=int, default=6)
     ap.add_argument("--batch-items", type=int, default=512)
     ap.add_argument("--leg", choices=["adjoint_24q", "batch_vqe", "random_26q", "adjoint_32q",
-                                      "autotune_30q", "pauli_30q"],
+                                      "autotune_30q", "pauli_30q", "sample_30q"],
                     help="run only this extra leg and print its JSON (for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also copy the state once (a device copy of known size, used to "
@@ -322,6 +322,38 @@ def pauli_leg(Q, W, n=30):
     return out
 
 
+def sample_leg(Q, W, n=30, count=1 << 20):
+    """Marginal probabilities and Z-basis sampling at 30 qubits (complex64)."""
+    rng = np.random.default_rng(93)
+    s = Q.State(n, "c64")
+    s.set_basis(0)
+    for q in range(n):
+        s.apply_named("ry", [q], float(rng.uniform(0.2, 2.9)))
+        s.apply_named("rz", [q], float(rng.uniform(-3.0, 3.0)))
+    N, S = 1 << n, 8
+    out = {"workload": f"{n}-qubit complex64 product state from RY/RZ on every qubit; marginals "
+                       f"with 0 and 3 measured qubits; {count} samples from seeded uniforms"}
+    for m in (0, 3):
+        vals = [2] * n
+        for q in range(m):
+            vals[q] = q & 1
+        s.marginal_probability(vals)
+        t0 = time.perf_counter()
+        prob = s.marginal_probability(vals)
+        t = time.perf_counter() - t0
+        out[f"marginal_{m}"] = {"prob": prob, "ms": t * 1e3, "gbps": (N >> m) * S / t / 1e9}
+    u = rng.uniform(size=count)
+    s.sample(u[:16])
+    t0 = time.perf_counter()
+    got = s.sample(u)
+    t = time.perf_counter() - t0
+    # the table build reads every amplitude once and writes one FP64 per amplitude
+    out["sample"] = {"count": count, "ms": t * 1e3, "samples_per_s": count / t,
+                     "table_gbps_lower_bound": N * (S + 8) / t / 1e9,
+                     "distinct": int(np.unique(got).size)}
+    return out
+
+
 def autotune_leg(Q, W, n=30):
     """The headline circuit's plan picked by the autotuner vs the default plan."""
     gates = W.layered_rx_rz_cnot(n, 10, seed_key=(2,))
@@ -354,7 +386,8 @@ def main():
         legs = {"adjoint_24q": lambda: adjoint_leg(Q, W, args.fd_params),
                 "batch_vqe": lambda: batch_leg(Q, W, args.batch_items),
                 "random_26q": lambda: random_leg(Q, W), "adjoint_32q": lambda: adjoint32_leg(Q, W),
-                "autotune_30q": lambda: autotune_leg(Q, W), "pauli_30q": lambda: pauli_leg(Q, W)}
+                "autotune_30q": lambda: autotune_leg(Q, W), "pauli_30q": lambda: pauli_leg(Q, W),
+                "sample_30q": lambda: sample_leg(Q, W)}
         print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
         return
 
@@ -459,6 +492,7 @@ def main():
         out["adjoint_32q"] = adjoint32_leg(Q, W)
         out["autotune_30q"] = autotune_leg(Q, W)
         out["pauli_30q"] = pauli_leg(Q, W)
+        out["sample_30q"] = sample_leg(Q, W)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, gates, args.cpu_seconds)
     print(json.dumps(out), flush=True)
