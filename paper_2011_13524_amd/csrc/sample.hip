@@ -50,49 +50,60 @@ __device__ __forceinline__ double scan_weight(const R* psi, uint64_t i) {
 // kScanChunk entries (the last chunk may be short); cdf receives the chunk's
 // local inclusive scan and sums[blockIdx.x] its total (the last scan value).
 // cdf may alias in: the chunk is read whole before it is written.
+//
+// The chunk passes through LDS so that global reads and writes stay
+// coalesced; entry j sits at j + j / 16 (one pad slot per thread's run of 16)
+// so that the per-thread runs fall in different banks.
+__device__ __forceinline__ uint32_t scan_slot(uint32_t j) { return j + (j >> 4); }
+
 template <typename R, bool AMP>
 __global__ void __launch_bounds__(kScanThreads)
     k_scan_chunks(const R* in, uint64_t count, double* cdf, double* __restrict__ sums) {
-  __shared__ double p[kScanChunk];
+  __shared__ double p[kScanChunk + kScanChunk / kScanPer];
   __shared__ double base[kScanThreads];
   const uint64_t first = uint64_t(blockIdx.x) << kScanChunkBits;
   const uint32_t len = uint32_t(min<uint64_t>(kScanChunk, count - first));
   const uint32_t tid = threadIdx.x;
   for (uint32_t j = tid; j < len; j += kScanThreads) {
     if constexpr (AMP)
-      p[j] = scan_weight(in, first + j);
+      p[scan_slot(j)] = scan_weight(in, first + j);
     else
-      p[j] = double(in[first + j]);
+      p[scan_slot(j)] = double(in[first + j]);
   }
   __syncthreads();
+  // thread t's entries 16t .. 16t + 15, scanned in registers
   const uint32_t j0 = tid * kScanPer;
-  double run = 0.0;
+  double run[kScanPer];
+  double acc = 0.0;
+#pragma unroll
   for (uint32_t k = 0; k < kScanPer; ++k) {
-    const uint32_t j = j0 + k;
-    if (j < len) {
-      run += p[j];
-      p[j] = run;
-    }
+    if (j0 + k < len) acc += p[scan_slot(j0 + k)];
+    run[k] = acc;
   }
-  base[tid] = run;  // thread total T_t (0 past the end)
+  base[tid] = acc;  // thread total T_t (0 past the end)
   __syncthreads();
+  // B_0 = 0, B_{t+1} = B_t + T_t, in order; 16 loads in flight per step
   if (tid == 0) {
-    double acc = 0.0;
-    for (uint32_t t = 0; t < kScanThreads; ++t) {
-      const double T = base[t];
-      base[t] = acc;
-      acc += T;
+    double b = 0.0;
+    for (uint32_t t0 = 0; t0 < kScanThreads; t0 += 16) {
+      double T[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) T[k] = base[t0 + k];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        base[t0 + k] = b;
+        b += T[k];
+      }
     }
   }
   __syncthreads();
   const double b = base[tid];
-  for (uint32_t k = 0; k < kScanPer; ++k) {
-    const uint32_t j = j0 + k;
-    if (j < len) p[j] = b + p[j];
-  }
+#pragma unroll
+  for (uint32_t k = 0; k < kScanPer; ++k)
+    if (j0 + k < len) p[scan_slot(j0 + k)] = b + run[k];
   __syncthreads();
-  for (uint32_t j = tid; j < len; j += kScanThreads) cdf[first + j] = p[j];
-  if (tid == 0) sums[blockIdx.x] = p[len - 1];
+  for (uint32_t j = tid; j < len; j += kScanThreads) cdf[first + j] = p[scan_slot(j)];
+  if (tid == 0) sums[blockIdx.x] = p[scan_slot(len - 1)];
 }
 
 // Smallest j in [lo, hi) with c[j] > r, given c[hi - 1] > r and c non-decreasing.
