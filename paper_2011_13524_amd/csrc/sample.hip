@@ -64,11 +64,26 @@ __global__ void __launch_bounds__(kScanThreads)
   const uint64_t first = uint64_t(blockIdx.x) << kScanChunkBits;
   const uint32_t len = uint32_t(min<uint64_t>(kScanChunk, count - first));
   const uint32_t tid = threadIdx.x;
-  for (uint32_t j = tid; j < len; j += kScanThreads) {
-    if constexpr (AMP)
-      p[scan_slot(j)] = scan_weight(in, first + j);
-    else
-      p[scan_slot(j)] = double(in[first + j]);
+  // a full chunk of amplitudes moves as 16-byte vectors, two entries per lane
+  const bool full = AMP && len == kScanChunk;
+  if (full) {
+    if constexpr (AMP) {
+#pragma unroll
+      for (uint32_t i = 0; i < kScanChunk / (2 * kScanThreads); ++i) {
+        const uint32_t j = 2 * (tid + i * kScanThreads);
+        cx<R> v[2];
+        AmpIO<R, 2>::load(in, first + j, v);
+        p[scan_slot(j)] = double(v[0].re) * double(v[0].re) + double(v[0].im) * double(v[0].im);
+        p[scan_slot(j + 1)] = double(v[1].re) * double(v[1].re) + double(v[1].im) * double(v[1].im);
+      }
+    }
+  } else {
+    for (uint32_t j = tid; j < len; j += kScanThreads) {
+      if constexpr (AMP)
+        p[scan_slot(j)] = scan_weight(in, first + j);
+      else
+        p[scan_slot(j)] = double(in[first + j]);
+    }
   }
   __syncthreads();
   // thread t's entries 16t .. 16t + 15, scanned in registers
@@ -102,7 +117,15 @@ __global__ void __launch_bounds__(kScanThreads)
   for (uint32_t k = 0; k < kScanPer; ++k)
     if (j0 + k < len) p[scan_slot(j0 + k)] = b + run[k];
   __syncthreads();
-  for (uint32_t j = tid; j < len; j += kScanThreads) cdf[first + j] = p[scan_slot(j)];
+  if (full) {
+#pragma unroll
+    for (uint32_t i = 0; i < kScanChunk / (2 * kScanThreads); ++i) {
+      const uint32_t j = 2 * (tid + i * kScanThreads);  // j and j + 1 share a run: adjacent slots
+      nt_store(f64x2{p[scan_slot(j)], p[scan_slot(j + 1)]}, reinterpret_cast<f64x2*>(cdf + first + j));
+    }
+  } else {
+    for (uint32_t j = tid; j < len; j += kScanThreads) cdf[first + j] = p[scan_slot(j)];
+  }
   if (tid == 0) sums[blockIdx.x] = p[scan_slot(len - 1)];
 }
 
