@@ -152,3 +152,30 @@ def test_sample_frequencies_match_probabilities():
     sigma = np.sqrt(p * (1 - p) / got.size)
     assert np.all(np.abs(freq - p) <= 5 * sigma + 1e-12)
     assert np.all(freq[p == 0] == 0)
+
+
+def test_sample_and_marginals_28_qubit_product_state():
+    # full-size check through properties: RY(t_q) on every qubit of |0...0>
+    # gives P(bit q = 1) = sin^2(t_q / 2) independently per qubit
+    rng = np.random.default_rng(77)
+    n = 28
+    t = rng.uniform(0.3, 2.8, n)
+    s = State(n, "c64")
+    s.set_basis(0)
+    for q in range(n):
+        s.apply_named("ry", [q], float(t[q]))
+    p1 = np.sin(t / 2) ** 2
+    for q in (0, 5, 13, 27):
+        vals = [2] * n
+        vals[q] = 1
+        assert s.marginal_probability(vals) == pytest.approx(p1[q], rel=1e-5)
+    vals = [2] * n
+    vals[1], vals[20] = 0, 1
+    assert s.marginal_probability(vals) == pytest.approx((1 - p1[1]) * p1[20], rel=1e-5)
+    m = 1 << 18
+    got = s.sample(rng.uniform(size=m))
+    assert got.min() >= 0 and got.max() < (1 << n)
+    bits = (got[:, None] >> np.arange(n)) & 1
+    freq = bits.mean(axis=0)
+    sigma = np.sqrt(p1 * (1 - p1) / m)
+    assert np.all(np.abs(freq - p1) <= 5 * sigma)
