@@ -185,7 +185,7 @@ int qsv_circuit_add_named(qsv_circuit* c, int kind, const int* qubits, int nq, d
  * circuit's parameter count becomes at least param_slot + 1. */
 int qsv_circuit_add_rotation(qsv_circuit* c, int pauli_id, int qubit, int param_slot);
 
-/* Append a multi-qubit Pauli rotation exp(+i theta P / 2) (section 4.3.3,
+/* Append a multi-qubit Pauli rotation exp(+i theta P / 2) (section 4.3.2,
  * Pauli rotation; the factor 1/2 as in Table 1's one-qubit rotations, so a
  * one-qubit string is RX/RY/RZ), P = prod_j sigma_{pauli_ids[j]} on qubits[j]
  * (ids 0..3 = I, X, Y, Z; distinct qubits, 1 <= w <= n). param_slot >= 0:
@@ -201,7 +201,7 @@ int qsv_circuit_add_pauli_rotation(qsv_circuit* c, const int* qubits, const int*
 int qsv_circuit_info(const qsv_circuit* c, int* n, int* gates, int* nparams);
 
 /* psi <- exp(+i theta P / 2) psi for the Pauli string P = prod_j
- * sigma_{pauli_ids[j]} on qubits[j] (section 4.3.3; ids 0..3, distinct qubits,
+ * sigma_{pauli_ids[j]} on qubits[j] (section 4.3.2; ids 0..3, distinct qubits,
  * 0 <= w <= n): one sweep over the amplitude pairs (x, x ^ F), F the X/Y
  * qubits (P's one nonzero per column is i^nY (-1)^|x & z|, z the Z/Y qubits).
  * Asynchronous on the state's stream. Errors: QSV_EINVAL (bad id or length,

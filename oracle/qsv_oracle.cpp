@@ -286,7 +286,7 @@ int orc_apply_observable(const double* psi, double* out, int n, int nterms, cons
   return 0;
 }
 
-// Multi-qubit Pauli rotation exp(+i theta P / 2) (section 4.3.3, Pauli
+// Multi-qubit Pauli rotation exp(+i theta P / 2) (section 4.3.2, Pauli
 // rotation; the factor 1/2 follows the one-qubit rotations of Table 1), P a
 // Pauli string on w distinct qubits (ids 1..3; 0 = identity on that qubit).
 // Since P^2 = I, exp(i theta P/2) = cos(theta/2) I + i sin(theta/2) P; P psi is

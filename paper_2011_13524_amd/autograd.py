@@ -16,15 +16,18 @@ from .binding import Circuit, Observable, Plan, State, adjoint_gradient
 
 
 class _Workspace:
-    """Two device states (psi, lambda) reused across calls for one (n, dtype)."""
+    """Two device states (psi, lambda) reused across calls for one (n, dtype,
+    stream): the library enqueues on torch's current stream, so the energy and
+    gradient are ordered with the caller's other work on that stream."""
 
     _cache: dict = {}
 
     @classmethod
     def get(cls, n: int, dtype: str):
-        key = (n, dtype)
+        stream = torch.cuda.current_stream() if torch.cuda.is_available() else None
+        key = (n, dtype, None if stream is None else int(stream.cuda_stream))
         if key not in cls._cache:
-            cls._cache[key] = (State(n, dtype), State(n, dtype))
+            cls._cache[key] = (State(n, dtype, stream=stream), State(n, dtype, stream=stream))
         return cls._cache[key]
 
 

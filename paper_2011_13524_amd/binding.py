@@ -99,6 +99,15 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2011_13524_amd.build`")
+        # One HIP runtime per process: torch ships its own copy of the HIP
+        # runtime, and a second copy loaded beside it finds no device. With
+        # torch imported first, the library's libamdhip64.so.7 dependency
+        # resolves to the copy torch loaded, so the library and torch share
+        # one runtime (and can share streams and memory).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)

@@ -11,6 +11,7 @@
 // states are streamed once per pass instead of once per gate.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "circuit.h"
 #include "dev_common.h"
@@ -710,7 +711,11 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
   }
   const int nrows = int(row_slot.size());
   const uint64_t tiles = dim(n - L);
-  const int G = int(std::min<uint64_t>(tiles, reg ? kAdjRegGrid : kAdjTileGrid));
+  // persistent grid; QSV_ADJOINT_GRID overrides it (tuning, and tests that give
+  // every workgroup a ragged range of several tiles at small sizes)
+  uint64_t gmax = reg ? kAdjRegGrid : kAdjTileGrid;
+  if (const char* e = std::getenv("QSV_ADJOINT_GRID")) gmax = uint64_t(std::max(1, std::atoi(e)));
+  const int G = int(std::min<uint64_t>(tiles, gmax));
   // one device allocation: passes | ops | pool | segs | rops | prow | partial[nrows x G] | rows[nrows]
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t o_ops = al(hp.size() * sizeof(TilePassDev));

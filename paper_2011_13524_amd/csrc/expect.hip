@@ -80,6 +80,14 @@ constexpr int kExpLdsTerms = 128;
 // by 3.5% (shorter ranges even out the tail); QSV_EXPECT_GRID overrides
 constexpr int kExpGrid = 2048;
 
+// Persistent grid of the expectation and lambda passes: kExpGrid, or the
+// QSV_EXPECT_GRID override (tuning, and tests that give every workgroup a
+// ragged range of several tiles at small sizes).
+uint64_t exp_grid_max() {
+  if (const char* e = std::getenv("QSV_EXPECT_GRID")) return uint64_t(std::max(1, std::atoi(e)));
+  return kExpGrid;
+}
+
 struct ExpPlan {
   int n = 0, L = 0, b = 0;
   std::vector<ExpPassDev> passes;
@@ -139,8 +147,10 @@ __device__ __forceinline__ uint64_t uni(uint64_t v) {
 }
 
 // Streaming of tiles through registers into LDS. Workgroups are persistent:
-// workgroup b takes tiles b, b + grid, b + 2 grid, ... in that order (so its
-// partial sums have a fixed order), and the loads of its next tile are issued
+// workgroup b takes the contiguous range of tile indices [b per, (b + 1) per),
+// per = ceil(tiles / grid), in increasing order (ExpTileRange below: the next
+// tile's base is the current one carried within the non-local qubit mask), so
+// its partial sum has a fixed order; the loads of its next tile are issued
 // before it computes on the current one.
 template <typename R, int NT, int LT = 0>
 struct ExpTileStream {
@@ -668,9 +678,7 @@ int expect_tiled_t(qsv_state* s, qsv_observable* o, double* out) {
   int rc = upload_exp_plan(pl, s->device);
   if (rc) return rc;
   const uint64_t tiles = dim(s->n - pl->L);
-  uint64_t gmax = kExpGrid;
-  if (const char* e = std::getenv("QSV_EXPECT_GRID")) gmax = uint64_t(std::max(1, std::atoi(e)));  // tuning
-  const uint64_t grid = std::min<uint64_t>(tiles, gmax);
+  const uint64_t grid = std::min<uint64_t>(tiles, exp_grid_max());
   if ((rc = ensure_reduce_scratch(s, size_t(grid) + 1))) return rc;
   const size_t lds = (size_t(1) << pl->L) * sizeof(cx<R>);
   // kernel variant: tile of the default size (compile-time trip counts), at
@@ -731,7 +739,7 @@ int apply_obs_tiled_t(const qsv_state* in, qsv_observable* o, qsv_state* out) {
   char* d = static_cast<char*>(pl->dev);
   for (size_t pi = 0; pi < pl->passes.size(); ++pi) {
     ProfScope ps("apply_obs", double(sizeof(cx<R>)) * double(N) * (pi > 0 ? 3.0 : 2.0), in->stream);
-    const dim3 grid(unsigned(std::min<uint64_t>(tiles, kExpGrid)));
+    const dim3 grid(unsigned(std::min<uint64_t>(tiles, exp_grid_max())));
     const auto* pd = reinterpret_cast<const ExpPassDev*>(d);
     const auto* gd = reinterpret_cast<const ExpGroupDev*>(d + pl->off_groups);
     const auto* td = reinterpret_cast<const ExpTermDev*>(d + pl->off_terms);

@@ -1,4 +1,4 @@
-// Multi-qubit Pauli rotations exp(+i t P / 2) (section 4.3.3, Pauli rotation;
+// Multi-qubit Pauli rotations exp(+i t P / 2) (section 4.3.2, Pauli rotation;
 // the factor 1/2 as in the one-qubit rotations of Table 1) and transition
 // amplitudes <a|O|b> (section 4.5).
 //

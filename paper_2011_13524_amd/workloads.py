@@ -30,7 +30,7 @@ same structure):
   random_u_cz         layers of a Haar-random one-qubit unitary per qubit and
                       CZ on a random perfect matching of the qubits (n=26, 20
                       layers), modelled on the paper's random-circuit benchmark
-                      (section 6.3).
+                      (section 6.6).
   hea_ry_rz_cz        hardware-efficient ansatz: layers of parametric RY, RZ on
                       every qubit and a CZ ladder (batched VQE items).
   ry_rz_cnot_ring     layers of parametric RY, RZ on every qubit and a CNOT ring

@@ -91,7 +91,9 @@ def test_shared_parameter_slot_sums_contributions():
 def test_adjoint_24q_sampled_against_gpu_shift(dt):
     # full-size adjoint workload (24 qubits, 20 layers, 500-term observable):
     # sampled gradient components against the exact shift rule evaluated with
-    # the (oracle-pinned) GPU forward + expectation.
+    # the GPU forward + expectation (those kernels meet the oracle on the same
+    # multi-tile paths in test_gpu_ranges.py, where a 24-qubit adjoint of the
+    # same circuit family is also compared with the oracle's own shift rule).
     n = 24
     gates, npar = W.ry_rz_cnot_ring(n, 20)
     theta = W.uniform_angles(npar, (4, 0))
@@ -122,7 +124,10 @@ def test_adjoint_24q_sampled_against_gpu_shift(dt):
 def test_adjoint_32q_c64_sampled():
     # 32 qubits complex64 (34.4 GB per state; psi, lambda and a check state in
     # HBM): sampled gradient components against the exact shift rule evaluated
-    # with the GPU forward + expectation (oracle-pinned up to 30 qubits)
+    # with the GPU forward + expectation. Those kernels are compared with the
+    # oracle at up to 16 qubits on every code path they take here (several
+    # tiles per persistent workgroup included, test_gpu_ranges.py) and at 24
+    # qubits on sampled inputs (test_gpu_ranges.py).
     n = 32
     gates, npar = W.ry_rz_cnot_ring(n, 20)
     theta = W.uniform_angles(npar, (4, 2))

@@ -147,3 +147,41 @@ def test_autotuned_launch_shape_matches_default(dt):
         scale = sum(abs(c) for c, _ in it["obs"])
         assert abs(e[i] - e0[i]) <= TOL[dt] * scale, (i, ch)
         assert np.max(np.abs(g[i] - g0[i])) <= TOL[dt] * scale, (i, ch)
+
+
+_ORACLE_DEV = {}
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_device_memory_items_vs_oracle(dt):
+    # items of 13-18 qubits run the in-workgroup device-memory tile passes
+    # (most of the batched-VQE workload's items): energies and sampled
+    # gradient components of one item per size against the oracle's exact
+    # shift rule
+    items = W.batch_items(24, seed=3)
+    picked = {}
+    for i, it in enumerate(items):
+        picked.setdefault(it["n"], i)
+    extra = []
+    for n in (13, 15):  # odd sizes: tiles whose non-local bits are not byte-aligned
+        gates, npar = W.ry_rz_cnot_ring(n, 3)
+        gates = [{"op": "h", "q": [n - 1]}] + gates + [{"op": "cz", "q": [0, n - 1]}]
+        extra.append({"n": n, "gates": gates, "theta": W.uniform_angles(npar, (31, n)),
+                      "obs": W.random_pauli_observable(n, 16, (1, 5), seed_key=(31, n))})
+    cases = [items[picked[n]] for n in (14, 16, 18) if n in picked] + extra
+    assert len(cases) == 5
+    b = Batch()
+    for it in cases:
+        b.add(Circuit.from_records(it["n"], it["gates"]), Observable(it["n"], it["obs"]), it["theta"])
+    e, g = b.run(dt)
+    for i, it in enumerate(cases):
+        n, npar = it["n"], len(it["theta"])
+        slots = [0, npar // 2, npar - 1]
+        if i not in _ORACLE_DEV:  # (one oracle run serves both dtypes)
+            _ORACLE_DEV[i] = (O.energy(n, it["gates"], it["theta"], it["obs"]),
+                              O.param_shift_grad(n, it["gates"], it["theta"], it["obs"], slots=slots))
+        e_ref, g_ref = _ORACLE_DEV[i]
+        scale = sum(abs(c) for c, _ in it["obs"])
+        assert abs(e[i] - e_ref) <= TOL[dt] * scale, (i, n)
+        assert np.max(np.abs(g[i][slots] - g_ref)) <= TOL[dt] * scale, (i, n)
