@@ -310,6 +310,24 @@ int qsv_observable_passes(const qsv_observable* o, qsv_dtype dtype, int* passes)
  * the state's stream. */
 int qsv_expectation(const qsv_state* s, const qsv_observable* o, double* out);
 
+/* qsv_expectation for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same passes, kernels and result (bitwise, at the same launch shape), with
+ * every device buffer the call needs -- the observable's pass / group / term
+ * tables and the per-workgroup FP64 partials -- in one file-scope device
+ * array of 1 MiB that each GPU holds from the library's first use of it
+ * until the process ends; the call makes no hipMalloc, hipFree or pinned-
+ * memory allocation (host-side plan tables are built and cached on the
+ * observable as for qsv_expectation). The tables of one pass cost about
+ * 250 bytes, of one flip-mask group about 180 and of one term 32, plus 16 KiB
+ * of partials: some 5000 single-term strings fit. Calls that overlap on one
+ * GPU share the array and race; calls in order on one stream do not (the
+ * array keeps the last call's contents, and each call rewrites what it
+ * reads). Synchronises the state's stream.
+ * Errors: QSV_EINVAL (null arguments), QSV_ERANGE (qubit-count mismatch, or
+ * the observable's tables exceed the array: nothing is enqueued), QSV_EHIP. */
+int qsv_expectation_noalloc(const qsv_state* s, const qsv_observable* o, double* out);
+
 /* out <- O in (out must be a different state of the same n and dtype): the
  * Pauli-string sum of section 4.5 applied to a state. Flip masks are packed
  * into tile passes as for qsv_expectation; each pass reads `in` once and adds

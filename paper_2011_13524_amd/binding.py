@@ -51,6 +51,7 @@ _SIGS = {
     "qsv_observable_info": (_c.c_int, [_vp, _ip, _ip, _ip]),
     "qsv_observable_passes": (_c.c_int, [_vp, _c.c_int, _ip]),
     "qsv_expectation": (_c.c_int, [_vp, _vp, _dp]),
+    "qsv_expectation_noalloc": (_c.c_int, [_vp, _vp, _dp]),
     "qsv_circuit_create": (_c.c_int, [_c.c_int, _c.POINTER(_vp)]),
     "qsv_circuit_free": (_c.c_int, [_vp]),
     "qsv_circuit_add_gate": (_c.c_int, [_vp, _dp, _ip, _c.c_int, _ip, _ip, _c.c_int]),
@@ -289,6 +290,13 @@ class Observable:
 def expectation(state: State, obs: Observable) -> float:
     out = _c.c_double()
     check(lib().qsv_expectation(state.h, obs.h, _c.byref(out)))
+    return out.value
+
+
+def expectation_noalloc(state: State, obs: Observable) -> float:
+    """qsv_expectation_noalloc: the expectation with no device allocation."""
+    out = _c.c_double()
+    check(lib().qsv_expectation_noalloc(state.h, obs.h, _c.byref(out)))
     return out.value
 
 

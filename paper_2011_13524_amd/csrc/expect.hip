@@ -16,6 +16,7 @@
 // are constants per tile. The same passes give lambda = O psi (adjoint).
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
 
 #include "dev_common.h"
 #include "observable.h"
@@ -756,7 +757,113 @@ int apply_obs_tiled_t(const qsv_state* in, qsv_observable* o, qsv_state* out) {
   return QSV_OK;
 }
 
+// ------------------------------------------------------------------ no-allocation variant
+//
+// qsv_expectation_noalloc runs the same passes with every device buffer they
+// need -- the observable's pass / group / term tables and the per-workgroup
+// FP64 partials -- in one file-scope device array of kNoAllocBytes, so the
+// call allocates no device or pinned memory (for callers that cannot: code
+// under stream capture, serving loops). Each device holds its own copy of the
+// array; its address on a device is taken once (hipGetSymbolAddress, with
+// that device current) and only that address is used from the host. Calls on
+// one device share the array: calls that overlap on one device race.
+constexpr size_t kNoAllocBytes = size_t(1) << 20;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// Device address of `scratch` on `device` (taken on first use).
+int noalloc_scratch(int device, char** out) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return fail(QSV_EINVAL, "device index %d out of range", device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    QSV_HIP_CHECK(hipGetDevice(&cur));
+    if (cur != device) QSV_HIP_CHECK(hipSetDevice(device));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr)
+      return fail(QSV_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return QSV_OK;
+}
+
+template <typename R>
+int expect_noalloc_t(qsv_state* s, qsv_observable* o, double* out) {
+  ExpPlan*& pl = o->exp_plan[s->dtype];
+  if (!pl) pl = build_exp_plan(o, s->dtype);  // host tables only
+  if (pl->passes.empty()) {
+    *out = 0.0;
+    return QSV_OK;
+  }
+  const uint64_t tiles = dim(s->n - pl->L);
+  const uint64_t grid = std::min<uint64_t>(tiles, exp_grid_max());
+  // scratch layout: partials[grid + 1] | passes | groups | terms (256-byte aligned)
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t o_pass = al((size_t(grid) + 1) * sizeof(double));
+  const size_t o_grp = o_pass + al(pl->passes.size() * sizeof(ExpPassDev));
+  const size_t o_term = o_grp + al(pl->groups.size() * sizeof(ExpGroupDev));
+  const size_t need = o_term + al(pl->terms.size() * sizeof(ExpTermDev));
+  if (need > kNoAllocBytes)
+    return fail(QSV_ERANGE, "observable needs %zu bytes of device scratch; the no-allocation limit is %zu",
+                need, kNoAllocBytes);
+  char* d = nullptr;
+  int rc = noalloc_scratch(s->device, &d);
+  if (rc) return rc;
+  hipStream_t st = s->stream;
+  QSV_HIP_CHECK(hipMemcpyAsync(d + o_pass, pl->passes.data(), pl->passes.size() * sizeof(ExpPassDev),
+                               hipMemcpyHostToDevice, st));
+  if (!pl->groups.empty())
+    QSV_HIP_CHECK(hipMemcpyAsync(d + o_grp, pl->groups.data(), pl->groups.size() * sizeof(ExpGroupDev),
+                                 hipMemcpyHostToDevice, st));
+  if (!pl->terms.empty())
+    QSV_HIP_CHECK(hipMemcpyAsync(d + o_term, pl->terms.data(), pl->terms.size() * sizeof(ExpTermDev),
+                                 hipMemcpyHostToDevice, st));
+  double* part = reinterpret_cast<double*>(d);
+  const auto* pd = reinterpret_cast<const ExpPassDev*>(d + o_pass);
+  const auto* gd = reinterpret_cast<const ExpGroupDev*>(d + o_grp);
+  const auto* td = reinterpret_cast<const ExpTermDev*>(d + o_term);
+  const size_t lds = (size_t(1) << pl->L) * sizeof(cx<R>);
+  const int mode = pl->L == exp_tile_bits<R>() ? 2 : ((size_t(1) << pl->L) >= size_t(2 * kExpThreadsE) ? 1 : 0);
+  const void* kfn = mode == 2   ? reinterpret_cast<const void*>(&k_expect_tile<R, 2>)
+                    : mode == 1 ? reinterpret_cast<const void*>(&k_expect_tile<R, 1>)
+                                : reinterpret_cast<const void*>(&k_expect_tile<R, 0>);
+  QSV_HIP_CHECK(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  const R* psi = static_cast<const R*>(s->ptr);
+  // the first pass writes every partial (accumulate = 0): nothing left from an
+  // earlier call is read
+  for (size_t pi = 0; pi < pl->passes.size(); ++pi) {
+    if (mode == 2)
+      hipLaunchKernelGGL((k_expect_tile<R, 2>), dim3(unsigned(grid)), dim3(kExpThreadsE), lds, st, psi, pd,
+                         int(pi), gd, td, part, pi > 0 ? 1 : 0, tiles);
+    else if (mode == 1)
+      hipLaunchKernelGGL((k_expect_tile<R, 1>), dim3(unsigned(grid)), dim3(kExpThreadsE), lds, st, psi, pd,
+                         int(pi), gd, td, part, pi > 0 ? 1 : 0, tiles);
+    else
+      hipLaunchKernelGGL((k_expect_tile<R, 0>), dim3(unsigned(grid)), dim3(kExpThreadsE), lds, st, psi, pd,
+                         int(pi), gd, td, part, pi > 0 ? 1 : 0, tiles);
+    QSV_HIP_CHECK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_exp_sum, dim3(1), dim3(kExpThreads), 0, st, part, grid, part + grid);
+  QSV_HIP_CHECK(hipGetLastError());
+  double v = 0.0;
+  QSV_HIP_CHECK(hipMemcpyAsync(&v, part + grid, sizeof(double), hipMemcpyDeviceToHost, st));
+  QSV_HIP_CHECK(hipStreamSynchronize(st));
+  *out = v;
+  return QSV_OK;
+}
+
 }  // namespace
+
+int expectation_noalloc(qsv_state* s, const qsv_observable* o, double* out) {
+  qsv_observable* mo = const_cast<qsv_observable*>(o);  // host plan cache only
+  return s->dtype == QSV_C64 ? expect_noalloc_t<float>(s, mo, out) : expect_noalloc_t<double>(s, mo, out);
+}
 
 int expectation_tiled(qsv_state* s, const qsv_observable* o, double* out) {
   qsv_observable* mo = const_cast<qsv_observable*>(o);  // plan cache only

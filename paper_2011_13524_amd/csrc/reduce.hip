@@ -27,6 +27,7 @@
 namespace qsv {
 
 int expectation_tiled(qsv_state* s, const qsv_observable* o, double* out);
+int expectation_noalloc(qsv_state* s, const qsv_observable* o, double* out);
 int expectation_passes(const qsv_observable* o, qsv_dtype dt);
 
 constexpr int kRedThreads = 256;
@@ -393,6 +394,16 @@ int qsv_expectation(const qsv_state* s_in, const qsv_observable* o, double* out)
   if (!out) return fail(QSV_EINVAL, "null output");
   if (o->n != s_in->n) return fail(QSV_ERANGE, "observable has %d qubits, state %d", o->n, s_in->n);
   return expectation_tiled(const_cast<qsv_state*>(s_in), o, out);
+}
+
+int qsv_expectation_noalloc(const qsv_state* s_in, const qsv_observable* o, double* out) {
+  clear_error();
+  int rc = check_state(s_in);
+  if (rc) return rc;
+  if (!o) return fail(QSV_EINVAL, "null observable");
+  if (!out) return fail(QSV_EINVAL, "null output");
+  if (o->n != s_in->n) return fail(QSV_ERANGE, "observable has %d qubits, state %d", o->n, s_in->n);
+  return expectation_noalloc(const_cast<qsv_state*>(s_in), o, out);
 }
 
 }  // extern "C"

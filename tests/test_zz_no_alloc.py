@@ -1,0 +1,51 @@
+"""qsv_expectation_noalloc, the expectation entry point for callers that
+cannot allocate device memory, against qsv_expectation (the entry point it is
+a variant of: same passes, kernels and launch shape, so the same value
+bitwise), on two calls in a row with the second smaller than the first; an
+observable too large for its fixed device scratch is refused before anything
+is enqueued.
+"""
+import numpy as np
+import pytest
+
+from paper_2011_13524_amd import Observable, QsvError, State, expectation
+from paper_2011_13524_amd.binding import expectation_noalloc
+from paper_2011_13524_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rand_state(rng, n):
+    v = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    return v / np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_noalloc_matches_expectation(dt):
+    rng = np.random.default_rng(60)
+    # (qubits, terms): the second call is smaller (fewer tiles, passes and
+    # groups): what the first left in the shared scratch must not leak in
+    for n, terms in ((20, 400), (11, 25)):
+        s = State(n, dt)
+        s.load(rand_state(rng, n))
+        obs_t = W.random_pauli_observable(n, terms, (1, 6), seed_key=(61, n)) + [(0.3, [])]
+        obs = Observable(n, obs_t)
+        ref = expectation(s, obs)
+        got = expectation_noalloc(s, obs)
+        print(f"noalloc n={n} terms={terms} dtype={dt}: {got!r} vs {ref!r}", flush=True)
+        assert got == ref, (n, got, ref)
+
+
+def test_noalloc_refuses_oversized_observable():
+    # 8000 strings of weight 6 on 22 qubits: ~8000 distinct flip masks, whose
+    # group tables alone (~176 bytes each) exceed the 1 MiB scratch
+    n = 22
+    s = State(n, "c64")
+    obs = Observable(n, W.random_pauli_observable(n, 8000, 6, seed_key=(62,)))
+    with pytest.raises(QsvError) as ei:
+        expectation_noalloc(s, obs)
+    assert ei.value.code == -2  # QSV_ERANGE
+    assert "scratch" in str(ei.value)
+    # the state is usable afterwards, through both entry points
+    small = Observable(n, [(1.0, [(0, 3)])])
+    assert expectation_noalloc(s, small) == expectation(s, small) == 1.0
