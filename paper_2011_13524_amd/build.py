@@ -3,7 +3,7 @@
 Usage: python -m paper_2011_13524_amd.build   (or build() from Python)
 
 Every translation unit is compiled by hipcc for gfx950 only, with packed FP32
-instructions disabled, then linked into paper_2011_13524_amd/libqsv.so.
+instructions disabled and matrix-core results in VGPRs, then linked into paper_2011_13524_amd/libqsv.so.
 """
 from __future__ import annotations
 
@@ -23,6 +23,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results stay in ordinary VGPRs (the register tiles feed them
+    # straight back to vector code; accumulation registers would cost copies
+    # and occupancy)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wno-unused-result", "-I" + os.path.join(HERE, "..", "include"),
 ]
 

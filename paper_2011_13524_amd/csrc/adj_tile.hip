@@ -580,7 +580,7 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
   const int L = std::min(n, Lc);
   // complex64: 256 threads x 16 amplitudes per state; complex128: 256 x 8
   const bool reg = n >= Lc;
-  const SegCfg cfg{sizeof(R) == 4 ? 4 : 3, 8, sizeof(R) == 4};
+  const SegCfg cfg{sizeof(R) == 4 ? 4 : 3, 8, sizeof(R) == 4, sizeof(R) == 4 && tile_mfma_default()};
   const int b = std::min(L, sizeof(R) == 4 ? 4 : 3);  // 128-byte contiguous runs
   const uint64_t low = (uint64_t(1) << b) - 1;
   std::vector<std::vector<int>> pass_ops;

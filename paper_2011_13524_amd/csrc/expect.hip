@@ -254,6 +254,15 @@ __host__ __device__ constexpr int exp_tile_bits() {
   return sizeof(R) == 4 ? 12 : 11;
 }
 
+// Re (REAL) or Im of conj(b) a. complex64: formed in FP32 (one rounding,
+// relative error <= 2^-23 of |a||b|; the caller accumulates in FP64), which
+// halves the vector instructions per pair against converting all four
+// components first; complex128: FP64.
+template <typename R, bool REAL>
+__device__ __forceinline__ R pair_product(const cx<R>& a, const cx<R>& b) {
+  return REAL ? fma(b.re, a.re, b.im * a.im) : fma(b.re, a.im, -(b.im * a.re));
+}
+
 // One single-term group with flip mask lf != 0 over a tile: the sum over the
 // pairs (x, x ^ lf), x with bit hb clear, of Re (REAL) or Im of
 // conj(psi_y) psi_x with the term's local Z/Y sign, in FP64. x is the thread
@@ -272,17 +281,17 @@ __device__ __forceinline__ double exp_pairs(const cx<R>* tx, const cx<R>* ty, co
     if (i0 >= TS / 2) break;
     if (FULL || i0 + tid < TS / 2) {
       const cx<R> a = tx[D.offx[k]], b = ty[D.offy[k]];
-      const double w = REAL ? double(b.re) * a.re + double(b.im) * a.im
-                            : double(b.re) * a.im - double(b.im) * a.re;
-      sw += xor_sign(w, pt ^ D.sgn[k]);
+      sw += xor_sign(double(pair_product<R, REAL>(a, b)), D.sgn[k]);
     }
   }
-  return sw;
+  return xor_sign(sw, pt);  // the thread's part of the sign, common to every step
 }
 
-// <psi|O|psi> over the tiles of one pass. Products and sums are FP64 (the
-// product of two FP32 values is exact in FP64), so for complex64 states the
-// reduction adds no error beyond the stored amplitudes. Each workgroup sums its
+// <psi|O|psi> over the tiles of one pass. Sums are FP64; the products of the
+// single-term groups are formed in the amplitude precision (for complex64 one
+// FP32 rounding per product, relative error <= 2^-23, so |dE| <= 2^-23 sum
+// |alpha| <psi|psi> beyond the stored amplitudes), those of multi-term groups
+// in FP64. Each workgroup sums its
 // tiles in a fixed order into partial[blockIdx.x] (added to the value of
 // earlier passes when accumulate is set). MODE 0: any tile size (per-lane
 // guards); 1: the tile has at least two amplitudes per thread, so every loop
@@ -328,7 +337,6 @@ __global__ void __launch_bounds__(kExpThreadsE)
       if (G.lf == 0 && nt == 1) {
         // sum of +-|psi_x|^2: thread part of the sign once, uniform part per step
         uint32_t pt = uint32_t(__popc(tid & G.zl) & 1) << 31;
-        asm volatile("" : "+v"(pt));  // keep the mask whole: one 3-way XOR per element
         double sum = 0.0;
 #pragma unroll
         for (int k = 0; k < NA; ++k) {
@@ -336,11 +344,10 @@ __global__ void __launch_bounds__(kExpThreadsE)
           if (j0 >= TS) break;
           if (FULL || j0 + tid < TS) {
             const cx<R> a = t[j0 + tid];
-            const double p = double(a.re) * a.re + double(a.im) * a.im;
-            sum += xor_sign(p, pt ^ G.d->sgn[k]);
+            sum += xor_sign(double(pair_product<R, true>(a, a)), G.d->sgn[k]);
           }
         }
-        acc += G.re * sum;
+        acc += G.re * xor_sign(sum, pt);
       } else if (G.lf == 0) {
         for (uint32_t j = tid; j < TS; j += NT) {
           const cx<R> a = t[j];
@@ -365,7 +372,6 @@ __global__ void __launch_bounds__(kExpThreadsE)
           const cx<R>* tx = t + xt;
           const cx<R>* ty = t + (xt ^ (lf & mt));
           uint32_t pt = uint32_t(__popc(xt & G.zl) & 1) << 31;
-          asm volatile("" : "+v"(pt));  // keep the mask whole: one 3-way XOR per pair
           if (G.im == 0.0)
             acc += 2.0 * G.re * exp_pairs<R, true, FULL, NA / 2, NT>(tx, ty, *G.d, pt, TS, tid);
           else

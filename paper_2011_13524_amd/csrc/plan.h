@@ -96,7 +96,13 @@ struct RegOpDev {
 struct SegCfg {
   int reg_bits, thread_bits;
   bool c64;  // complex64: the HBM layouts keep local bit 0 in registers (16-byte pairs)
+  bool mfma = false;  // complex64: uncontrolled dense one-qubit ops on the matrix cores
 };
+
+// Whether complex64 register segments put uncontrolled dense one-qubit ops on
+// the matrix cores (default on; QSV_TILE_MFMA=0 keeps them on the vector ALUs,
+// for comparison).
+bool tile_mfma_default();
 
 // Splits the ops of pass d (ho[d.op_begin ..]) into register segments,
 // appending them to segs / rops; d.seg_count is incremented per segment (the

@@ -350,6 +350,11 @@ void pass_runs(TilePassDev& d) {
   }
 }
 
+bool tile_mfma_default() {
+  const char* e = std::getenv("QSV_TILE_MFMA");
+  return !(e && e[0] == '0');
+}
+
 int build_reg_segments(const SegCfg& cfg, const std::vector<TileOpDev>& ho, TilePassDev& d,
                        std::vector<RegSegDev>& out_segs, std::vector<RegOpDev>& out_rops) {
   const int RB = cfg.reg_bits, TB = cfg.thread_bits, L = d.L;
@@ -632,7 +637,9 @@ int build_reg_segments(const SegCfg& cfg, const std::vector<TileOpDev>& ho, Tile
       } else {
         r.kind = 3;
       }
-      if (r.kind == 0 || r.kind == 1 || r.kind == 4) {
+      if (r.kind == 0 && cfg.c64 && cfg.mfma && r.ri_cm == 0 && r.ti_cm == 0) {
+        r.key = reg_key(7, r.p1, 0, false);
+      } else if (r.kind == 0 || r.kind == 1 || r.kind == 4) {
         r.key = reg_key(r.kind, r.p1, r.p2, r.ri_cm != 0 || r.ti_cm != 0);
       } else if (r.kind == 2) {
         // register-bit targets of the diagonal, ascending (-1: absent)
@@ -765,7 +772,8 @@ static int upload_tables(qsv_plan* p, std::vector<int>& moffs, size_t& pool_elem
     d.seg_begin = int(p->h_segs.size());
     d.seg_count = 0;
     if (p->reg_bits > 0 && d.L == p->reg_bits + p->thread_bits) {
-      const SegCfg cfg{p->reg_bits, p->thread_bits, p->dtype == QSV_C64};
+      const SegCfg cfg{p->reg_bits, p->thread_bits, p->dtype == QSV_C64,
+                       p->dtype == QSV_C64 && tile_mfma_default()};
       int rc = build_reg_segments(cfg, ho, d, p->h_segs, p->h_rops);
       if (rc) return rc;
     }

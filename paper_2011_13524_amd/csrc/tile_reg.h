@@ -163,6 +163,46 @@ __device__ __forceinline__ void reg_dense1(const cx<R>* v, cx<R>* o, const cx<R>
   }
 }
 
+// Dense one-qubit op on the matrix cores (complex64, no controls). For the
+// register pair (a, b) of a lane, the output (a', b') is the real 4x4 matrix
+// [[Re m00, -Im m00, Re m01, -Im m01], [Im m00, Re m00, Im m01, Re m01],
+//  [Re m10, -Im m10, Re m11, -Im m11], [Im m10, Re m10, Im m11, Re m11]]
+// times (Re a, Im a, Re b, Im b). v_mfma_f32_4x4x1_16b_f32 forms, per block of
+// four lanes, the outer product of a 4-vector held one element per lane (A)
+// and each lane's own scalar (B), accumulated into four registers per lane:
+// register r of lane l gains A(lane 4*(l/4) + r) * B(l). With A = column c of
+// the matrix (row = lane % 4) and B = input component c of the lane's own
+// pair, four accumulating instructions give each lane its own (a', b') in the
+// register order (Re a', Im a', Re b', Im b'): the layout the vector ALU code
+// uses, at twice the non-packed FP32 FMA rate, off the vector ALU.
+template <int NR, int P>
+__device__ __forceinline__ void reg_dense1_mfma(const cx<float>* v, cx<float>* o,
+                                                const cx<float>* __restrict__ m) {
+  if constexpr ((1 << P) >= NR) {
+    reg_copy<float, NR>(v, o);
+  } else {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const uint32_t lane = threadIdx.x & 63u;
+    const bool hi = (lane & 2u) != 0, odd = (lane & 1u) != 0;
+    const cx<float> m00 = m[0], m01 = m[1], m10 = m[2], m11 = m[3];
+    const float c0r = hi ? m10.re : m00.re, c0i = hi ? m10.im : m00.im;
+    const float c1r = hi ? m11.re : m01.re, c1i = hi ? m11.im : m01.im;
+    const float a0 = odd ? c0i : c0r, a1 = odd ? c0r : -c0i;
+    const float a2 = odd ? c1i : c1r, a3 = odd ? c1r : -c1i;
+#pragma unroll
+    for (int g = 0; g < NR / 2; ++g) {
+      const int i = ins1<P>(g), j = i | (1 << P);
+      v4f d = {0.f, 0.f, 0.f, 0.f};
+      d = __builtin_amdgcn_mfma_f32_4x4x1f32(a0, v[i].re, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_4x4x1f32(a1, v[i].im, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_4x4x1f32(a2, v[j].re, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_4x4x1f32(a3, v[j].im, d, 0, 0, 0);
+      o[i] = {d[0], d[1]};
+      o[j] = {d[2], d[3]};
+    }
+  }
+}
+
 // Pauli-X exchange (X, CNOT on register bits): moves only.
 template <typename R, int NR, int P, bool HASC>
 __device__ __forceinline__ void reg_swap1(const cx<R>* v, cx<R>* o, uint32_t cm, uint32_t cv, bool lane) {
@@ -254,10 +294,18 @@ __device__ __forceinline__ void reg_diag(const cx<R>* v, cx<R>* o, const cx<R>* 
 #define QSV_CDP5(HC)                                                             \
   QSV_CD(HC, 4, -1) QSV_CD(HC, 0, 4) QSV_CD(HC, 1, 4) QSV_CD(HC, 2, 4) QSV_CD(HC, 3, 4)
 
-// kind 0 dense one-qubit, 1 dense two-qubit, 2 diagonal, 4 Pauli-X exchange;
-// a, b: register bits (diagonal: -1 when absent, a < b)
+#define QSV_CM(P)                                                                \
+  case 288 + (P):                                                                \
+    if constexpr (sizeof(R) == 4) reg_dense1_mfma<NR, P>(v, o, m);               \
+    else __builtin_unreachable();                                                \
+    break;
+
+// kind 0 dense one-qubit, 1 dense two-qubit, 2 diagonal, 4 Pauli-X exchange,
+// 7 dense one-qubit on the matrix cores (complex64, no controls); a, b:
+// register bits (diagonal: -1 when absent, a < b)
 __host__ __device__ __forceinline__ int reg_key(int kind, int a, int b, bool hc) {
   const int h = hc ? 1 : 0;
+  if (kind == 7) return 288 + a;
   if (kind == 1) return 32 + h * 64 + a * 8 + b;
   if (kind == 2) return 160 + h * 64 + (a + 1) * 8 + (b + 1);
   return ((kind == 4) * 2 + h) * 8 + a;
@@ -270,9 +318,11 @@ __device__ __forceinline__ void reg_apply(const cx<R>* v, cx<R>* o, int key, con
     QSV_C1P(0, 0) QSV_C1P(0, 1) QSV_C1P(1, 0) QSV_C1P(1, 1)
     QSV_C2P4(0) QSV_C2P4(1)
     QSV_CDP4(0) QSV_CDP4(1)
+    QSV_CM(0) QSV_CM(1) QSV_CM(2) QSV_CM(3)
     default:
       if constexpr (NR > 16) {
         switch (key) {
+          QSV_CM(4)
           QSV_C1(0, 0, 4) QSV_C1(0, 1, 4) QSV_C1(1, 0, 4) QSV_C1(1, 1, 4)
           QSV_C2P5(0) QSV_C2P5(1)
           QSV_CDP5(0) QSV_CDP5(1)
@@ -293,6 +343,7 @@ __device__ __forceinline__ void reg_apply(const cx<R>* v, cx<R>* o, int key, con
 #undef QSV_CD
 #undef QSV_CDP4
 #undef QSV_CDP5
+#undef QSV_CM
 
 // Factor table of a diagonal op (k <= 2) for this thread: index bits from
 // thread and non-local targets are fixed; register targets become the bits

@@ -174,12 +174,14 @@ def test_zz_autograd_function():
                                atol=1e-11)
 
 
-@pytest.mark.parametrize("dt", ["c128", "c64"])
-def test_tiled_reverse_sweep_vs_parameter_shift(dt, monkeypatch):
+@pytest.mark.parametrize("dt,mfma", [("c128", "1"), ("c64", "1"), ("c64", "0")])
+def test_tiled_reverse_sweep_vs_parameter_shift(dt, mfma, monkeypatch):
     # the tile-pass reverse sweep (used by default from 20 qubits) forced on
     # small states: one tile (n=9) and several tiles with non-local controls
-    # and diagonal gates (n=14)
+    # and diagonal gates (n=14); complex64 one-qubit ops on the matrix cores
+    # (default) and on the vector ALU
     monkeypatch.setenv("QSV_ADJOINT_TILED_MIN", "1")
+    monkeypatch.setenv("QSV_TILE_MFMA", mfma)
     cases = [(9, W.ry_rz_cnot_ring(9, 2)), (14, W.hea_ry_rz_cz(14, 1))]
     for n, (gates, npar) in cases:
         # (one gate per slot: the two-term shift rule is exact only then)

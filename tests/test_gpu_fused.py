@@ -214,3 +214,26 @@ def test_commuting_diagonal_blocks_run_ahead(dt):
         got, info = fused_state(n, gates, dt, **kw)
         assert info["passes"] > 1
         assert np.max(np.abs(got - ref)) <= AMP_TOL[dt], (kw, info)
+
+
+@pytest.mark.parametrize("mfma", ["1", "0"])
+@pytest.mark.parametrize("tb,tile", [("8", 0), ("9", 13), ("8", 13), ("7", 11)])
+def test_one_qubit_ops_matrix_cores_and_vector_alu(mfma, tb, tile, monkeypatch):
+    # complex64 register tiles run uncontrolled dense one-qubit ops on the
+    # matrix cores by default (QSV_TILE_MFMA=0: vector ALU); Haar gates on
+    # every qubit (every register bit of every segment) with CZ and CNOT
+    # layers between them, both forms against the oracle
+    monkeypatch.setenv("QSV_TILE_MFMA", mfma)
+    monkeypatch.setenv("QSV_TILE_THREAD_BITS", tb)
+    n = 16
+    rng = np.random.default_rng(int(tb) * 10 + int(mfma))
+    gates = []
+    for layer in range(6):
+        for q in range(n):
+            gates.append({"op": "dense", "q": [q], "mat": W.haar_unitary(rng, 2)})
+        for q in range(layer % 2, n - 1, 2):
+            gates.append({"op": "cz" if layer % 3 else "cnot", "q": [q, q + 1]})
+    got, info = fused_state(n, gates, "c64", max_k=1, tile_qubits=tile)
+    assert info["segments"] > 0
+    ref = O.run_circuit(n, gates)
+    assert np.max(np.abs(got - ref)) <= AMP_TOL["c64"], info

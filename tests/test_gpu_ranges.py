@@ -13,9 +13,10 @@ positions); and the default grids are checked at 24 qubits on seeded inputs
 against the oracle.
 
 Bars (section 4.5 expectation, the adjoint of section 4.4's parametric
-circuits): expectations of a loaded state <= 1e-12 * sum|alpha| (both dtypes:
-the GPU reduces the stored amplitudes in FP64, the oracle the same rounded
-amplitudes); O psi <= 1e-13 * sum|alpha| (c128) and 1e-6 * sum|alpha| (c64,
+circuits): expectations of a loaded state <= 1e-12 * sum|alpha| (c128) and
+(2^-23 + 1e-12) * sum|alpha| (c64: each pair product is formed in FP32, one
+rounding of relative size <= 2^-23, then summed in FP64; the oracle reduces
+the same rounded amplitudes); O psi <= 1e-13 * sum|alpha| (c128) and 1e-6 * sum|alpha| (c64,
 lambda stored in complex64); energies and gradients of circuits <= 1e-10 *
 sum|alpha| (c128) and 2e-5 * sum|alpha| (c64).
 """
@@ -28,6 +29,10 @@ from paper_2011_13524_amd import (Circuit, Observable, Plan, State, adjoint_grad
 from paper_2011_13524_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+# expectation of a loaded (unit-norm) state against the oracle on the same
+# rounded amplitudes, per unit of sum|alpha|
+E_LOADED = {"c128": 1e-12, "c64": 2.0 ** -23 + 1e-12}
 
 GRAD_TOL = {"c128": 1e-10, "c64": 2e-5}
 LAM_TOL = {"c128": 1e-13, "c64": 1e-6}
@@ -68,7 +73,7 @@ def test_expectation_and_lambda_ragged_ranges(dt, grid, monkeypatch):
         s, out = State(n, dt), State(n, dt)
         s.load(psi)
         e = expectation(s, obs)
-        assert abs(e - O.expectation(ref_in, obs_t)) <= 1e-12 * scale, (n, dt, grid)
+        assert abs(e - O.expectation(ref_in, obs_t)) <= E_LOADED[dt] * scale, (n, dt, grid)
         apply_observable(s, obs, out)
         err = np.max(np.abs(out.store() - O.apply_observable(ref_in, obs_t)))
         assert err <= LAM_TOL[dt] * scale, (n, dt, grid, err)
@@ -110,7 +115,7 @@ def test_expectation_and_lambda_24q_default_grid(dt):
     s, out = State(n, dt), State(n, dt)
     s.load(psi)
     e = expectation(s, obs)
-    assert abs(e - O.expectation(ref_in, obs_t)) <= 1e-12 * scale, dt
+    assert abs(e - O.expectation(ref_in, obs_t)) <= E_LOADED[dt] * scale, dt
     apply_observable(s, obs, out)
     err = np.max(np.abs(out.store() - O.apply_observable(ref_in, obs_t)))
     assert err <= LAM_TOL[dt] * scale, (dt, err)
