@@ -29,6 +29,19 @@ Extra legs (same JSON line):
                 default plan
   pauli_30q     multi-qubit Pauli rotations and transition amplitudes at 30
                 qubits (GB/s of the state sweeps)
+  sample_30q    marginal probabilities and Z-basis sampling at 30 qubits
+  precision_30q_c128
+                the headline step in complex128, and the complex64 energy and
+                amplitudes' error against it
+  small_10q     the 10-qubit complex128 layered circuit: microseconds per
+                circuit (fused, unfused), state and <Z_0> against the oracle
+  iqp_30q       a commuting RZ + CZ circuit at 30 qubits: light vs heavy
+                (commutation-aware) planning, planning time included
+
+Every leg states its results' error: against the CPU oracle where it runs in
+seconds (10 and 26 qubits, sampled batch items), else against the complex128
+GPU path (30-qubit headline, 24-qubit gradients), itself oracle-pinned in the
+tests.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode fused|unfused]
                        [--quick] [--no-cpu] [--leg NAME]
@@ -67,7 +80,8 @@ def parse():
     ap.add_argument("--fd-params", type=int, default=6)
     ap.add_argument("--batch-items", type=int, default=512)
     ap.add_argument("--leg", choices=["adjoint_24q", "batch_vqe", "random_26q", "adjoint_32q",
-                                      "autotune_30q", "pauli_30q", "sample_30q"],
+                                      "autotune_30q", "pauli_30q", "sample_30q", "small_10q",
+                                      "iqp_30q"],
                     help="run only this extra leg and print its JSON (for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also copy the state once (a device copy of known size, used to "
@@ -109,6 +123,52 @@ def read_families(Q, steps):
     return fams
 
 
+def state_diff(a, b, chunk=1 << 24):
+    """max |a - b| and ||a - b|| / ||b|| of two host complex128 vectors (chunked)."""
+    mx, num, den = 0.0, 0.0, 0.0
+    for i in range(0, a.size, chunk):
+        d = a[i:i + chunk] - b[i:i + chunk]
+        mx = max(mx, float(np.max(np.abs(d))))
+        num += float(np.vdot(d, d).real)
+        den += float(np.vdot(b[i:i + chunk], b[i:i + chunk]).real)
+    return mx, (num / den) ** 0.5 if den > 0 else float("nan")
+
+
+def companion_c128(Q, n, circ, obs, obs_terms, state64, e64, steps=3):
+    """The headline step in complex128 on the GPU (the paper's precision), and
+    the complex64 result's error against it: energy and amplitudes."""
+    plan = Q.Plan(circ, "c128", max_k=2)
+    s = Q.State(n, "c128")
+
+    def step():
+        s.set_basis(0)
+        Q.apply_fused(s, plan)
+        return Q.expectation(s, obs)
+
+    step()
+    sync(Q, s)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e = step()
+    sync(Q, s)
+    dt = (time.perf_counter() - t0) / steps
+    ngates = circ.info()[1]
+    a64 = state64.store()  # upcast to complex128 on the host
+    a128 = s.store()
+    mx, rel = state_diff(a64, a128)
+    del a64, a128, s
+    scale = sum(abs(c) for c, _ in obs_terms)
+    return {"workload": "the headline circuit and observable in complex128 (FP64 amplitudes)",
+            "ms_per_step": dt * 1e3, "gates_per_s": ngates / dt, "energy": e,
+            "reference": "complex128 GPU path: oracle-pinned to 1e-12 (amplitudes up to 16 "
+                         "qubits, expectations of 24-qubit states); the 30-qubit oracle needs "
+                         "minutes per gate",
+            "c64_abs_energy_error": abs(e64 - e),
+            "c64_energy_error_over_sum_abs_alpha": abs(e64 - e) / scale,
+            "c64_amp_max_abs_error": mx, "c64_amp_rel_l2_error": rel,
+            "bars": {"amp_max_abs": 1e-5, "energy_over_sum_abs_alpha": 2e-5}}
+
+
 def cpu_baseline(n, gates, budget_s):
     """Time the CPU oracle (complex128) on the first gates of the circuit."""
     from oracle import oracle as O
@@ -123,10 +183,24 @@ def cpu_baseline(n, gates, budget_s):
             break
     dt = time.perf_counter() - t0
     threads = int(lib.orc_num_threads())
+    out = {"value": done / dt, "unit": "gates/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {done} of {len(gates)} gates of the {n}-qubit circuit, complex128, "
+                     f"{dt:.1f} s"}
+    # the same oracle on one thread (a bounded sample: the first gates)
+    lib.orc_set_num_threads(1)
+    done1 = 0
+    t0 = time.perf_counter()
+    for g in gates:
+        O.apply_gate(psi, g)
+        done1 += 1
+        if time.perf_counter() - t0 > budget_s / 3 and done1 >= 1:
+            break
+    dt1 = time.perf_counter() - t0
+    lib.orc_set_num_threads(threads)
     del psi
-    return {"value": done / dt, "unit": "gates/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {done} of {len(gates)} gates of the {n}-qubit circuit, complex128, "
-                      f"{dt:.1f} s"}
+    out["one_thread"] = {"value": done1 / dt1, "unit": "gates/s", "cores": 1,
+                         "sample": f"next {done1} gates of the same circuit, {dt1:.1f} s"}
+    return out
 
 
 def adjoint_leg(Q, W, fd_params):
@@ -138,6 +212,7 @@ def adjoint_leg(Q, W, fd_params):
     obs = Q.Observable(n, obs_t)
     out = {"workload": "24 qubits, 20 layers RY/RZ + CNOT ring (1440 gates, 960 parameters), "
                        "500 random Pauli strings of weight 1..6", "params": npar}
+    grads = {}
     for dt in ("c64", "c128"):
         plan = Q.Plan(circ, dt, max_k=2)
         psi, lam, s = Q.State(n, dt), Q.State(n, dt), Q.State(n, dt)
@@ -165,12 +240,22 @@ def adjoint_leg(Q, W, fd_params):
             fd.append((energy(tp) - energy(tm)) / (2 * h))
         t_fd = (time.perf_counter() - t0) / len(slots)  # seconds per gradient component
         scale = sum(abs(c) for c, _ in obs_t)
+        grads[dt] = (e, g)
         out[dt] = {"adjoint_s": t_adj, "grads_per_s": npar / t_adj,
                    "fd_grads_per_s": 1.0 / t_fd, "fd_sample_params": len(slots), "fd_h": h,
                    "speedup_vs_fd": (npar / t_adj) * t_fd,
                    "max_abs_adjoint_minus_fd_over_sum_abs_alpha":
                        float(np.max(np.abs(g[slots] - np.array(fd))) / scale),
                    "energy": e}
+    # complex64 against the complex128 path (oracle-pinned at small sizes and,
+    # for expectations, at 24 qubits); the 24-qubit oracle forward alone takes
+    # seconds per gate, so the full gradient is not re-derived on the CPU here
+    scale = sum(abs(c) for c, _ in obs_t)
+    (e64, g64), (e128, g128) = grads["c64"], grads["c128"]
+    out["c64_vs_c128"] = {"energy_error_over_sum_abs_alpha": abs(e64 - e128) / scale,
+                          "grad_max_abs_error_over_sum_abs_alpha":
+                              float(np.max(np.abs(g64 - g128))) / scale,
+                          "bar_over_sum_abs_alpha": 2e-5}
     return out
 
 
@@ -230,6 +315,18 @@ def batch_leg(Q, W, count):
         o = Q.Observable(it["n"], it["obs"])
         circs.append((c, o))
         b.add(c, o, it["theta"])
+    # oracle references for sampled items (one per qubit count): energy and 4
+    # gradient components by the exact two-term shift rule
+    from oracle import oracle as O
+    oracle_refs = {}
+    for nq in sorted({it["n"] for it in items}):
+        i = next(k for k, it in enumerate(items) if it["n"] == nq)
+        it = items[i]
+        npi = len(it["theta"])
+        slots = [0, npi // 3, (2 * npi) // 3, npi - 1]
+        oracle_refs[i] = (O.energy(nq, it["gates"], it["theta"], it["obs"]), slots,
+                          O.param_shift_grad(nq, it["gates"], it["theta"], it["obs"], slots=slots),
+                          sum(abs(c) for c, _ in it["obs"]))
     for dt in ("c64", "c128"):
         shape = b.autotune(dt, reps=1)  # launch shape by measurement (outside the timed runs)
         b.run(dt)  # builds device tables, captures the launch graph
@@ -253,19 +350,63 @@ def batch_leg(Q, W, count):
             e1, g1 = Q.adjoint_gradient(c, items[i]["theta"], o, psi, lam)
             t_pc += time.perf_counter() - t0
         per_item = t_pc / len(sample)
+        # finite differences on the same kernels (fused forward + expectation per
+        # energy), timed on a sample of parameters of the sampled items
+        h = 1e-6 if dt == "c128" else 4e-3
+        fd_t, fd_n = 0.0, 0
+        for i in sample[:8]:
+            n = items[i]["n"]
+            c, o = circs[i]
+            pl = Q.Plan(c, dt, max_k=2)
+            s1 = states[n][0] if n in states else Q.State(n, dt)
+            th = items[i]["theta"]
+            for sl in (0, len(th) // 2):
+                t0 = time.perf_counter()
+                tp, tm = th.copy(), th.copy()
+                tp[sl] += h
+                tm[sl] -= h
+                s1.set_basis(0)
+                Q.apply_fused(s1, pl, tp)
+                ep = Q.expectation(s1, o)
+                s1.set_basis(0)
+                Q.apply_fused(s1, pl, tm)
+                em = Q.expectation(s1, o)
+                fd_t += time.perf_counter() - t0
+                fd_n += 1
+        fd_grads_per_s = fd_n / fd_t
+        # error against the oracle on sampled items (one per qubit count): energy
+        # and 4 gradient components by the exact two-term shift rule
+        e_err, g_err, checked = 0.0, 0.0, []
+        for i, (e_ref, slots, g_ref, scale) in oracle_refs.items():
+            e_err = max(e_err, abs(e[i] - e_ref) / scale)
+            g_err = max(g_err, float(np.max(np.abs(g[i][slots] - g_ref))) / scale)
+            checked.append(i)
         out[dt] = {"batch_s": t_b, "items_per_s": count / t_b, "launch_shape": shape,
                    "grads_per_s": out["params_total"] / t_b,
                    "per_circuit_items_per_s": 1.0 / per_item,
-                   "speedup_vs_per_circuit": (count / t_b) * per_item}
+                   "speedup_vs_per_circuit": (count / t_b) * per_item,
+                   "fd_grads_per_s": fd_grads_per_s, "fd_h": h,
+                   "speedup_vs_fd": (out["params_total"] / t_b) / fd_grads_per_s,
+                   "oracle_check": {"items": checked, "gradient_slots_per_item": 4,
+                                    "energy_error_over_sum_abs_alpha": e_err,
+                                    "grad_max_abs_error_over_sum_abs_alpha": g_err,
+                                    "bar_over_sum_abs_alpha": 1e-10 if dt == "c128" else 2e-5}}
     return out
 
 
-def random_leg(Q, W):
+def random_leg(Q, W, check=True):
     n = 26
     gates = W.random_u_cz(n, 20, seed_key=(1,))
     circ = Q.Circuit.from_records(n, gates)
     out = {"workload": "26 qubits, 20 layers of Haar 1q on every qubit + CZ on a random "
                        "perfect matching (780 gates)"}
+    ref = None
+    if check:
+        # one complex128 oracle run (1 GiB), all host threads
+        from oracle import oracle as O
+        t0 = time.perf_counter()
+        ref = O.run_circuit(n, gates)
+        out["oracle"] = {"s": time.perf_counter() - t0, "threads": int(O.lib().orc_num_threads())}
     for dt in ("c64", "c128"):
         s = Q.State(n, dt)
         plan = Q.Plan(circ, dt, max_k=2)
@@ -281,10 +422,58 @@ def random_leg(Q, W):
             f()
             sync(Q, s)
             t = time.perf_counter() - t0
-            r[mode] = {"s": t, "gates_per_s": len(gates) / t}
+            r[mode] = {"s": t, "gates_per_s": len(gates) / t,
+                       "hbm_gb_per_s_algorithmic":
+                           (2 * (1 << n) * (8 if dt == "c64" else 16) *
+                            (pl.info()["passes"] if pl is not None else 0)) / t / 1e9
+                           if pl is not None else None}
+            if ref is not None:
+                s.set_basis(0)
+                f()
+                mx, rel = state_diff(s.store(), ref)
+                r[mode]["max_abs_error_vs_oracle"] = mx
+                r[mode]["rel_l2_error_vs_oracle"] = rel
         r["passes"] = plan.info()["passes"]
         r["autotune"] = {"choice": tuned.choice, "passes": tuned.info()["passes"], "tuning_s": t_tune}
         out[dt] = r
+    return out
+
+
+def iqp_leg(Q, W, n=30, depth=20):
+    """Commuting circuit (section 6.6: the random circuit with one RZ per qubit
+    per layer, CZ brickwork): light vs heavy (commutation-aware) planning,
+    complex64, with and without the planning time."""
+    gates = W.iqp_rz_cz(n, depth, seed_key=(5,))
+    circ = Q.Circuit.from_records(n, gates)
+    s = Q.State(n, "c64")
+    out = {"workload": f"{n} qubits complex64, {depth + 1} RZ layers on every qubit and {depth} "
+                       f"CZ brickwork layers ({len(gates)} gates, all diagonal)"}
+    for name, heavy in (("light", False), ("heavy", True)):
+        t0 = time.perf_counter()
+        pl = Q.Plan(circ, "c64", max_k=2, heavy=heavy)
+        t_plan = time.perf_counter() - t0
+        s.set_basis(0)
+        Q.apply_fused(s, pl)
+        sync(Q, s)
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            Q.apply_fused(s, pl)
+        sync(Q, s)
+        t = (time.perf_counter() - t0) / reps
+        info = pl.info()
+        out[name] = {"plan_ms": t_plan * 1e3, "blocks": info["blocks"], "passes": info["passes"],
+                     "apply_ms": t * 1e3, "gates_per_s": len(gates) / t,
+                     "gates_per_s_incl_plan": len(gates) / (t + t_plan),
+                     "hbm_gb_per_s_algorithmic": 2 * (1 << n) * 8 * info["passes"] / t / 1e9}
+    s.set_basis(0)
+    Q.apply_fused(s, Q.Plan(circ, "c64", max_k=2, heavy=True))
+    a = s.store()
+    s.set_basis(0)
+    Q.apply_fused(s, Q.Plan(circ, "c64", max_k=2))
+    mx, rel = state_diff(a, s.store())
+    out["heavy_vs_light_max_abs"] = mx
+    out["heavy_vs_light_rel_l2"] = rel
     return out
 
 
@@ -354,6 +543,41 @@ def sample_leg(Q, W, n=30, count=1 << 20):
     return out
 
 
+def small_leg(Q, W, reps=200):
+    """The 10-qubit complex128 layered circuit (290 gates): time per circuit
+    (state reset + circuit, one fused pass) against the paper's ~10 us per GPU
+    call, and the unfused per-gate launches; state and <Z_0> against the oracle."""
+    from oracle import oracle as O
+    n = 10
+    gates = W.layered_rx_rz_cnot(n, 10, seed_key=(0,))
+    circ = Q.Circuit.from_records(n, gates)
+    plan = Q.Plan(circ, "c128", max_k=2)
+    s = Q.State(n, "c128")
+    out = {"workload": "10 qubits complex128, 10 layers RX/RZ on every qubit + CNOT ladder "
+                       f"({len(gates)} gates), from |0..0>", "passes": plan.info()["passes"]}
+    for mode, f, r in (("fused", lambda: Q.apply_fused(s, plan), reps),
+                       ("unfused", lambda: Q.apply_circuit(s, circ), max(1, reps // 10))):
+        s.set_basis(0)
+        f()
+        sync(Q, s)
+        t0 = time.perf_counter()
+        for _ in range(r):
+            s.set_basis(0)
+            f()
+        sync(Q, s)
+        t = (time.perf_counter() - t0) / r
+        out[mode] = {"us_per_circuit": t * 1e6, "gates_per_s": len(gates) / t}
+    s.set_basis(0)
+    Q.apply_fused(s, plan)
+    ref = O.run_circuit(n, gates)
+    z0 = [(1.0, [(0, 3)])]
+    out["max_abs_error_vs_oracle"] = float(np.max(np.abs(s.store() - ref)))
+    out["z0"] = Q.expectation(s, Q.Observable(n, z0))
+    out["z0_error_vs_oracle"] = abs(out["z0"] - O.expectation(ref, z0))
+    out["bar"] = 1e-12
+    return out
+
+
 def autotune_leg(Q, W, n=30):
     """The headline circuit's plan picked by the autotuner vs the default plan."""
     gates = W.layered_rx_rz_cnot(n, 10, seed_key=(2,))
@@ -387,7 +611,8 @@ def main():
                 "batch_vqe": lambda: batch_leg(Q, W, args.batch_items),
                 "random_26q": lambda: random_leg(Q, W), "adjoint_32q": lambda: adjoint32_leg(Q, W),
                 "autotune_30q": lambda: autotune_leg(Q, W), "pauli_30q": lambda: pauli_leg(Q, W),
-                "sample_30q": lambda: sample_leg(Q, W)}
+                "sample_30q": lambda: sample_leg(Q, W), "small_10q": lambda: small_leg(Q, W),
+                "iqp_30q": lambda: iqp_leg(Q, W)}
         print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
         return
 
@@ -484,14 +709,18 @@ def main():
         other.copy_from(state)  # device-to-device copy of 2^n x 8 bytes
         other.norm2()
         del other
+    if not args.quick:
+        out["precision_30q_c128"] = companion_c128(Q, n, circ, obs, obs_terms, state, energy)
     del state
     if not args.quick:
+        out["small_10q"] = small_leg(Q, W)
         out["adjoint_24q"] = adjoint_leg(Q, W, args.fd_params)
         out["batch_vqe"] = batch_leg(Q, W, args.batch_items)
         out["random_26q"] = random_leg(Q, W)
         out["adjoint_32q"] = adjoint32_leg(Q, W)
         out["autotune_30q"] = autotune_leg(Q, W)
         out["pauli_30q"] = pauli_leg(Q, W)
+        out["iqp_30q"] = iqp_leg(Q, W)
         out["sample_30q"] = sample_leg(Q, W)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, gates, args.cpu_seconds)

@@ -230,6 +230,27 @@ int qsv_apply_circuit(qsv_state* s, const qsv_circuit* c, const double* theta);
 int qsv_plan_fused(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qubits,
                    int low_qubits, qsv_plan** out);
 
+/* qsv_plan_fused with options. flags: 0, or QSV_PLAN_HEAVY for the heavy
+ * optimization of section 5.4: every gate carries, per qubit it touches, the
+ * Paulis it commutes with there (CNOT: Z on the control, X on the target;
+ * diagonal gates: Z; RX/RY/RZ and Pauli rotations: their Pauli; fixed
+ * matrices: tested on the matrix), and a gate joins an earlier block that it
+ * can be moved next to by passing blocks it commutes with (a shared commuting
+ * Pauli on every common qubit), within the same size and arithmetic rules.
+ * Planning takes longer (each gate may scan back over all blocks); circuits
+ * of commuting gates compress to constant depth. Errors as qsv_plan_fused,
+ * plus QSV_EINVAL for unknown flags. */
+#define QSV_PLAN_HEAVY 1
+
+/* Commutation information of gate `gate` of a circuit on `qubit` (section 5.4:
+ * each gate keeps, per qubit, the Pauli bases it commutes with): *paulis
+ * receives bit 0 if the gate commutes with X on that qubit, bit 1 for Y, bit 2
+ * for Z (7 on qubits the gate does not touch). Errors: QSV_EINVAL (null
+ * argument), QSV_ERANGE (gate or qubit out of range). */
+int qsv_circuit_commute(const qsv_circuit* c, int gate, int qubit, int* paulis);
+int qsv_plan_fused_ex(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qubits,
+                      int low_qubits, int flags, qsv_plan** out);
+
 /* Autotuned plan (section 5.4: the fusion width is a tuning choice): builds
  * candidate plans over fusion widths max_k = 1, 2, 3 and tile shapes
  * (tile qubits, thread bits) = (12, 8), (11, 7) and, for complex64, (13, 9)

@@ -56,6 +56,8 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
+        L.orc_set_num_threads.restype = ctypes.c_int
         L.orc_set_basis.argtypes = [dp, ctypes.c_int, ctypes.c_uint64]
         L.orc_apply_matrix.argtypes = [dp, ctypes.c_int, dp, ip, ctypes.c_int, ip, ip, ctypes.c_int]
         L.orc_apply_matrix.restype = ctypes.c_int

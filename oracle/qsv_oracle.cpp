@@ -46,6 +46,18 @@ int orc_num_threads(void) {
 #endif
 }
 
+// Sets the number of threads of the parallel B0 loop (timing at one thread and
+// at all cores); returns the new count. No effect on any result.
+int orc_set_num_threads(int t) {
+#ifdef _OPENMP
+  if (t > 0) omp_set_num_threads(t);
+  return omp_get_max_threads();
+#else
+  (void)t;
+  return 1;
+#endif
+}
+
 // |k> : all amplitudes zero except amplitude k, which is one (section 4.2.1).
 void orc_set_basis(double* psi, int n, uint64_t k) {
   const uint64_t N = uint64_t(1) << n;

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libqsv.so")
 
 QSV_C64 = 1
 QSV_C128 = 2
+QSV_PLAN_HEAVY = 1
 GATE = {"x": 1, "y": 2, "z": 3, "h": 4, "rx": 5, "ry": 6, "rz": 7, "cnot": 8, "cz": 9, "swap": 10}
 PAULI_ID = {"rx": 1, "ry": 2, "rz": 3}
 
@@ -65,6 +66,9 @@ _SIGS = {
     "qsv_circuit_info": (_c.c_int, [_vp, _ip, _ip, _ip]),
     "qsv_apply_circuit": (_c.c_int, [_vp, _vp, _dp]),
     "qsv_plan_fused": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.POINTER(_vp)]),
+    "qsv_circuit_commute": (_c.c_int, [_vp, _c.c_int, _c.c_int, _ip]),
+    "qsv_plan_fused_ex": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int,
+                                     _c.POINTER(_vp)]),
     "qsv_plan_autotune": (_c.c_int, [_vp, _vp, _dp, _c.c_int, _c.POINTER(_vp), _ip]),
     "qsv_plan_info": (_c.c_int, [_vp, _ip, _ip, _ip]),
     "qsv_plan_free": (_c.c_int, [_vp]),
@@ -340,6 +344,12 @@ class Circuit:
         else:
             raise ValueError(op)
 
+    def commute(self, gate: int, qubit: int) -> int:
+        """Paulis gate `gate` commutes with on `qubit` (bit 0 X, 1 Y, 2 Z)."""
+        m = _c.c_int()
+        check(lib().qsv_circuit_commute(self.h, gate, qubit, _c.byref(m)))
+        return m.value
+
     def info(self):
         n, g, p = _c.c_int(), _c.c_int(), _c.c_int()
         check(lib().qsv_circuit_info(self.h, _c.byref(n), _c.byref(g), _c.byref(p)))
@@ -372,10 +382,11 @@ class Plan:
     """Fused execution plan (qsv_plan) of a circuit for one dtype."""
 
     def __init__(self, circ: Circuit, dtype: str = "c128", max_k: int = 2, tile_qubits: int = 0,
-                 low_qubits: int = 0):
+                 low_qubits: int = 0, heavy: bool = False):
         h = _vp()
-        check(lib().qsv_plan_fused(circ.h, QSV_C64 if dtype == "c64" else QSV_C128, max_k,
-                                   tile_qubits, low_qubits, _c.byref(h)))
+        check(lib().qsv_plan_fused_ex(circ.h, QSV_C64 if dtype == "c64" else QSV_C128, max_k,
+                                      tile_qubits, low_qubits, QSV_PLAN_HEAVY if heavy else 0,
+                                      _c.byref(h)))
         self.h = h
         self.dtype = dtype
 

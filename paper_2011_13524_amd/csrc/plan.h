@@ -139,6 +139,7 @@ struct qsv_plan {
   int n = 0;
   qsv_dtype dtype = QSV_C128;
   int max_k = 2;
+  bool heavy = false;  // commutation-aware merging (QSV_PLAN_HEAVY)
   int L = 12, b = 5;
   const qsv_circuit* circ = nullptr;  // borrowed structure snapshot below
   qsv_circuit circ_copy;

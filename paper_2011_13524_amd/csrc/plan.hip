@@ -15,6 +15,17 @@
 //     diagonal or exchange block only on a subset of its own qubits. Block
 //     matrices are products K_later K_earlier on the ascending union of
 //     qubits.
+//     Heavy mode (section 5.4, the heavy optimization): every gate carries,
+//     per qubit it touches, the set of Paulis it commutes with there (a CNOT
+//     commutes with Z on its control and X on its target; a diagonal gate
+//     with Z on every qubit; RX/RY/RZ with X/Y/Z). A gate may then join an
+//     earlier block that is not its immediate predecessor: walking back from
+//     the newest block, it moves past every block with which it shares, on
+//     each common qubit, a commuting Pauli (such a block and the gate are
+//     then both block-diagonal in that Pauli's eigenbasis on every shared
+//     qubit, so they commute), and joins the first block sharing a qubit
+//     where the merge rules above allow it. On circuits whose gates all
+//     commute (diagonal layers) this compresses the depth to a constant.
 //  3. Passes: a pass fixes a set of L local qubits (always including the low b
 //     qubits, so that each run of 2^b amplitudes is contiguous in HBM) and
 //     greedily takes, in order, every block whose non-diagonal targets are
@@ -196,6 +207,51 @@ void matmul(const std::vector<cd>& a, const std::vector<cd>& b, int D, std::vect
     }
 }
 
+// Paulis (bit 0: X, bit 1: Y, bit 2: Z) commuting with the gate on each of
+// its qubits; 7 on qubits it does not touch. Rotations exp(i t P / 2) commute
+// with P on their target(s) for every angle; fixed matrices are tested on
+// their full matrix over targets and controls.
+std::vector<uint8_t> commute_masks(const Gate& g, const GateInfo& gi, int n) {
+  std::vector<uint8_t> m(size_t(n), 7);
+  if (g.kind == Gate::ROTATION) {
+    m[size_t(g.targets[0])] = uint8_t(1u << (g.pauli - 1));
+    return m;
+  }
+  if (g.kind == Gate::PAULI) {
+    for (size_t j = 0; j < g.targets.size(); ++j) m[size_t(g.targets[j])] = uint8_t(1u << (g.paulis[j] - 1));
+    return m;
+  }
+  const std::vector<int> qs = mask_list(gi.qubits);
+  std::vector<cd> M;
+  embed(gi.mat, gi, qs, M);
+  const int D = 1 << qs.size();
+  double big = 0.0;
+  for (const cd& z : M) big = std::max(big, std::fabs(z.re) + std::fabs(z.im));
+  const double tol = 1e-12 * std::max(big, 1.0);
+  auto close = [tol](cd a, cd b) { return std::fabs(a.re - b.re) + std::fabs(a.im - b.im) <= tol; };
+  for (size_t j = 0; j < qs.size(); ++j) {
+    const int bit = 1 << j;
+    bool cx = true, cy = true, cz = true;
+    for (int r = 0; r < D; ++r)
+      for (int c = 0; c < D; ++c) {
+        const cd v = M[size_t(r) * D + c];
+        // Z_j M = M Z_j: no element between rows and columns whose bit j differs
+        if (((r ^ c) & bit) && !close(v, cd{0, 0})) cz = false;
+        // X_j M = M X_j: M[r ^ bit][c] = M[r][c ^ bit]
+        if (!close(M[size_t(r ^ bit) * D + c], M[size_t(r) * D + (c ^ bit)])) cx = false;
+        // Y_j M = M Y_j with Y|0> = i|1>, Y|1> = -i|0>:
+        //   (Y M)[r][c] = (bit of r ? i : -i) M[r ^ bit][c]
+        //   (M Y)[r][c] = (bit of c ? -i : i) M[r][c ^ bit]
+        const cd a = M[size_t(r ^ bit) * D + c], b = M[size_t(r) * D + (c ^ bit)];
+        const cd ya = (r & bit) ? cd{-a.im, a.re} : cd{a.im, -a.re};
+        const cd yb = (c & bit) ? cd{b.im, -b.re} : cd{-b.im, b.re};
+        if (!close(ya, yb)) cy = false;
+      }
+    m[size_t(qs[j])] = uint8_t((cx ? 1 : 0) | (cy ? 2 : 0) | (cz ? 4 : 0));
+  }
+  return m;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ host: planning
@@ -212,42 +268,64 @@ static int build_plan(qsv_plan* p) {
   std::vector<uint64_t> bq;  // qubit masks of blocks
   std::vector<char> bx;      // block is a single exchange gate
   std::vector<int> last(n, -1);
+  std::vector<std::vector<uint8_t>> bcm;  // heavy: per block, commuting Paulis per qubit
+  // merge rule for gate I joining block j (arithmetic per amplitude never rises)
+  auto merge_ok = [&](int j, const GateInfo& I) {
+    const Block& B = blocks[size_t(j)];
+    const uint64_t uni = bq[size_t(j)] | I.qubits;
+    const int ku = __builtin_popcountll(uni);
+    const bool cheap_b = B.diagonal || bx[size_t(j)], cheap_i = I.diagonal || I.exchange;
+    if (B.diagonal && I.diagonal) return ku <= 2;  // diagonal blocks stay register-friendly
+    if (cheap_b && cheap_i) return false;          // the product would be dense: costlier
+    if (cheap_i) return (I.qubits & ~bq[size_t(j)]) == 0;
+    if (cheap_b) return (bq[size_t(j)] & ~I.qubits) == 0 && ku <= std::max(p->max_k, 1);
+    return ku <= p->max_k;
+  };
   for (size_t gi = 0; gi < C.gates.size(); ++gi) {
     const GateInfo& I = info[gi];
-    int cand = -2;
-    for (int q : mask_list(I.qubits)) {
-      if (last[q] < 0) continue;
-      if (cand == -2) cand = last[q];
-      else if (cand != last[q]) cand = -1;
-    }
-    bool merged = false;
-    if (cand >= 0) {
-      Block& B = blocks[cand];
-      const uint64_t uni = bq[cand] | I.qubits;
-      const int ku = __builtin_popcountll(uni);
-      const bool cheap_b = B.diagonal || bx[cand], cheap_i = I.diagonal || I.exchange;
-      bool ok = false;
-      if (B.diagonal && I.diagonal) ok = ku <= 2;  // diagonal blocks stay register-friendly
-      else if (cheap_b && cheap_i) ok = false;     // the product would be dense: costlier
-      else if (cheap_i) ok = (I.qubits & ~bq[cand]) == 0;
-      else if (cheap_b) ok = (bq[cand] & ~I.qubits) == 0 && ku <= std::max(p->max_k, 1);
-      else ok = ku <= p->max_k;
-      if (ok) {
-        B.gates.push_back(int(gi));
-        bq[cand] = uni;
-        bx[cand] = 0;
-        B.diagonal = B.diagonal && I.diagonal;
-        merged = true;
-        for (int q : mask_list(I.qubits)) last[q] = cand;
+    std::vector<uint8_t> gcm;
+    int target = -1;
+    if (p->heavy) {
+      gcm = commute_masks(C.gates[gi], I, n);
+      for (int j = int(blocks.size()) - 1; j >= 0; --j) {
+        const uint64_t shared = bq[size_t(j)] & I.qubits;
+        if (!shared) continue;
+        if (merge_ok(j, I)) {
+          target = j;
+          break;
+        }
+        bool passes = true;  // the gate commutes with block j: move it further back
+        for (int q : mask_list(shared))
+          if (!(bcm[size_t(j)][size_t(q)] & gcm[size_t(q)])) passes = false;
+        if (!passes) break;
       }
+    } else {
+      int cand = -2;
+      for (int q : mask_list(I.qubits)) {
+        if (last[q] < 0) continue;
+        if (cand == -2) cand = last[q];
+        else if (cand != last[q]) cand = -1;
+      }
+      if (cand >= 0 && merge_ok(cand, I)) target = cand;
     }
-    if (!merged) {
+    if (target >= 0) {
+      Block& B = blocks[size_t(target)];
+      B.gates.push_back(int(gi));
+      bq[size_t(target)] |= I.qubits;
+      bx[size_t(target)] = 0;
+      B.diagonal = B.diagonal && I.diagonal;
+      for (int q : mask_list(I.qubits)) {
+        last[q] = std::max(last[q], target);
+        if (p->heavy) bcm[size_t(target)][size_t(q)] &= gcm[size_t(q)];
+      }
+    } else {
       Block B;
       B.gates = {int(gi)};
       B.diagonal = I.diagonal;
       blocks.push_back(B);
       bq.push_back(I.qubits);
       bx.push_back(I.exchange ? 1 : 0);
+      if (p->heavy) bcm.push_back(gcm);
       for (int q : mask_list(I.qubits)) last[q] = int(blocks.size()) - 1;
     }
   }
@@ -972,7 +1050,7 @@ static void plan_release(qsv_plan* p) {
 // Plan with an explicit register tile shape (thread bits TB); tile_qubits /
 // low_qubits 0 select the defaults.
 static int plan_create(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qubits, int low_qubits,
-                       int TB, qsv_plan** out) {
+                       int TB, qsv_plan** out, bool heavy = false) {
   *out = nullptr;
   const int n = c->n;
   int L = tile_qubits > 0 ? tile_qubits : 12;
@@ -991,6 +1069,7 @@ static int plan_create(const qsv_circuit* c, qsv_dtype dtype, int max_k, int til
   p->n = n;
   p->dtype = dtype;
   p->max_k = max_k;
+  p->heavy = heavy;
   p->L = L;
   p->b = b;
   // (blocks of 4-5 qubits run through LDS with 32-amplitude temporaries: the
@@ -1023,12 +1102,18 @@ extern "C" {
 
 int qsv_plan_fused(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qubits, int low_qubits,
                    qsv_plan** out) {
+  return qsv_plan_fused_ex(c, dtype, max_k, tile_qubits, low_qubits, 0, out);
+}
+
+int qsv_plan_fused_ex(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qubits, int low_qubits,
+                      int flags, qsv_plan** out) {
   clear_error();
   if (!out) return fail(QSV_EINVAL, "null output handle");
   *out = nullptr;
   if (!c) return fail(QSV_EINVAL, "null circuit");
   if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_EDTYPE, "unknown dtype");
   if (max_k < 1 || max_k > 5) return fail(QSV_EINVAL, "max_k must be in 1..5");
+  if (flags & ~QSV_PLAN_HEAVY) return fail(QSV_EINVAL, "unknown plan flags 0x%x", unsigned(flags));
   // default tile: 2^12 amplitudes over 256 threads (TB = 8) x 16 in registers:
   // measured on MI355X, 2^12-amplitude tiles with 256 threads beat 2^13 with
   // 512 threads (6% at 30 qubits complex64, more workgroups in flight per
@@ -1042,7 +1127,7 @@ int qsv_plan_fused(const qsv_circuit* c, qsv_dtype dtype, int max_k, int tile_qu
     const int v = std::atoi(e);
     TB = v == 9 ? 9 : (v == 7 ? 7 : 8);
   }
-  return plan_create(c, dtype, max_k, L, low_qubits, TB, out);
+  return plan_create(c, dtype, max_k, L, low_qubits, TB, out, (flags & QSV_PLAN_HEAVY) != 0);
 }
 
 int qsv_plan_autotune(const qsv_circuit* c, qsv_state* scratch, const double* theta, int reps,
@@ -1113,6 +1198,16 @@ int qsv_plan_autotune(const qsv_circuit* c, qsv_state* scratch, const double* th
     choice[3] = best->reg_bits;
   }
   *out = best;
+  return QSV_OK;
+}
+
+int qsv_circuit_commute(const qsv_circuit* c, int gate, int qubit, int* paulis) {
+  clear_error();
+  if (!c || !paulis) return fail(QSV_EINVAL, "null argument");
+  if (gate < 0 || gate >= int(c->gates.size())) return fail(QSV_ERANGE, "gate index %d out of range", gate);
+  if (qubit < 0 || qubit >= c->n) return fail(QSV_ERANGE, "qubit %d out of range", qubit);
+  const Gate& g = c->gates[size_t(gate)];
+  *paulis = commute_masks(g, analyse(g), c->n)[size_t(qubit)];
   return QSV_OK;
 }
 

@@ -35,6 +35,8 @@ same structure):
                       every qubit and a CZ ladder (batched VQE items).
   ry_rz_cnot_ring     layers of parametric RY, RZ on every qubit and a CNOT ring
                       (i -> i+1 mod n) (24-qubit adjoint workload).
+  iqp_rz_cz           RZ layers and CZ brickwork only: every gate commutes
+                      (section 6.6, circuits dominated by commuting gates).
 """
 from __future__ import annotations
 
@@ -84,6 +86,24 @@ def random_u_cz(n: int, layers: int, seed_key=(1,)):
         perm = rng.permutation(n)
         for j in range(n // 2):
             gates.append({"op": "cz", "q": [int(perm[2 * j]), int(perm[2 * j + 1])]})
+    return gates
+
+
+def iqp_rz_cz(n: int, depth: int, seed_key=(5,)):
+    """Commuting (IQP-like) circuit: depth + 1 layers of RZ with uniform angles
+    on every qubit, separated by depth brickwork layers of CZ(i, i+1) (even i
+    in even layers, odd i in odd ones): the random circuit of section 6.6 with
+    each qubit's three rotations replaced by one RZ, so that every gate is
+    diagonal."""
+    rng = rng_for(*seed_key)
+    gates = []
+    for layer in range(depth + 1):
+        for q in range(n):
+            gates.append({"op": "rz", "q": [q], "angle": float(rng.uniform(0.0, TWO_PI))})
+        if layer == depth:
+            break
+        for q in range(layer % 2, n - 1, 2):
+            gates.append({"op": "cz", "q": [q, q + 1]})
     return gates
 
 

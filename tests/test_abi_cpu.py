@@ -175,6 +175,73 @@ def test_merge_never_raises_arithmetic():
     assert blocks([U, U01], k=1) == 2
 
 
+X_, Y_, Z_ = 1, 2, 4
+
+
+def test_commute_metadata():
+    # per-qubit commuting Paulis (section 5.4): pinned by the algebra of each
+    # gate (a controlled gate is diagonal on its control; X-type targets
+    # commute with X; H and SWAP with none of X, Y, Z on a single qubit)
+    rng = np.random.default_rng(8)
+    u = W.haar_unitary(rng, 2)
+    recs = [{"op": "cnot", "q": [0, 1]}, {"op": "cz", "q": [1, 2]}, {"op": "h", "q": [0]},
+            {"op": "swap", "q": [0, 2]}, {"op": "rx", "q": [1], "slot": 0},
+            {"op": "ry", "q": [2], "slot": 1}, {"op": "rz", "q": [0], "angle": 0.4},
+            {"op": "x", "q": [1]}, {"op": "y", "q": [1]}, {"op": "z", "q": [1]},
+            {"op": "dense", "q": [0, 1], "mat": np.kron(np.eye(2), u)},
+            {"op": "dense", "q": [1, 0], "mat": np.array([[1, 0, 0, 0], [0, 1, 0, 0],
+                                                          [0, 0, 0, 1], [0, 0, 1, 0]])},
+            {"op": "dense", "q": [2], "mat": Q.binding.np.array(
+                [[np.cos(0.3), 1j * np.sin(0.3)], [1j * np.sin(0.3), np.cos(0.3)]]),
+             "controls": [0], "ctrl_vals": [0]},
+            {"op": "pauli_rot", "q": [0, 2], "paulis": [1, 3], "angle": 0.7}]
+    c = Q.Circuit.from_records(3, recs)
+    want = [(Z_, X_, 7), (7, Z_, Z_), (0, 7, 7), (0, 7, 0), (7, X_, 7), (7, 7, Y_), (Z_, 7, 7),
+            (7, X_, 7), (7, Y_, 7), (7, Z_, 7),
+            (0, 7, 7),            # kron(I, u): u on qubit 0 (bit 0 <-> q[0]), identity on 1
+            (Z_, X_, 7),          # App. A matrix on targets [1, 0]: CNOT control 0, target 1
+            (Z_, 7, X_),          # X rotation on 2 controlled by qubit 0
+            (X_, 7, Z_)]
+    for gi, w in enumerate(want):
+        got = tuple(c.commute(gi, q) for q in range(3))
+        assert got == w, (gi, recs[gi]["op"], got, w)
+    assert _code(c.commute, len(recs), 0) == ERANGE
+    assert _code(c.commute, 0, 3) == ERANGE
+
+
+def test_heavy_merge_on_host():
+    def blocks(n, recs, heavy, k=2):
+        return Q.Plan(Q.Circuit.from_records(n, recs), "c128", max_k=k, heavy=heavy).info()["blocks"]
+
+    rz0 = {"op": "rz", "q": [0], "angle": 0.3}
+    rx0 = {"op": "rx", "q": [0], "angle": 0.3}
+    rx1 = {"op": "rx", "q": [1], "angle": 0.3}
+    cx = {"op": "cnot", "q": [0, 1]}
+    h0 = {"op": "h", "q": [0]}
+    cz = {"op": "cz", "q": [0, 1]}
+    # a Z rotation passes the CNOT's control, an X rotation its target
+    assert (blocks(2, [rz0, cx, rz0], False), blocks(2, [rz0, cx, rz0], True)) == (3, 2)
+    assert (blocks(2, [rx1, cx, rx1], False), blocks(2, [rx1, cx, rx1], True)) == (3, 2)
+    # ... but not the other way round, and nothing passes H (no shared Pauli)
+    assert blocks(2, [rx0, cx, rx0], True) == 3
+    assert blocks(2, [h0, cz, h0], True) == 3
+    # commuting (IQP-like) circuits compress to constant depth: the block count
+    # no longer grows with the number of layers
+    n = 16
+    for depth in (4, 16):
+        g = W.iqp_rz_cz(n, depth, seed_key=(5, depth))
+        light, heavy = blocks(n, g, False), blocks(n, g, True)
+        assert heavy <= 2 * n, (depth, heavy)
+        assert light >= depth * (n - 1) // 2, (depth, light)
+    # on the headline circuit heavy planning never needs more blocks
+    g = W.layered_rx_rz_cnot(12, 4, seed_key=(2,))
+    assert blocks(12, g, True) <= blocks(12, g, False)
+    with pytest.raises(Q.QsvError):
+        Q.lib()  # (library loaded)
+        B.check(Q.lib().qsv_plan_fused_ex(Q.Circuit.from_records(2, [cx]).h, 2, 2, 0, 0, 2,
+                                          ctypes.byref(ctypes.c_void_p())))
+
+
 def test_batch_validation():
     b = Q.Batch()
     c = Q.Circuit(3)

@@ -237,3 +237,54 @@ def test_one_qubit_ops_matrix_cores_and_vector_alu(mfma, tb, tile, monkeypatch):
     assert info["segments"] > 0
     ref = O.run_circuit(n, gates)
     assert np.max(np.abs(got - ref)) <= AMP_TOL["c64"], info
+
+
+def commuting_mix(n, count, seed):
+    """Random gates rich in commuting pairs (rotations about Z and X, CNOT and
+    CZ on few qubits, some H), so heavy planning moves gates past others."""
+    rng = np.random.default_rng(seed)
+    g = []
+    for _ in range(count):
+        r = int(rng.integers(0, 7))
+        a, b = (int(q) for q in rng.choice(min(n, 5), size=2, replace=False))
+        t = float(rng.uniform(0, 6.3))
+        if r == 0:
+            g.append({"op": "rz", "q": [a], "angle": t})
+        elif r == 1:
+            g.append({"op": "rx", "q": [a], "angle": t})
+        elif r == 2:
+            g.append({"op": "cnot", "q": [a, b]})
+        elif r == 3:
+            g.append({"op": "cz", "q": [a, b]})
+        elif r == 4:
+            g.append({"op": "dense", "q": [a, b], "mat": np.diag(np.exp(1j * rng.uniform(0, 6, 4)))})
+        elif r == 5:
+            g.append({"op": "ry", "q": [a], "angle": t})
+        else:
+            g.append({"op": "h", "q": [int(rng.integers(0, n))]})
+    return g
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("kw", [dict(max_k=2), dict(max_k=3), dict(max_k=2, tile_qubits=6, low_qubits=2),
+                                dict(max_k=4, tile_qubits=8, low_qubits=3)])
+def test_heavy_plans_match_oracle(dt, kw):
+    # commutation-aware merging (section 5.4) is an exact rewrite: the fused
+    # state equals the unfused oracle state up to rounding
+    cases = [(12, commuting_mix(12, 300, 31)), (13, mixed_circuit(13, 200, 32)),
+             (16, W.iqp_rz_cz(16, 12, seed_key=(5, 16))),
+             (14, W.layered_rx_rz_cnot(14, 6, seed_key=(2, 14)))]
+    for n, gates in cases:
+        got, info = fused_state(n, gates, dt, heavy=True, **kw)
+        ref = O.run_circuit(n, gates)
+        assert np.max(np.abs(got - ref)) <= AMP_TOL[dt], (n, kw, info)
+
+
+def test_heavy_compresses_commuting_circuit():
+    n = 16
+    gates = W.iqp_rz_cz(n, 20, seed_key=(5, 20))
+    light = fused_state(n, gates, "c64", max_k=2)
+    heavy = fused_state(n, gates, "c64", max_k=2, heavy=True)
+    assert heavy[1]["blocks"] <= 2 * n < light[1]["blocks"]
+    assert np.max(np.abs(heavy[0] - light[0])) <= 2e-6
+    assert np.max(np.abs(heavy[0] - O.run_circuit(n, gates))) <= AMP_TOL["c64"]
