@@ -121,11 +121,18 @@ int qsv_copy(qsv_state* dst, const qsv_state* src);
 /* Apply a basic gate psi <- K psi (section 4.3.2, Eq. update_mat) with gate
  * matrix mat (2^k x 2^k, see conventions) on targets[0..k-1], acting only on
  * the amplitudes whose control qubits controls[i] hold ctrl_vals[i] in {0, 1}
- * (controlled gates, section 4.3.2). 1 <= k <= 5; targets and controls
+ * (controlled gates, section 4.3.2). 1 <= k <= 10; targets and controls
  * distinct and in [0, n). K need not be unitary. The library recognises the
  * structured matrices the paper lists (diagonal, Pauli-X / CNOT / SWAP
  * permutations, one-entry phases such as Z or CZ) and applies them with fewer
- * memory operations. controls / ctrl_vals may be NULL when nc == 0. */
+ * memory operations. k <= 5 runs on register-resident kernels; 6 <= k <= 10
+ * on the generic path (the 2^k-amplitude temporal vector of one B0 element in
+ * LDS, as section 5.5 does for wide gates; the matrix is kept in FP64 in a
+ * per-state device buffer, grown on first use, so such a call may allocate
+ * and synchronises the state's stream once to stage the matrix). Circuits and
+ * fused plans take gates of at most 5 targets. controls / ctrl_vals may be
+ * NULL when nc == 0. Errors: QSV_EINVAL (k outside 1..10, bad control
+ * values), QSV_ERANGE / QSV_EDUP (qubits), QSV_ENOMEM (matrix buffer). */
 int qsv_apply_gate(qsv_state* s, const double* mat, const int* targets, int k,
                    const int* controls, const int* ctrl_vals, int nc);
 

@@ -231,6 +231,56 @@ __global__ void __launch_bounds__(256) k_dense(R* __restrict__ psi, const cx<R>*
   }
 }
 
+// Dense gate on K = 6..10 targets (section 4.3.2 for any number of targets;
+// the temporal vector of 2^K amplitudes sits in shared memory, as section 5.5
+// does for wide gates). One workgroup per B0 element x0 (grid-stride over
+// them): the 2^K amplitudes x0 + s(c) are gathered into LDS in FP64, then
+// thread r forms output r = sum_c M[r][c] v[c] from the matrix stored
+// transposed (mt[c * 2^K + r]: the lanes of a wavefront read consecutive
+// entries) and writes it to x0 + s(r). Every read of the group comes from LDS,
+// so the writes need no further ordering.
+struct DenseBigArgs {
+  uint64_t ngroups;
+  uint64_t or_mask;
+  int k;
+  int tq[10];
+  int m;
+  int pos[kMaxPos];
+};
+
+__device__ __forceinline__ uint64_t spread_bits(uint32_t c, const int* tq, int k) {
+  uint64_t o = 0;
+  for (int j = 0; j < k; ++j) o |= uint64_t((c >> j) & 1) << tq[j];
+  return o;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_dense_big(R* __restrict__ psi, const cd* __restrict__ mt,
+                                                   const DenseBigArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  cx<double>* v = reinterpret_cast<cx<double>*>(smem);
+  const int D = 1 << a.k;
+  for (uint64_t grp = blockIdx.x; grp < a.ngroups; grp += gridDim.x) {
+    const uint64_t x0 = insert_zeros(grp, a.pos, a.m) | a.or_mask;
+    __syncthreads();  // the previous group's LDS reads are done
+    for (int c = threadIdx.x; c < D; c += blockDim.x) {
+      const cx<R> x = load1(psi, x0 + spread_bits(uint32_t(c), a.tq, a.k));
+      v[c] = {double(x.re), double(x.im)};
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < D; r += blockDim.x) {
+      double ar = 0.0, ai = 0.0;
+      for (int c = 0; c < D; ++c) {
+        const cd m = mt[size_t(c) * D + r];
+        const cx<double> x = v[c];
+        ar = fma(m.re, x.re, fma(-m.im, x.im, ar));
+        ai = fma(m.re, x.im, fma(m.im, x.re, ai));
+      }
+      store1(psi, x0 + spread_bits(uint32_t(r), a.tq, a.k), cx<R>{R(ar), R(ai)});
+    }
+  }
+}
+
 // ------------------------------------------------------------------ host side
 
 namespace {
@@ -478,8 +528,53 @@ int launch_dense_k(qsv_state* s, const cd* mat, const int* targets, uint64_t cma
 }
 
 template <typename R>
+int launch_dense_big(qsv_state* s, const cd* mat, const int* targets, int k, uint64_t cmask,
+                     uint64_t cval) {
+  const int D = 1 << k;
+  DenseBigArgs a{};
+  a.k = k;
+  uint64_t ins = cmask;
+  for (int j = 0; j < k; ++j) {
+    a.tq[j] = targets[j];
+    ins |= uint64_t(1) << targets[j];
+  }
+  InsertPos ip;
+  sort_positions(ins, &ip);
+  a.m = ip.m;
+  for (int j = 0; j < ip.m; ++j) a.pos[j] = ip.pos[j];
+  a.or_mask = cval;
+  a.ngroups = uint64_t(1) << (s->n - ip.m);
+  std::vector<cd> mt(size_t(D) * D);
+  for (int r = 0; r < D; ++r)
+    for (int c = 0; c < D; ++c) mt[size_t(c) * D + r] = mat[size_t(r) * D + c];
+  const size_t bytes = mt.size() * sizeof(cd);
+  if (s->big_cap < bytes) {
+    QSV_HIP_CHECK(hipStreamSynchronize(s->stream));  // earlier gates may still read it
+    if (s->big) (void)hipFree(s->big);
+    s->big = nullptr;
+    s->big_cap = 0;
+    if (hipMalloc(&s->big, bytes) != hipSuccess) {
+      s->big = nullptr;
+      return fail(QSV_ENOMEM, "dense gate matrix (%zu bytes) allocation failed", bytes);
+    }
+    s->big_cap = bytes;
+  }
+  // stream-ordered after the kernels that read the previous matrix; the host
+  // copy must outlive the transfer, so wait for it
+  QSV_HIP_CHECK(hipMemcpyAsync(s->big, mt.data(), bytes, hipMemcpyHostToDevice, s->stream));
+  QSV_HIP_CHECK(hipStreamSynchronize(s->stream));
+  const unsigned grid = unsigned(std::min<uint64_t>(a.ngroups, 4096));
+  ProfScope ps("dense", 2.0 * sizeof(R) * 2 * double(a.ngroups) * D, s->stream);
+  hipLaunchKernelGGL(k_dense_big<R>, dim3(grid), dim3(256), size_t(D) * sizeof(cx<double>), s->stream,
+                     static_cast<R*>(s->ptr), static_cast<const cd*>(s->big), a);
+  QSV_HIP_CHECK(hipGetLastError());
+  return QSV_OK;
+}
+
+template <typename R>
 int launch_dense(qsv_state* s, const cd* mat, const int* targets, int k, uint64_t cmask,
                  uint64_t cval) {
+  if (k >= 6) return launch_dense_big<R>(s, mat, targets, k, cmask, cval);
   switch (k) {
     case 2: return launch_dense_k<R, 2>(s, mat, targets, cmask, cval);
     case 3: return launch_dense_k<R, 3>(s, mat, targets, cmask, cval);
@@ -584,7 +679,7 @@ int apply_gate_impl(qsv_state* s, const cd* mat_in, const int* targets, int k, c
       return launch_pair(s, cmask | b0 | b1, cval, b0, b1, id, PK_SWAP);
     }
   }
-  if (diag) {
+  if (diag && k <= 5) {
     std::vector<cd> d(D);
     for (int i = 0; i < D; ++i) d[i] = mat[i * D + i];
     return s->dtype == QSV_C64 ? launch_diag_t<float>(s, d.data(), tq.data(), k, cmask, cval)
@@ -658,7 +753,7 @@ int qsv_apply_gate(qsv_state* s, const double* mat, const int* targets, int k, c
   int rc = check_state(s);
   if (rc) return rc;
   if (!mat) return fail(QSV_EINVAL, "null matrix");
-  if ((rc = validate_gate(s->n, targets, k, controls, ctrl_vals, nc, 5))) return rc;
+  if ((rc = validate_gate(s->n, targets, k, controls, ctrl_vals, nc, 10))) return rc;
   return apply_gate_impl(s, reinterpret_cast<const cd*>(mat), targets, k, controls, ctrl_vals, nc);
 }
 

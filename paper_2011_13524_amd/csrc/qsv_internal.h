@@ -76,6 +76,9 @@ struct qsv_state {
   double* red = nullptr;
   double* red_host = nullptr;  // pinned
   size_t red_cap = 0;
+  // matrix of a dense gate on 6..10 targets (FP64, transposed), grown on use
+  void* big = nullptr;
+  size_t big_cap = 0;
 };
 
 namespace qsv {

@@ -230,6 +230,7 @@ int qsv_state_free(qsv_state* s) {
   if (s->owned && s->ptr) (void)hipFree(s->ptr);
   if (s->red) (void)hipFree(s->red);
   if (s->red_host) (void)hipHostFree(s->red_host);
+  if (s->big) (void)hipFree(s->big);
   delete s;
   return QSV_OK;
 }

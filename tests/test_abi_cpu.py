@@ -103,6 +103,8 @@ def test_validation_before_any_launch_on_wrapped_memory():
     assert _code(s.apply_gate, np.eye(2), [4]) == ERANGE
     assert _code(s.apply_gate, np.eye(4), [2, 2]) == EDUP
     assert _code(s.apply_gate, np.eye(2), [0], [1], [3]) == EINVAL
+    assert L.qsv_apply_gate(s.h, np.eye(2).ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            (ctypes.c_int * 11)(*range(11)), 11, None, None, 0) == EINVAL
     assert _code(s.apply_named, "cnot", [1]) == EINVAL
     assert _code(s.set_basis, 16) == ERANGE
     h2 = ctypes.c_void_p()

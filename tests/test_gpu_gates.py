@@ -149,6 +149,39 @@ def test_dense_k(dt, k):
 
 
 @pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("k", [6, 7, 8, 10])
+def test_dense_wide_k(dt, k):
+    # the generic path (6 <= k <= 10 targets, temporal vector in LDS):
+    # non-unitary, non-symmetric matrices (a transposed or conjugated operand
+    # fails), targets in random order, with and without controls of either
+    # value, several B0 groups and a ragged last grid stride
+    rng = np.random.default_rng(40 + k)
+    for n in (k, k + 2, 13):
+        psi = rand_state(rng, n)
+        qs = [int(q) for q in rng.choice(n, size=k, replace=False)]
+        m = (rng.standard_normal((1 << k, 1 << k)) + 1j * rng.standard_normal((1 << k, 1 << k))) / (1 << (k // 2))
+        ref = ref_input(psi, dt)
+        O.apply_matrix(ref, m, qs)
+        got = gpu_apply(dt, psi, lambda s: s.apply_gate(m, qs))
+        check_close(got, ref, dt)
+        if n >= k + 2:
+            qc = [int(q) for q in rng.choice(n, size=k + 2, replace=False)]
+            vals = [int(v) for v in rng.integers(0, 2, size=2)]
+            ref = ref_input(psi, dt)
+            O.apply_matrix(ref, m, qc[:k], qc[k:], vals)
+            got = gpu_apply(dt, psi, lambda s: s.apply_gate(m, qc[:k], qc[k:], vals))
+            check_close(got, ref, dt)
+    # a wide diagonal gate takes the same path
+    n = k + 1
+    psi = rand_state(rng, n)
+    d = np.diag(np.exp(1j * rng.uniform(0, 6, 1 << k)))
+    qs = [int(q) for q in rng.choice(n, size=k, replace=False)]
+    ref = ref_input(psi, dt)
+    O.apply_matrix(ref, d, qs)
+    check_close(gpu_apply(dt, psi, lambda s: s.apply_gate(d, qs)), ref, dt)
+
+
+@pytest.mark.parametrize("dt", DTYPES)
 def test_diagonal_and_structured_k(dt):
     rng = np.random.default_rng(33)
     n = 9
