@@ -165,9 +165,11 @@ int qsv_marginal_probability(const qsv_state* s, const int* values, double* out)
  * indices, out[i] = the smallest x with C(x) > u[i] * C(2^n - 1), C the
  * inclusive cumulative sum of |psi|^2 in FP64 (unnormalised states are
  * sampled from |psi|^2 / <psi|psi>). An index of probability zero is never
- * returned. The call allocates a temporary FP64 table of 2^n entries
- * (8 bytes per amplitude) plus 2^(n-12) for the chunk totals, frees it before
- * returning, and synchronises. count == 0 only builds the table.
+ * returned. The table takes 2^n FP64 entries (8 bytes per amplitude) plus
+ * 2^(n-12) chunk totals and 16 bytes per sample, carved from the state's work
+ * buffer: allocated on the first call (or grown), kept for later calls and
+ * freed with the state. The call synchronises. count == 0 only builds the
+ * table.
  * Errors: QSV_EINVAL (null arguments, count < 0, a state of zero norm),
  * QSV_ERANGE (a uniform outside [0, 1) or NaN, count > 2^31), QSV_ENOMEM. */
 int qsv_sample(const qsv_state* s, const double* u, int64_t count, int64_t* out);
@@ -375,7 +377,12 @@ int qsv_apply_observable(const qsv_state* in, const qsv_observable* o, qsv_state
  * forward_plan: optional fused plan of the same circuit and dtype for the
  * forward pass (NULL = one launch per gate). grad: circuit nparams doubles,
  * overwritten; a slot used by several gates receives the sum of their
- * contributions. Gradients accumulate in double. Synchronises the stream. */
+ * contributions. Gradients accumulate in double. Parametric multi-qubit Pauli
+ * rotations (qsv_circuit_add_pauli_rotation) are differentiated too. From 20
+ * (complex64) / 19 (complex128) qubits the reverse sweep runs in tile passes
+ * whose tables live in psi's work buffer (allocated on first use, kept,
+ * freed with the state); Pauli strings on more than 5 qubits keep the
+ * per-gate sweep. Synchronises the stream. */
 int qsv_adjoint_gradient(const qsv_circuit* c, qsv_plan* forward_plan, const double* theta,
                          const qsv_observable* o, qsv_state* psi, qsv_state* lam,
                          double* energy, double* grad);

@@ -123,6 +123,40 @@ __device__ __forceinline__ double adj_rot(cx<R>* __restrict__ ps, cx<R>* __restr
   return acc;
 }
 
+// -Im of i^ph (sr + i si).
+__device__ __forceinline__ double neg_im_phase(double sr, double si, int ph) {
+  switch (ph & 3) {
+    case 0: return -si;
+    case 1: return -sr;
+    case 2: return si;
+    default: return sr;
+  }
+}
+
+// Gradient term of a multi-qubit Pauli rotation exp(i t P/2) (TileOpDev kind
+// 3): this thread's share of -Im<lambda|P|psi> over the tile, with
+// (P psi)_x = i^ph (-1)^{|x & zy|} psi_{x ^ f} (the constant part of the sign
+// folded into ph on the host; Z/Y factors on non-local qubits give the tile's
+// sign). The states are not changed.
+template <typename R>
+__device__ __forceinline__ double adj_pauli_grad(const cx<R>* __restrict__ ps, const cx<R>* __restrict__ la,
+                                                 const TileOpDev& op, int L, uint64_t base) {
+  const uint32_t lf = op.off[0], zl = op.off[1];
+  const uint64_t zg = uint64_t(op.off[3]) | (uint64_t(op.off[4]) << 32);
+  const uint32_t gs = uint32_t(__popcll(base & zg) & 1);
+  const int TS = 1 << L;
+  double sr = 0.0, si = 0.0;
+  for (int j = threadIdx.x; j < TS; j += blockDim.x) {
+    const cx<R> a = ps[uint32_t(j) ^ lf], l = la[j];
+    const double wr = double(l.re) * a.re + double(l.im) * a.im;
+    const double wi = double(l.re) * a.im - double(l.im) * a.re;
+    const bool neg = ((__popc(uint32_t(j) & zl) & 1) ^ gs) != 0;
+    sr += neg ? -wr : wr;
+    si += neg ? -wi : wi;
+  }
+  return neg_im_phase(sr, si, int(op.off[2]));
+}
+
 template <typename R, int KMAX>
 __global__ void __launch_bounds__(kAdjTileThreads)
     k_tile_adj(R* __restrict__ psi, R* __restrict__ lam, const TilePassDev* __restrict__ passes,
@@ -153,8 +187,9 @@ __global__ void __launch_bounds__(kAdjTileThreads)
     for (int o = 0; o < P.op_count; ++o) {
       const TileOpDev& op = ops[P.op_begin + o];
       if ((base & op.gcm) != op.gcv) continue;
-      if (op.kind == 2) {
-        double acc = adj_rot<R>(ts, tl, op, pool + op.moff, L, base);
+      if (op.kind == 2 || op.kind == 3) {
+        double acc = op.kind == 2 ? adj_rot<R>(ts, tl, op, pool + op.moff, L, base)
+                                  : adj_pauli_grad<R>(ts, tl, op, L, base);
 #pragma unroll
         for (int s = 32; s > 0; s >>= 1) acc += __shfl_xor(acc, s, 64);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -330,6 +365,37 @@ __device__ __forceinline__ void adj_step(const RegOpDev& opr, const cx<R>* s, co
     return;
   }
   const cx<R>* m = pool + op.moff;
+  if (op.kind == 8) {
+    // Pauli-string gradient: psi staged in LDS in this segment's layout; the
+    // partner x ^ f of element i is at its address XOR pf_lds (the swizzle is
+    // linear over XOR and the tile starts at LDS address 0)
+    const LdsMap<R, RB, TB> ms(S.get_reg, S.get_tcol, 0u, tau);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) ms.put(smem, i, s[i]);
+    __syncthreads();
+    typedef R R2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(3))) R2 lds_r2;
+    const uint32_t tpar = uint32_t(__popc(tau & op.pz_thr) + __popcll(base & op.pz_glob)) & 1u;
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const R2 av = *reinterpret_cast<lds_r2*>(uintptr_t(reinterpret_cast<uintptr_t>(ms.at(smem, i)) ^ op.pf_lds));
+      const cx<R> c = l[i];
+      const double wr = double(c.re) * av.x + double(c.im) * av.y;
+      const double wi = double(c.re) * av.y - double(c.im) * av.x;
+      const bool neg = ((uint32_t(__popc(uint32_t(i) & op.pz_reg)) ^ tpar) & 1u) != 0;
+      sr += neg ? -wr : wr;
+      si += neg ? -wi : wi;
+      os[i] = s[i];
+      ol[i] = c;
+    }
+    __syncthreads();  // every read done before the LDS tile is written again
+    double acc = neg_im_phase(sr, si, op.pph);
+#pragma unroll
+    for (int sft = 32; sft > 0; sft >>= 1) acc += __shfl_xor(acc, sft, 64);
+    if ((tau & 63) == 0) wslot[op.aux * (1 << (TB - 6))] += acc;
+    return;
+  }
   if (op.kind == 5 || op.kind == 6) {
     double acc = grad_apply<R, NR>(s, l, os, ol, op, tau, base, m);
 #pragma unroll
@@ -500,6 +566,7 @@ struct BOp {
   std::vector<int> targets, controls, ctrl_vals;
   std::vector<cd> val;  // dense: matrix; diagonal: diagonal entries
   int pauli = 0, row = -1;
+  std::vector<int> paulis;  // kind 3: Pauli ids (1..3) of the string on targets
 };
 
 void dagger_inplace(std::vector<cd>& m, int D) {
@@ -530,6 +597,17 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
   std::vector<cd> m;
   for (int gi = int(c->gates.size()) - 1; gi >= 0; --gi) {
     const Gate& g = c->gates[gi];
+    if (g.kind == Gate::PAULI && g.slot >= 0) {
+      // gradient term -Im<lambda|P|psi> of exp(i t P/2) (its own op), then the
+      // uncompute exp(-i t P/2) as an ordinary gate below
+      BOp gr;
+      gr.kind = 3;
+      gr.targets = g.targets;
+      gr.paulis = g.paulis;
+      gr.row = int(row_slot.size());
+      row_slot.push_back(g.slot);
+      ops.push_back(gr);
+    }
     if (g.kind == Gate::ROTATION && g.slot >= 0) {
       // gradient term fused with the uncompute exp(-i t P/2)
       BOp gr;
@@ -601,10 +679,14 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
       }
       uint64_t dense = 0;
       if (o.kind == 0 || (o.kind == 2 && o.pauli != 3)) dense = qmask_of(o.targets);
+      if (o.kind == 3)  // the X/Y qubits of the string: pairs x, x ^ f in one tile
+        for (size_t j = 0; j < o.targets.size(); ++j)
+          if (o.paulis[j] != 3) dense |= uint64_t(1) << o.targets[j];
       const uint64_t need = dense & ~local;
-      const bool rows_full = reg && o.kind == 2 && nrow >= kAdjMaxRows;
+      const bool grad = o.kind == 2 || o.kind == 3;
+      const bool rows_full = reg && grad && nrow >= kAdjMaxRows;
       if (!rows_full && __builtin_popcountll(local | need) <= L) {
-        if (o.kind == 2) ++nrow;
+        if (grad) ++nrow;
         local |= need;
         take.push_back(oi);
       } else {
@@ -651,6 +733,34 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
       const BOp& o = ops[oi];
       TileOpDev t{};
       for (int j = 0; j < 5; ++j) t.lt[j] = t.gq[j] = -1;
+      if (o.kind == 3) {
+        t.kind = 3;
+        t.k = int(o.targets.size());
+        t.ins[0] = o.row;
+        t.ins[1] = d.row_count++;
+        prow.push_back(o.row);
+        uint32_t lf = 0, zl = 0;
+        uint64_t zg = 0;
+        int ny = 0;
+        for (size_t j = 0; j < o.targets.size(); ++j) {
+          const int q = o.targets[j], pid = o.paulis[j];
+          if (pid == 2) ++ny;
+          if (pid != 3) lf |= 1u << lpos[q];  // (X/Y qubits are local)
+          if (pid != 1) {
+            if (lpos[q] >= 0) zl |= 1u << lpos[q];
+            else zg |= uint64_t(1) << q;
+          }
+        }
+        t.off[0] = lf;
+        t.off[1] = zl;
+        // (P psi)_x = i^nY (-1)^{|(x ^ f) & zy|} psi_{x ^ f}; the part of the
+        // sign from f & zy is a constant: two more quarter turns when odd
+        t.off[2] = uint32_t((ny + 2 * (__builtin_popcount(lf & zl) & 1)) & 3);
+        t.off[3] = uint32_t(zg);
+        t.off[4] = uint32_t(zg >> 32);
+        ho.push_back(t);
+        continue;
+      }
       if (o.kind == 2) {
         t.kind = 2;
         t.k = o.pauli;
@@ -726,14 +836,15 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
   const size_t o_part = o_prow + al(std::max<size_t>(1, prow.size()) * sizeof(int));
   const size_t o_rows = o_part + al(std::max<size_t>(1, size_t(nrows) * G) * sizeof(double));
   const size_t total = o_rows + al(std::max(1, nrows) * sizeof(double));
-  char* d = nullptr;
-  if (hipMalloc(reinterpret_cast<void**>(&d), total) != hipSuccess)
-    return fail(QSV_ENOMEM, "tiled sweep tables allocation failed");
+  // the tables live in psi's work buffer (kept for the next gradient; the
+  // sweep synchronises before returning)
+  void* wb = nullptr;
+  if (int e = state_work(psi, total, &wb)) return e;
+  char* d = static_cast<char*>(wb);
   hipStream_t st = psi->stream;
   int rc = QSV_OK;
   auto fin = [&](int r) {
     (void)hipStreamSynchronize(st);
-    (void)hipFree(d);
     return r;
   };
   if (hipMemcpyAsync(d, hp.data(), hp.size() * sizeof(TilePassDev), hipMemcpyHostToDevice, st) != hipSuccess ||

@@ -137,17 +137,17 @@ int adjoint_t(const qsv_circuit* c, qsv_plan* plan, const double* theta, const q
   *energy = re;
   // backward
   int nrot = 0;
-  bool pauli = false;  // multi-qubit Pauli rotations: per-gate sweep only
+  bool wide = false;  // Pauli rotations on more than 5 qubits: per-gate sweep only
   for (const Gate& g : c->gates) {
     if ((g.kind == Gate::ROTATION || g.kind == Gate::PAULI) && g.slot >= 0) ++nrot;
-    if (g.kind == Gate::PAULI) pauli = true;
+    if (g.kind == Gate::PAULI && g.targets.size() > 5) wide = true;
   }
   // large states: reverse sweep by tile passes (both states streamed once per
   // pass); small states keep one launch per gate, which spreads better
   const int Ltile = sizeof(R) == 4 ? 12 : 11;
   int tiled_min = Ltile + 8;
   if (const char* e = std::getenv("QSV_ADJOINT_TILED_MIN")) tiled_min = std::atoi(e);  // testing
-  if (n >= tiled_min && !pauli) {
+  if (n >= tiled_min && !wide) {
     std::vector<int> rs;
     std::vector<double> rv;
     if ((rc = adjoint_backward_tiled<R>(c, theta, psi, lam, rs, rv))) return rc;

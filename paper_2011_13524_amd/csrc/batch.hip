@@ -29,14 +29,15 @@ constexpr int kBatchMaxQ = 24;    // qubits per item
 constexpr int kBatchRows = 64;    // gradient rows per reverse pass (LDS slots)
 constexpr size_t kBatchStateLds = 65536;  // default LDS for psi + lambda (whole states or tiles)
 
-enum BatchOpKind { BO_ROT = 0, BO_CZ = 1, BO_CNOT = 2, BO_DENSE1 = 3 };
+enum BatchOpKind { BO_ROT = 0, BO_CZ = 1, BO_CNOT = 2, BO_DENSE1 = 3, BO_PAULI = 4 };
 
 struct BatchOp {
   int kind;
-  int q0, q1;    // ROT/DENSE1: q0 target; CZ: q0, q1; CNOT: q0 control, q1 target
-  int pauli;     // ROT
-  int slot;      // ROT: parameter slot (>= 0) or -1 for a fixed angle
-  int moff;      // DENSE1 / fixed ROT: offset of the 2x2 matrix in the pool
+  int q0, q1;    // ROT/DENSE1: q0 target; CZ: q0, q1; CNOT: q0 control, q1 target;
+                 // PAULI: q0 flip mask (X/Y qubits), q1 sign mask (Y/Z qubits)
+  int pauli;     // ROT: Pauli id; PAULI: number of Y factors
+  int slot;      // ROT/PAULI: parameter slot (>= 0) or -1 for a fixed angle
+  int moff;      // DENSE1 / fixed ROT: offset of the 2x2 matrix in the pool; fixed PAULI: of its angle
 };
 
 struct BatchItem {
@@ -66,9 +67,10 @@ struct BatchPass {
 struct BTOp {
   int kind;
   int p0, p1, g0, g1;
-  int pauli, slot;  // ROT
+  int pauli, slot;  // ROT (PAULI: number of Y factors, slot)
   int bop;          // index of the op in the item's op list (its matrix)
   int row;          // reverse passes: gradient row in the pass (-1: none)
+  uint32_t lf, lz, gz;  // PAULI: flip and sign masks in local index space, sign mask on non-local qubits
 };
 
 struct BatchGroup {
@@ -142,10 +144,81 @@ __device__ __forceinline__ uint32_t ins2(uint32_t i, int lo, int hi) {
   return i;
 }
 
+// Multi-qubit Pauli rotation exp(i t P/2) = cos(t/2) + i sin(t/2) P on the
+// index set [0, TS) (a whole state or a tile), with
+// (P v)_x = i^ny (-1)^{|(x ^ f) & z| + gs} v_{x ^ f} (gs: the tile's sign from
+// Z/Y factors on non-local qubits).
+__device__ __forceinline__ int par32(uint32_t x) { return __popc(x) & 1; }
+
+template <typename R>
+__device__ __forceinline__ cx<R> times_ipow(cx<R> v, int k) {  // v * i^k
+  switch (k & 3) {
+    case 0: return v;
+    case 1: return {-v.im, v.re};
+    case 2: return {-v.re, -v.im};
+    default: return {v.im, -v.re};
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void pauli_rot_set(cx<R>* v, uint32_t TS, uint32_t f, uint32_t z, int ny, int gs,
+                                              double t) {
+  double sn, cs;
+  sincos(0.5 * t, &sn, &cs);
+  const R c = R(cs), s = R(sn);
+  if (f == 0) {  // diagonal: cos + i sin (-1)^{|x & z| + gs}
+    for (uint32_t x = threadIdx.x; x < TS; x += blockDim.x) {
+      const cx<R> fx = {c, (par32(x & z) ^ gs) ? -s : s};
+      v[x] = fx * v[x];
+    }
+    return;
+  }
+  const int h = __ffs(f) - 1;
+  for (uint32_t i = threadIdx.x; i < TS / 2; i += blockDim.x) {
+    const uint32_t x = ((i >> h) << (h + 1)) | (i & ((1u << h) - 1)), y = x ^ f;
+    const cx<R> a = v[x], b = v[y];
+    // i sin (P v)_x = sin i^(ny+1) (-1)^{|y & z| + gs} b, and symmetrically at y
+    const cx<R> pb = times_ipow(b, ny + 1), pa = times_ipow(a, ny + 1);
+    const R sx = (par32(y & z) ^ gs) ? -s : s, sy = (par32(x & z) ^ gs) ? -s : s;
+    v[x] = {c * a.re + sx * pb.re, c * a.im + sx * pb.im};
+    v[y] = {c * b.re + sy * pa.re, c * b.im + sy * pa.im};
+  }
+}
+
+// This thread's share of -Im<lam|P|psi> on the index set [0, TS).
+template <typename R>
+__device__ __forceinline__ double pauli_grad_set(const cx<R>* ps, const cx<R>* la, uint32_t TS, uint32_t f,
+                                                 uint32_t z, int ny, int gs) {
+  double sr = 0.0, si = 0.0;
+  for (uint32_t x = threadIdx.x; x < TS; x += blockDim.x) {
+    const uint32_t y = x ^ f;
+    const cx<R> a = ps[y], l = la[x];
+    const double wr = double(l.re) * a.re + double(l.im) * a.im;
+    const double wi = double(l.re) * a.im - double(l.im) * a.re;
+    const bool neg = (par32(y & z) ^ gs) != 0;
+    sr += neg ? -wr : wr;
+    si += neg ? -wi : wi;
+  }
+  // -Im of i^ny (sr + i si)
+  switch (ny & 3) {
+    case 0: return -si;
+    case 1: return -sr;
+    case 2: return si;
+    default: return sr;
+  }
+}
+
+__device__ __forceinline__ double op_angle(const BatchOp& op, const double* theta, const double* pool) {
+  return op.slot >= 0 ? theta[op.slot] : pool[op.moff];
+}
+
 template <typename R>
 __device__ __forceinline__ void wg_apply_op(cx<R>* s, int n, const BatchOp& op, const double* theta,
                                             const double* pool, bool dag) {
-  if (op.kind == BO_ROT) {
+  if (op.kind == BO_PAULI) {
+    const double t = op_angle(op, theta, pool);
+    pauli_rot_set<R>(s, 1u << n, uint32_t(op.q0), uint32_t(op.q1), op.pauli, 0, dag ? -t : t);
+  } else if (op.kind == BO_ROT) {
     const double t = op.slot >= 0 ? theta[op.slot] : 0.0;
     M2<R> u = op.slot >= 0 ? rot2<R>(op.pauli, dag ? -t : t) : pool2<R>(pool + op.moff, dag);
     wg_apply_2x2(s, n, op.q0, u);
@@ -239,7 +312,18 @@ __device__ __forceinline__ void bt_cnot(cx<R>* t, const BTOp& op, uint32_t TS, u
 // gradient term -Im<lambda|P|psi> when the op is a parametric rotation.
 template <typename R>
 __device__ __forceinline__ double bt_rev(cx<R>* ps, cx<R>* la, const BTOp& op, const M2<R>* mats, uint32_t TS,
-                                         uint32_t base) {
+                                         uint32_t base, double t) {
+  if (op.kind == BO_PAULI) {
+    const int gs = par32(base & op.gz);
+    double acc = 0.0;
+    if (op.row >= 0) {
+      acc = pauli_grad_set<R>(ps, la, TS, op.lf, op.lz, op.pauli, gs);
+      __syncthreads();  // every read of the term before the uncompute writes
+    }
+    pauli_rot_set<R>(ps, TS, op.lf, op.lz, op.pauli, gs, -t);
+    pauli_rot_set<R>(la, TS, op.lf, op.lz, op.pauli, gs, -t);
+    return acc;
+  }
   if (op.kind == BO_CZ) {
     bt_cz(ps, op, TS, base);
     bt_cz(la, op, TS, base);
@@ -314,6 +398,9 @@ __device__ void bt_forward(const BatchArgs& a, const BatchItem& I, cx<R>* psi, M
         const BTOp op = a.tops[P.op_begin + o];
         if (op.kind == BO_CZ) bt_cz(t, op, TS, base);
         else if (op.kind == BO_CNOT) bt_cnot(t, op, TS, base);
+        else if (op.kind == BO_PAULI)
+          pauli_rot_set<R>(t, TS, op.lf, op.lz, op.pauli, par32(base & op.gz),
+                           op_angle(a.ops[I.op_begin + op.bop], theta, a.pool));
         else bt_pair(t, op.p0, mats[op.bop], TS);
         __syncthreads();
       }
@@ -328,6 +415,7 @@ __device__ void bt_forward(const BatchArgs& a, const BatchItem& I, cx<R>* psi, M
 template <typename R>
 __device__ void bt_reverse(const BatchArgs& a, const BatchItem& I, cx<R>* psi, cx<R>* lam, const M2<R>* mats,
                            double* grad, char* smem) {
+  const double* theta = a.theta + I.theta_off;
   const int NW = int(blockDim.x >> 6);
   cx<R>* ts = reinterpret_cast<cx<R>*>(smem);
   cx<R>* tl = ts + a.lds_state_bytes / 2 / sizeof(cx<R>);
@@ -349,7 +437,8 @@ __device__ void bt_reverse(const BatchArgs& a, const BatchItem& I, cx<R>* psi, c
       __syncthreads();
       for (int o = 0; o < P.op_count; ++o) {
         const BTOp op = a.tops[P.op_begin + o];
-        double acc = bt_rev(ts, tl, op, mats, TS, base);
+        const double t = op.kind == BO_PAULI ? op_angle(a.ops[I.op_begin + op.bop], theta, a.pool) : 0.0;
+        double acc = bt_rev(ts, tl, op, mats, TS, base, t);
         if (op.row >= 0) {
 #pragma unroll
           for (int sft = 32; sft > 0; sft >>= 1) acc += __shfl_xor(acc, sft, 64);
@@ -471,6 +560,13 @@ __global__ void __launch_bounds__(NT) k_batch(BatchArgs a) {
         acc = wg_sum(acc, red);
         if (threadIdx.x == 0) grad[op.slot] += acc;
         __syncthreads();
+      } else if (op.kind == BO_PAULI && op.slot >= 0) {
+        // -Im<lambda|P|psi>, then the uncompute of both states
+        double acc = pauli_grad_set<R>(psi, lam, N, uint32_t(op.q0), uint32_t(op.q1), op.pauli, 0);
+        acc = wg_sum(acc, red);  // (its barriers also order the reads before the writes)
+        if (threadIdx.x == 0) grad[op.slot] += acc;
+        wg_apply_op<R>(psi, n, op, theta, a.pool, true);
+        wg_apply_op<R>(lam, n, op, theta, a.pool, true);
       } else {
         wg_apply_op<R>(psi, n, op, theta, a.pool, true);
         wg_apply_op<R>(lam, n, op, theta, a.pool, true);
@@ -534,6 +630,7 @@ void schedule_item(int n, int L, int b, const BatchOp* ops, int count, bool reve
   pcount = 0;
   const uint64_t low = (uint64_t(1) << b) - 1;
   auto qubits = [&](const BatchOp& o) {
+    if (o.kind == BO_PAULI) return uint64_t(uint32_t(o.q0) | uint32_t(o.q1));
     uint64_t m = uint64_t(1) << o.q0;
     if (o.kind == BO_CZ || o.kind == BO_CNOT) m |= uint64_t(1) << o.q1;
     return m;
@@ -551,8 +648,10 @@ void schedule_item(int n, int L, int b, const BatchOp* ops, int count, bool reve
         continue;
       }
       const uint64_t dense =
-          o.kind == BO_CZ ? 0 : (o.kind == BO_CNOT ? uint64_t(1) << o.q1 : uint64_t(1) << o.q0);
-      const bool grad = reverse && o.kind == BO_ROT && o.slot >= 0;
+          o.kind == BO_PAULI ? uint64_t(uint32_t(o.q0))  // the X/Y qubits: pairs x, x ^ f in one tile
+          : o.kind == BO_CZ  ? 0
+                             : (o.kind == BO_CNOT ? uint64_t(1) << o.q1 : uint64_t(1) << o.q0);
+      const bool grad = reverse && (o.kind == BO_ROT || o.kind == BO_PAULI) && o.slot >= 0;
       const uint64_t need = dense & ~local;
       if (!(grad && nrow >= kBatchRows) && __builtin_popcountll(local | need) <= L) {
         local |= need;
@@ -585,14 +684,26 @@ void schedule_item(int n, int L, int b, const BatchOp* ops, int count, bool reve
       const BatchOp& o = ops[oi];
       BTOp t{};
       t.kind = o.kind;
-      t.p0 = lpos[size_t(o.q0)];
-      t.g0 = o.q0;
-      t.p1 = (o.kind == BO_CZ || o.kind == BO_CNOT) ? lpos[size_t(o.q1)] : -1;
-      t.g1 = o.q1;
+      if (o.kind == BO_PAULI) {
+        t.p0 = t.p1 = t.g0 = t.g1 = -1;
+        for (int q = 0; q < n; ++q) {
+          const uint32_t bit = 1u << q;
+          if (uint32_t(o.q0) & bit) t.lf |= 1u << lpos[size_t(q)];  // (local)
+          if (uint32_t(o.q1) & bit) {
+            if (lpos[size_t(q)] >= 0) t.lz |= 1u << lpos[size_t(q)];
+            else t.gz |= bit;
+          }
+        }
+      } else {
+        t.p0 = lpos[size_t(o.q0)];
+        t.g0 = o.q0;
+        t.p1 = (o.kind == BO_CZ || o.kind == BO_CNOT) ? lpos[size_t(o.q1)] : -1;
+        t.g1 = o.q1;
+      }
       t.pauli = o.pauli;
       t.slot = o.slot;
       t.bop = oi;
-      t.row = (reverse && o.kind == BO_ROT && o.slot >= 0) ? P.row_count++ : -1;
+      t.row = (reverse && (o.kind == BO_ROT || o.kind == BO_PAULI) && o.slot >= 0) ? P.row_count++ : -1;
       tops.push_back(t);
     }
     passes.push_back(P);
@@ -627,8 +738,27 @@ int build_device(qsv_batch* b, qsv_dtype dt) {
     I.op_begin = int(ops.size());
     for (const Gate& g : it.c.gates) {
       BatchOp op{};
-      if (g.kind == Gate::PAULI)
-        return fail(QSV_EINVAL, "batched items support one-qubit gates, rotations, CZ and CNOT");
+      if (g.kind == Gate::PAULI) {
+        op.kind = BO_PAULI;
+        uint32_t f = 0, z = 0;
+        int ny = 0;
+        for (size_t j = 0; j < g.targets.size(); ++j) {
+          const uint32_t bit = 1u << g.targets[j];
+          if (g.paulis[j] != 3) f |= bit;
+          if (g.paulis[j] != 1) z |= bit;
+          if (g.paulis[j] == 2) ++ny;
+        }
+        op.q0 = int(f);
+        op.q1 = int(z);
+        op.pauli = ny;
+        op.slot = g.slot;
+        if (g.slot < 0) {
+          op.moff = int(pool.size());
+          pool.push_back(g.fixed_angle);
+        }
+        ops.push_back(op);
+        continue;
+      }
       if (g.kind == Gate::ROTATION) {
         op.kind = BO_ROT;
         op.q0 = g.targets[0];
@@ -675,7 +805,7 @@ int build_device(qsv_batch* b, qsv_dtype dt) {
           op.q0 = __builtin_ctzll(cm);
           op.q1 = tq[0];
         } else {
-          return fail(QSV_EINVAL, "batched items support one-qubit gates, rotations, CZ and CNOT");
+          return fail(QSV_EINVAL, "batched items support one-qubit gates, rotations, Pauli rotations, CZ and CNOT");
         }
       }
       ops.push_back(op);

@@ -17,7 +17,12 @@ constexpr int kTileMaxGlobal = 40;
 // bit p <-> qubit local[p]).
 struct TileOpDev {
   int kind;        // 0 dense on local targets, 1 diagonal (targets local or not),
-                   // 2 gradient rotation of the reverse sweep (k = Pauli id)
+                   // 2 gradient rotation of the reverse sweep (k = Pauli id),
+                   // 3 gradient term of a multi-qubit Pauli rotation (reverse sweep;
+                   //   no update): off[0] local flip mask, off[1] local Z/Y mask,
+                   //   off[2] phase exponent (P x = i^off[2] (-1)^|x & zy| (x ^ f)
+                   //   up to the tile's sign), off[3..4] Z/Y mask on non-local
+                   //   qubits (low, high word), ins[0] row, ins[1] slot in the pass
   int k;           // number of targets
   int m;           // number of inserted zero positions (dense: targets + local controls)
   int moff;        // offset of the matrix / diagonal in the pool (complex elements)
@@ -89,6 +94,13 @@ struct RegOpDev {
   int lop;              // index of the equivalent TileOpDev (LDS execution)
   int aux;              // gradient: slot of its row in the pass
   int key;              // kinds 0, 1, 2, 4: variant of the register op (reg_key)
+  // kind 8 (reverse sweep): gradient term of a multi-qubit Pauli rotation,
+  // evaluated with psi staged in LDS: the partner of element i sits at its LDS
+  // address XOR pf_lds; the sign parity is that of (i & pz_reg), (thread index
+  // & pz_thr) and (tile base & pz_glob); phase exponent pph (0..3)
+  uint32_t pf_lds, pz_reg, pz_thr;
+  int pph;
+  uint64_t pz_glob;
 };
 
 // Register-resident layout of a tile: 2^reg_bits amplitudes per thread,

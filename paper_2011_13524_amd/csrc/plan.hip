@@ -456,6 +456,10 @@ int build_reg_segments(const SegCfg& cfg, const std::vector<TileOpDev>& ho, Tile
       nd[i] = o.k == 3 ? 0u : t1;
       dg[i] = o.k == 3 ? t1 : 0u;
       need[i] = o.k == 3 ? 0u : t1;
+    } else if (o.kind == 3) {  // Pauli-string gradient: X/Y qubits non-diagonal, Z diagonal
+      nd[i] = o.off[0];
+      dg[i] = o.off[1] & ~o.off[0];
+      need[i] = 0;
     } else if (o.kind == 0) {
       nd[i] = tg;
       dg[i] = o.lcm;
@@ -672,8 +676,22 @@ int build_reg_segments(const SegCfg& cfg, const std::vector<TileOpDev>& ho, Tile
           r.ti_cv |= val << thridx[pos];
         }
       }
-      r.aux = o.kind == 2 ? o.ins[1] : 0;  // gradient: slot of the row in the pass
-      if (o.kind == 2 && o.k != 3) {
+      r.aux = (o.kind == 2 || o.kind == 3) ? o.ins[1] : 0;  // gradient: slot of the row in the pass
+      if (o.kind == 3) {
+        // Pauli-string gradient through LDS in this segment's layout
+        r.kind = 8;
+        const int SBp = c64 ? 5 : 4;
+        const uint32_t msk = (1u << SBp) - 1, fl = o.off[0];
+        r.pf_lds = (fl ^ ((fl >> SBp) & msk) ^ ((fl >> (2 * SBp)) & msk)) * (c64 ? 8u : 16u);
+        r.pz_reg = r.pz_thr = 0;
+        for (int pos = 0; pos < L; ++pos) {
+          if (!(o.off[1] >> pos & 1)) continue;
+          if (regidx[pos] >= 0) r.pz_reg |= 1u << regidx[pos];
+          else r.pz_thr |= 1u << thridx[pos];
+        }
+        r.pph = int(o.off[2]);
+        r.pz_glob = uint64_t(o.off[3]) | (uint64_t(o.off[4]) << 32);
+      } else if (o.kind == 2 && o.k != 3) {
         r.kind = 5;
         r.p1 = regidx[o.lt[0]];
         if (r.p1 < 0) return fail(QSV_EINVAL, "internal: gradient target not in registers");

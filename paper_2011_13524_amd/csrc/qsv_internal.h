@@ -79,7 +79,18 @@ struct qsv_state {
   // matrix of a dense gate on 6..10 targets (FP64, transposed), grown on use
   void* big = nullptr;
   size_t big_cap = 0;
+  // work buffer of calls that synchronise the stream before returning
+  // (sampling tables, reverse-sweep tables): grown on demand, kept for the
+  // next call, freed with the state
+  mutable void* work = nullptr;
+  mutable size_t work_cap = 0;
 };
+
+namespace qsv {
+// *out = at least `bytes` of the state's work buffer (grown after a stream
+// sync when too small); QSV_OK, or QSV_ENOMEM / QSV_EHIP with the error set.
+int state_work(const qsv_state* s, size_t bytes, void** out);
+}  // namespace qsv
 
 namespace qsv {
 

@@ -164,25 +164,43 @@ __global__ void __launch_bounds__(kSampleThreads)
 
 namespace {
 
-// Device buffers of one sampling call, freed on every exit path.
+// Device memory of one sampling call, carved from the state's work buffer
+// (kept for the next call; every call synchronises before returning).
 struct SampleBuffers {
-  std::vector<void*> ptrs;
-  ~SampleBuffers() {
-    for (void* p : ptrs) (void)hipFree(p);
-  }
+  char* base = nullptr;
+  size_t used = 0, cap = 0;
   template <typename T>
   T* get(size_t n) {
-    void* p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return nullptr;
-    ptrs.push_back(p);
-    return static_cast<T*>(p);
+    const size_t bytes = (std::max<size_t>(n, 1) * sizeof(T) + 255) / 256 * 256;
+    if (used + bytes > cap) return nullptr;
+    T* p = reinterpret_cast<T*>(base + used);
+    used += bytes;
+    return p;
   }
 };
 
 template <typename R>
 int sample_t(const qsv_state* s, const double* u, int64_t count, int64_t* out) {
   hipStream_t st = s->stream;
+  // sizes: level 0 table (one FP64 per amplitude), the chunk totals of every
+  // level, then the uniforms and the outputs
+  size_t need = 0;
+  auto add = [&need](size_t bytes) { need += (std::max<size_t>(bytes, 1) + 255) / 256 * 256; };
+  {
+    uint64_t c = dim(s->n);
+    add(c * sizeof(double));
+    do {
+      c = (c + kScanChunk - 1) >> kScanChunkBits;
+      add(c * sizeof(double));
+    } while (c > 1);
+    add(size_t(count) * sizeof(double));
+    add(size_t(count) * sizeof(int64_t));
+  }
   SampleBuffers buf;
+  void* wb = nullptr;
+  if (int rc = state_work(s, need, &wb)) return rc;
+  buf.base = static_cast<char*>(wb);
+  buf.cap = need;
   ScanTree T{};
   uint64_t cnt = dim(s->n);
   // level 0: |psi|^2 chunks of the state; higher levels scan the chunk totals in place

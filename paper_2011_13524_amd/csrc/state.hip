@@ -87,6 +87,25 @@ int Uploader::release(int slot, hipStream_t stream) {
   return QSV_OK;
 }
 
+int state_work(const qsv_state* s, size_t bytes, void** out) {
+  *out = nullptr;
+  if (s->work_cap < bytes || !s->work) {
+    // the old buffer may still be read by enqueued work
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(QSV_EHIP, "stream synchronisation failed");
+    if (s->work) (void)hipFree(s->work);
+    s->work = nullptr;
+    s->work_cap = 0;
+    const size_t cap = std::max<size_t>(bytes, 256);
+    if (hipMalloc(&s->work, cap) != hipSuccess) {
+      s->work = nullptr;
+      return fail(QSV_ENOMEM, "work buffer of %zu bytes: allocation failed", bytes);
+    }
+    s->work_cap = cap;
+  }
+  *out = s->work;
+  return QSV_OK;
+}
+
 // ------------------------------------------------------------------ kernels
 
 // Zero the state and set amplitude k to one: the computational basis state |k>.
@@ -231,6 +250,7 @@ int qsv_state_free(qsv_state* s) {
   if (s->red) (void)hipFree(s->red);
   if (s->red_host) (void)hipHostFree(s->red_host);
   if (s->big) (void)hipFree(s->big);
+  if (s->work) (void)hipFree(s->work);
   delete s;
   return QSV_OK;
 }

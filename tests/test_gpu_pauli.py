@@ -92,6 +92,40 @@ def test_circuits_with_pauli_rotations(dt):
         assert np.max(np.abs(s.store() - ref)) <= AMP[dt], kw
 
 
+@pytest.mark.parametrize("dt,mfma", [("c128", "1"), ("c64", "1"), ("c64", "0")])
+@pytest.mark.parametrize("grid", ["0", "3"])
+def test_tiled_sweep_with_pauli_rotations_vs_shift_rule(dt, mfma, grid, monkeypatch):
+    # the tile-pass reverse sweep with parametric Pauli strings (gradient op
+    # -Im<lambda|P|psi> on the tile, then the uncompute as a dense block):
+    # forced on at 9 qubits (LDS sweep, one tile) and 14 qubits (register
+    # sweep, several tiles; grid 3: ragged ranges of tiles per workgroup);
+    # strings with Y factors, Z factors on non-local qubits, weights 1..5
+    monkeypatch.setenv("QSV_ADJOINT_TILED_MIN", "1")
+    monkeypatch.setenv("QSV_TILE_MFMA", mfma)
+    if grid != "0":
+        monkeypatch.setenv("QSV_ADJOINT_GRID", grid)
+    for n, seed in ((9, 71), (14, 72)):
+        rng = np.random.default_rng(seed)
+        gates, npar = pauli_circuit(n, 2, seed)
+        for w in (1, 2, 5):
+            qs, ps = rand_string(rng, n, w, identities=False)
+            gates.append({"op": "pauli_rot", "q": qs, "paulis": ps, "slot": npar})
+            npar += 1
+        gates.append({"op": "pauli_rot", "q": [0, n - 1, n - 2], "paulis": [3, 3, 2], "slot": npar})
+        npar += 1
+        theta = W.uniform_angles(npar, (6, n))
+        obs = W.random_pauli_observable(n, 15, (1, 4), seed_key=(6, n)) + [(0.2, [])]
+        c = Circuit.from_records(n, gates)
+        psi, lam = State(n, dt), State(n, dt)
+        e, g = adjoint_gradient(c, theta, Observable(n, obs), psi, lam)
+        scale = sum(abs(cf) for cf, _ in obs)
+        assert abs(e - O.energy(n, gates, theta, obs)) <= RED[dt] * scale
+        slots = list(range(0, npar, 2)) + [npar - 4, npar - 3, npar - 2, npar - 1]
+        g_ref = O.param_shift_grad(n, gates, theta, obs, slots=slots)
+        err = np.max(np.abs(g[slots] - g_ref))
+        assert err <= RED[dt] * scale, (n, err)
+
+
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("fused", [False, True])
 def test_adjoint_with_pauli_rotations_vs_shift_rule(dt, fused):
@@ -128,10 +162,25 @@ def test_transition_amplitude_vs_oracle(dt):
     assert abs(transition_amplitude(sa, o, sa) - O.expectation_complex(a, obs)) <= RED[dt] * scale
 
 
-def test_batch_rejects_pauli_rotations():
-    n = 4
-    gates = [{"op": "pauli_rot", "q": [0, 1], "paulis": [1, 1], "slot": 0}]
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_batch_items_with_pauli_rotations_vs_shift_rule(dt):
+    # Pauli-string rotations (parametric and fixed) in batched items: LDS-
+    # resident items (4..10 qubits) and items streamed through tiles in device
+    # memory (13 and 14 qubits), against the oracle's exact shift rule
+    items = []
+    for i, n in enumerate((4, 7, 10, 13, 14)):
+        gates, npar = pauli_circuit(n, 2, 80 + i)
+        theta = W.uniform_angles(npar, (8, i))
+        obs = W.random_pauli_observable(n, 10, (1, 4), seed_key=(8, n)) + [(0.3, [])]
+        items.append((n, gates, theta, obs))
     b = Batch()
-    b.add(Circuit.from_records(n, gates), Observable(n, [(1.0, [(0, 3)])]), [0.3])
-    with pytest.raises(QsvError):
-        b.run("c64")
+    for n, gates, theta, obs in items:
+        b.add(Circuit.from_records(n, gates), Observable(n, obs), theta)
+    e, g = b.run(dt)
+    for i, (n, gates, theta, obs) in enumerate(items):
+        scale = sum(abs(c) for c, _ in obs)
+        assert abs(e[i] - O.energy(n, gates, theta, obs)) <= RED[dt] * scale, (i, n)
+        npar = len(theta)
+        slots = sorted(set(range(0, npar, max(1, npar // 10))) | {npar - 1})
+        g_ref = O.param_shift_grad(n, gates, theta, obs, slots=slots)
+        assert np.max(np.abs(g[i][slots] - g_ref)) <= RED[dt] * scale, (i, n)
