@@ -321,17 +321,19 @@ __device__ __forceinline__ double grad_apply(const cx<R>* s, const cx<R>* l, cx<
 
 // Re-map of one state's registers through LDS (write in the old layout with
 // the folded map, read in the new one).
+// close: a cross-wave re-map ends with a workgroup barrier (another state's
+// re-map writes next); otherwise that barrier is left to the next LDS write.
 template <typename R, int RB, int TB>
 __device__ __forceinline__ void adj_remap(cx<R> (&v)[1 << RB], const LdsMap<R, RB, TB>& mo,
-                                          const LdsMap<R, RB, TB>& mn, bool xw, char* smem) {
+                                          const LdsMap<R, RB, TB>& mn, bool xw, bool close, char* smem) {
 #pragma unroll
   for (int i = 0; i < (1 << RB); ++i) mo.put(smem, i, v[i]);
   if (xw) __syncthreads();
   else wave_sync();
 #pragma unroll
   for (int i = 0; i < (1 << RB); ++i) v[i] = mn.get(smem, i);
-  if (xw) __syncthreads();
-  else wave_sync();
+  if (!xw) wave_sync();
+  else if (close) __syncthreads();
 }
 
 // A block applied through LDS to one state held in registers (v in, o out).
@@ -370,6 +372,7 @@ __device__ __forceinline__ void adj_step(const RegOpDev& opr, const cx<R>* s, co
     // partner x ^ f of element i is at its address XOR pf_lds (the swizzle is
     // linear over XOR and the tile starts at LDS address 0)
     const LdsMap<R, RB, TB> ms(S.get_reg, S.get_tcol, 0u, tau);
+    __syncthreads();  // (a preceding cross-wave re-map's reads are done)
 #pragma unroll
     for (int i = 0; i < NR; ++i) ms.put(smem, i, s[i]);
     __syncthreads();
@@ -405,6 +408,7 @@ __device__ __forceinline__ void adj_step(const RegOpDev& opr, const cx<R>* s, co
   }
   if (op.kind == 3) {
     const LdsMap<R, RB, TB> ms(S.get_reg, S.get_tcol, 0u, tau);
+    __syncthreads();  // (a preceding cross-wave re-map's reads are done)
     adj_lds_op<R, RB, TB, KMAX>(s, os, ms, smem, lops[op.lop], pool, L, base, sw);
     adj_lds_op<R, RB, TB, KMAX>(l, ol, ms, smem, lops[op.lop], pool, L, base, sw);
     return;
@@ -413,8 +417,8 @@ __device__ __forceinline__ void adj_step(const RegOpDev& opr, const cx<R>* s, co
   int a = op.p1, bb = op.p2;
   if (op.kind == 2) diag_table<R>(op, m, tau, base, gtab, a, bb);
   const bool lane = (tau & op.ti_cm) == op.ti_cv;
-  reg_apply<R, NR>(s, os, op.key, m, gtab, op.ri_cm, op.ri_cv, lane);
-  reg_apply<R, NR>(l, ol, op.key, m, gtab, op.ri_cm, op.ri_cv, lane);
+  reg_apply<R, NR, false>(s, os, op.key, m, gtab, op.ri_cm, op.ri_cv, lane, pool, op.lm);
+  reg_apply<R, NR, false>(l, ol, op.key, m, gtab, op.ri_cm, op.ri_cv, lane, pool, op.lm);
 }
 
 template <typename R, int RB, int KMAX, int TB>
@@ -487,12 +491,12 @@ __global__ void __launch_bounds__(1 << TB)
       const RegSegDev* Sn = &segs[P.seg_begin + sgi];
       if (sgi > 0) {
         // re-map both states through LDS (folded X / CNOT ops applied to both)
-        const bool xw = Sn->xwave != 0;
-        if (Sn->xwave == 2) __syncthreads();
+        const bool xw = (Sn->xwave & 1) != 0;
+        if (Sn->xwave & 2) __syncthreads();
         const LdsMap<R, RB, TB> mo(Sn->put_reg, Sn->put_tcol, Sn->put_tcst, tau);
         const LdsMap<R, RB, TB> mn(Sn->get_reg, Sn->get_tcol, 0u, tau);
-        adj_remap<R, RB, TB>(vs, mo, mn, xw, smem);
-        adj_remap<R, RB, TB>(vl, mo, mn, xw, smem);
+        adj_remap<R, RB, TB>(vs, mo, mn, xw, true, smem);
+        adj_remap<R, RB, TB>(vl, mo, mn, xw, false, smem);
       }
       S = Sn;
       // ops alternate between the register arrays (vs, vl) and (ws, wl)
@@ -658,7 +662,8 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
   const int L = std::min(n, Lc);
   // complex64: 256 threads x 16 amplitudes per state; complex128: 256 x 8
   const bool reg = n >= Lc;
-  const SegCfg cfg{sizeof(R) == 4 ? 4 : 3, 8, sizeof(R) == 4, sizeof(R) == 4 && tile_mfma_default()};
+  SegCfg cfg{sizeof(R) == 4 ? 4 : 3, 8, sizeof(R) == 4, sizeof(R) == 4 && tile_mfma_default()};
+  cfg.layers = false;  // (k_adj_reg has no layer variants)
   const int b = std::min(L, sizeof(R) == 4 ? 4 : 3);  // 128-byte contiguous runs
   const uint64_t low = (uint64_t(1) << b) - 1;
   std::vector<std::vector<int>> pass_ops;

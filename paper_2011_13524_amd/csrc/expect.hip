@@ -568,7 +568,9 @@ ExpPlan* build_exp_plan(const qsv_observable* o, qsv_dtype dt) {
   int Ldef = dt == QSV_C64 ? 12 : 11;
   if (const char* e = std::getenv("QSV_EXPECT_TILE")) Ldef = std::max(6, std::min(Ldef, std::atoi(e)));
   p->L = std::min(n, Ldef);
-  p->b = std::min(p->L, dt == QSV_C64 ? 4 : 3);  // 128-byte contiguous runs
+  int bdef = dt == QSV_C64 ? 4 : 3;  // 128-byte contiguous runs
+  if (const char* e = std::getenv("QSV_EXPECT_LOW")) bdef = std::max(1, std::min(8, std::atoi(e)));
+  p->b = std::min(p->L, bdef);
   const int L = p->L, b = p->b;
   const uint64_t low = (uint64_t(1) << b) - 1;
   std::vector<int> rem(groups.size());

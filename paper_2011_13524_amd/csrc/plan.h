@@ -61,8 +61,9 @@ constexpr int kRegMaxThreadBits = 9;   // up to 512-thread workgroups
 struct RegSegDev {
   int reg[kRegMaxBits];        // local positions of register-index bits, ascending
   int thr[kRegMaxThreadBits];  // local position of thread-index bit k
-  int xwave;                   // re-map into this layout: 0 within wavefronts, 1 across
-                               // them, 2 across them after a workgroup barrier
+  int xwave;                   // re-map into this layout: bit 0 across wavefronts (a
+                               // barrier between writes and reads; none after the
+                               // reads), bit 1 a workgroup barrier before the writes
   int op_begin, op_count;
   // the re-map into this layout writes local index x of the previous layout
   // to position M x ^ mcst (folded X / controlled-X ops); mcol[p] = M e_p
@@ -83,7 +84,8 @@ struct RegSegDev {
 struct RegOpDev {
   int kind;             // 0 dense one-qubit, 1 dense two-qubit, 2 diagonal (k <= 2), 3 via LDS,
                         // 4 Pauli-X exchange on one register bit; reverse sweep: 5 gradient of an
-                        // X/Y rotation on register bit p1, 6 gradient of a Z rotation (dsrc/dbit[0])
+                        // X/Y rotation on register bit p1, 6 gradient of a Z rotation (dsrc/dbit[0]),
+                        // 8 gradient of a Pauli string; 10 layer of one-qubit ops (lm)
   int p1, p2;           // register bits of matrix index bits 0 and 1
   int k;
   int dsrc[2], dbit[2]; // diagonal targets: source 0 register bit, 1 thread bit, 2 global qubit
@@ -93,7 +95,10 @@ struct RegOpDev {
   int moff;
   int lop;              // index of the equivalent TileOpDev (LDS execution)
   int aux;              // gradient: slot of its row in the pass
-  int key;              // kinds 0, 1, 2, 4: variant of the register op (reg_key)
+  int key;              // kinds 0, 1, 2, 4, 10: variant of the register op (reg_key)
+  // kind 10: a layer of uncontrolled dense one-qubit ops on distinct register
+  // bits 0..3 in one dispatch; lm[p]: pool offset of the matrix on bit p
+  int lm[4];
   // kind 8 (reverse sweep): gradient term of a multi-qubit Pauli rotation,
   // evaluated with psi staged in LDS: the partner of element i sits at its LDS
   // address XOR pf_lds; the sign parity is that of (i & pz_reg), (thread index
@@ -109,6 +114,7 @@ struct SegCfg {
   int reg_bits, thread_bits;
   bool c64;  // complex64: the HBM layouts keep local bit 0 in registers (16-byte pairs)
   bool mfma = false;  // complex64: uncontrolled dense one-qubit ops on the matrix cores
+  bool layers = true;  // group one-qubit ops on distinct register bits into layer ops
 };
 
 // Whether complex64 register segments put uncontrolled dense one-qubit ops on

@@ -605,9 +605,15 @@ int build_reg_segments(const SegCfg& cfg, const std::vector<TileOpDev>& ho, Tile
   // into other wavefronts' regions of the old layout; after a wave-local re-map
   // (no trailing barrier) those wavefronts may still be reading there, so such
   // a re-map also waits for the workgroup before writing.
+  // A cross-wave re-map does not close with a barrier: waves go on with the
+  // segment's register ops, and the barrier moves to the next LDS write (the
+  // next re-map's, or an op through LDS, which always waits first). Until then
+  // other waves may still read any region, so the next re-map waits first.
   std::vector<char> pre(K, 0);
-  for (int k = 2; k < K; ++k)
+  for (int k = 2; k < K; ++k) {
     if (segs[k].xwave && !segs[k - 1].xwave && (ftarget[k] & segs[k - 1].w)) pre[k] = 1;
+    if (segs[k - 1].xwave) pre[k] = 1;
+  }
 
   for (Seg& s : segs) {
     RegSegDev sd{};
@@ -647,15 +653,37 @@ int build_reg_segments(const SegCfg& cfg, const std::vector<TileOpDev>& ho, Tile
         sd.thr[nt++] = pos;
       }
     if (nr != RB || nt != TB) return fail(QSV_EINVAL, "internal: bad segment layout");
-    sd.xwave = s.xwave ? 1 : 0;
-    if (pre[&s - segs.data()]) sd.xwave = 2;
+    sd.xwave = (s.xwave ? 1 : 0) | (pre[&s - segs.data()] ? 2 : 0);
     {
       const int k = int(&s - segs.data());
       for (int q = 0; q < L; ++q) sd.mcol[q] = mcol[k][q];
       sd.mcst = mcst[k];
     }
     sd.op_begin = int(out_rops.size());
-    sd.op_count = int(s.ops.size());
+    // runs of uncontrolled dense one-qubit ops on distinct register bits 0..3
+    // become one layer op (one dispatch: the op loop's scalar work per op --
+    // descriptor loads, control checks, the branch tree over the variants --
+    // costs as much as a one-qubit op's arithmetic)
+    const char* lay_env = std::getenv("QSV_TILE_LAYERS");  // "0": one dispatch per op (comparison)
+    const bool use_layers = cfg.layers && !(lay_env && lay_env[0] == '0');
+    int lay_mask = 0;
+    int lay_moff[4] = {0, 0, 0, 0};
+    RegOpDev lay_first{};
+    auto flush_layer = [&]() {
+      if (lay_mask == 0) return;
+      if (__builtin_popcount(lay_mask) == 1) {
+        out_rops.push_back(lay_first);
+      } else {
+        RegOpDev lr{};
+        lr.kind = 10;
+        lr.moff = lay_first.moff;
+        lr.lop = lay_first.lop;
+        for (int p = 0; p < 4; ++p) lr.lm[p] = (lay_mask >> p & 1) ? lay_moff[p] : 0;
+        lr.key = reg_key(10, lay_mask, cfg.c64 && cfg.mfma ? 1 : 0, false);
+        out_rops.push_back(lr);
+      }
+      lay_mask = 0;
+    };
     for (int li : s.ops) {
       const int oi = d.op_begin + li;
       const TileOpDev& o = ho[oi];
@@ -748,8 +776,20 @@ int build_reg_segments(const SegCfg& cfg, const std::vector<TileOpDev>& ho, Tile
         if (b >= 0 && b < a) std::swap(a, b);
         r.key = reg_key(2, a, b, r.ri_cm != 0 || r.ti_cm != 0);
       }
+      const bool layerable = use_layers && r.kind == 0 && o.kind == 0 && o.k == 1 && !o.xswap && r.ri_cm == 0 &&
+                             r.ti_cm == 0 && r.gcm == 0 && r.p1 >= 0 && r.p1 < 4;
+      if (layerable) {
+        if (lay_mask >> r.p1 & 1) flush_layer();  // (same qubit: keep the order)
+        if (lay_mask == 0) lay_first = r;
+        lay_mask |= 1 << r.p1;
+        lay_moff[r.p1] = r.moff;
+        continue;
+      }
+      flush_layer();
       out_rops.push_back(r);
     }
+    flush_layer();
+    sd.op_count = int(out_rops.size()) - sd.op_begin;
     out_segs.push_back(sd);
     d.seg_count++;
   }

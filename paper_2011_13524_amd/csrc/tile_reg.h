@@ -203,6 +203,83 @@ __device__ __forceinline__ void reg_dense1_mfma(const cx<float>* v, cx<float>* o
   }
 }
 
+// A layer of uncontrolled dense one-qubit ops on distinct register bits (the
+// bits of MASK, applied in bit order: ops on distinct qubits commute), in one
+// dispatch: the per-op scalar work of the op loop (descriptor loads, control
+// checks, the branch tree over the variants) is shared by the whole layer.
+// The first step reads v and writes every element of o; later steps update o
+// in place (no temporary copy of the tile: the register budget keeps four
+// workgroups per compute unit). The matrix of bit p is at pool + lm[p].
+template <typename R, int NR, int P>
+__device__ __forceinline__ void lay_dense1(const cx<R>* src, cx<R>* dst, const cx<R>* __restrict__ m) {
+  const cx<R> m00 = m[0], m01 = m[1], m10 = m[2], m11 = m[3];
+#pragma unroll
+  for (int g = 0; g < NR / 2; ++g) {
+    const int i = ins1<P>(g), j = i | (1 << P);
+    const cx<R> a = src[i], b = src[j];
+    dst[i] = cfma(m00, a, m01 * b);
+    dst[j] = cfma(m10, a, m11 * b);
+  }
+}
+
+// The same on the matrix cores (complex64; see reg_dense1_mfma), four pairs'
+// accumulation chains interleaved at a time.
+template <int NR, int P>
+__device__ __forceinline__ void lay_dense1_mfma(const cx<float>* src, cx<float>* dst,
+                                                const cx<float>* __restrict__ m) {
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  const uint32_t lane = threadIdx.x & 63u;
+  const bool hi = (lane & 2u) != 0, odd = (lane & 1u) != 0;
+  const cx<float> m00 = m[0], m01 = m[1], m10 = m[2], m11 = m[3];
+  const float c0r = hi ? m10.re : m00.re, c0i = hi ? m10.im : m00.im;
+  const float c1r = hi ? m11.re : m01.re, c1i = hi ? m11.im : m01.im;
+  const float a0 = odd ? c0i : c0r, a1 = odd ? c0r : -c0i;
+  const float a2 = odd ? c1i : c1r, a3 = odd ? c1r : -c1i;
+  constexpr int C = NR / 2 < 4 ? NR / 2 : 4;
+#pragma unroll
+  for (int g0 = 0; g0 < NR / 2; g0 += C) {
+    v4f d[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      d[c] = __builtin_amdgcn_mfma_f32_4x4x1f32(a0, src[ins1<P>(g0 + c)].re, v4f{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+    for (int c = 0; c < C; ++c) d[c] = __builtin_amdgcn_mfma_f32_4x4x1f32(a1, src[ins1<P>(g0 + c)].im, d[c], 0, 0, 0);
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      d[c] = __builtin_amdgcn_mfma_f32_4x4x1f32(a2, src[ins1<P>(g0 + c) | (1 << P)].re, d[c], 0, 0, 0);
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      d[c] = __builtin_amdgcn_mfma_f32_4x4x1f32(a3, src[ins1<P>(g0 + c) | (1 << P)].im, d[c], 0, 0, 0);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int i = ins1<P>(g0 + c), j = i | (1 << P);
+      dst[i] = {d[c][0], d[c][1]};
+      dst[j] = {d[c][2], d[c][3]};
+    }
+  }
+}
+
+template <typename R, int NR, int P, bool MF>
+__device__ __forceinline__ void lay_step(const cx<R>* src, cx<R>* dst, const cx<R>* __restrict__ m) {
+  if constexpr ((1 << P) >= NR) {  // no such register bit (never selected)
+    if (src != dst) reg_copy<R, NR>(src, dst);
+  } else if constexpr (MF && sizeof(R) == 4) {
+    lay_dense1_mfma<NR, P>(src, dst, m);
+  } else {
+    lay_dense1<R, NR, P>(src, dst, m);
+  }
+}
+
+template <typename R, int NR, int MASK, bool MF>
+__device__ __forceinline__ void reg_layer(const cx<R>* v, cx<R>* o, const cx<R>* __restrict__ pool,
+                                          const int* lm) {
+  constexpr int F = (MASK & 1) ? 0 : (MASK & 2) ? 1 : (MASK & 4) ? 2 : 3;
+  lay_step<R, NR, F, MF>(v, o, pool + lm[F]);
+  if constexpr (F < 1 && (MASK & 2)) lay_step<R, NR, 1, MF>(o, o, pool + lm[1]);
+  if constexpr (F < 2 && (MASK & 4)) lay_step<R, NR, 2, MF>(o, o, pool + lm[2]);
+  if constexpr (F < 3 && (MASK & 8)) lay_step<R, NR, 3, MF>(o, o, pool + lm[3]);
+}
+
 // Pauli-X exchange (X, CNOT on register bits): moves only.
 template <typename R, int NR, int P, bool HASC>
 __device__ __forceinline__ void reg_swap1(const cx<R>* v, cx<R>* o, uint32_t cm, uint32_t cv, bool lane) {
@@ -300,20 +377,48 @@ __device__ __forceinline__ void reg_diag(const cx<R>* v, cx<R>* o, const cx<R>* 
     else __builtin_unreachable();                                                \
     break;
 
+#define QSV_CL(MASK)                                                             \
+  case 320 + (MASK):                                                             \
+    reg_layer<R, NR, MASK, false>(v, o, pool, lm);                               \
+    break;                                                                       \
+  case 336 + (MASK):                                                             \
+    if constexpr (sizeof(R) == 4) reg_layer<R, NR, MASK, true>(v, o, pool, lm);  \
+    else __builtin_unreachable();                                                \
+    break;
+#define QSV_CLP                                                                  \
+  QSV_CL(3) QSV_CL(5) QSV_CL(6) QSV_CL(7) QSV_CL(9) QSV_CL(10) QSV_CL(11)        \
+  QSV_CL(12) QSV_CL(13) QSV_CL(14) QSV_CL(15)
+
 // kind 0 dense one-qubit, 1 dense two-qubit, 2 diagonal, 4 Pauli-X exchange,
-// 7 dense one-qubit on the matrix cores (complex64, no controls); a, b:
-// register bits (diagonal: -1 when absent, a < b)
+// 7 dense one-qubit on the matrix cores (complex64, no controls), 10 layer of
+// dense one-qubit ops on the register bits of mask a (at least two; b = 1:
+// on the matrix cores); a, b: register bits (diagonal: -1 when absent, a < b)
 __host__ __device__ __forceinline__ int reg_key(int kind, int a, int b, bool hc) {
   const int h = hc ? 1 : 0;
   if (kind == 7) return 288 + a;
+  if (kind == 10) return (b ? 336 : 320) + a;
   if (kind == 1) return 32 + h * 64 + a * 8 + b;
   if (kind == 2) return 160 + h * 64 + (a + 1) * 8 + (b + 1);
   return ((kind == 4) * 2 + h) * 8 + a;
 }
 
-template <typename R, int NR>
+// LAY: the layer variants are compiled in (the forward tile kernel; the
+// reverse sweep, whose two register-resident states leave no room for them,
+// leaves them out and its planner emits none).
+template <typename R, int NR, bool LAY = true>
 __device__ __forceinline__ void reg_apply(const cx<R>* v, cx<R>* o, int key, const cx<R>* m, const cx<R>* g,
-                                          uint32_t cm, uint32_t cv, bool lane) {
+                                          uint32_t cm, uint32_t cv, bool lane, const cx<R>* __restrict__ pool,
+                                          const int* lm) {
+  if constexpr (LAY) {
+    if (key >= 320) {
+      switch (key) {
+        QSV_CLP
+        default:
+          __builtin_unreachable();
+      }
+      return;
+    }
+  }
   switch (key) {
     QSV_C1P(0, 0) QSV_C1P(0, 1) QSV_C1P(1, 0) QSV_C1P(1, 1)
     QSV_C2P4(0) QSV_C2P4(1)
@@ -344,6 +449,8 @@ __device__ __forceinline__ void reg_apply(const cx<R>* v, cx<R>* o, int key, con
 #undef QSV_CDP4
 #undef QSV_CDP5
 #undef QSV_CM
+#undef QSV_CL
+#undef QSV_CLP
 
 // Factor table of a diagonal op (k <= 2) for this thread: index bits from
 // thread and non-local targets are fixed; register targets become the bits
@@ -445,6 +552,7 @@ __device__ __forceinline__ void reg_step(const RegOpDev& opr, const cx<R>* v, cx
   const cx<R>* m = pool + op.moff;
   if (op.kind == 3) {
     const LdsMap<R, RB, TB> ms(S.get_reg, S.get_tcol, 0u, tau);
+    __syncthreads();  // (a preceding cross-wave re-map's reads are done)
 #pragma unroll
     for (int i = 0; i < NR; ++i) ms.put(smem, i, v[i]);
     __syncthreads();
@@ -459,11 +567,20 @@ __device__ __forceinline__ void reg_step(const RegOpDev& opr, const cx<R>* v, cx
   int a = op.p1, bb = op.p2;
   if (op.kind == 2) diag_table<R>(op, m, tau, base, g, a, bb);
   const bool lane = (tau & op.ti_cm) == op.ti_cv;
-  reg_apply<R, NR>(v, o, op.key, m, g, op.ri_cm, op.ri_cv, lane);
+  reg_apply<R, NR>(v, o, op.key, m, g, op.ri_cm, op.ri_cv, lane, pool, op.lm);
+}
+
+// Register budget (the launch bound's second argument: wavefronts per SIMD):
+// complex64 tiles of 16 amplitudes per thread keep four (128 VGPRs; with 32
+// KiB of LDS per 256 threads, four workgroups of 256 or two of 512 per compute
+// unit); wider tiles and complex128 take what they need.
+template <typename R, int RB>
+constexpr int tile_waves_per_simd() {
+  return (sizeof(R) == 4 && RB == 4) ? 4 : 1;
 }
 
 template <typename R, int RB, int KMAX, int TB>
-__global__ void __launch_bounds__(1 << TB)
+__global__ void __launch_bounds__(1 << TB, (tile_waves_per_simd<R, RB>()))
     k_tile_reg(R* __restrict__ psi, const TilePassDev* __restrict__ passes, int pass_idx,
                const RegSegDev* __restrict__ segs, const RegOpDev* __restrict__ rops,
                const TileOpDev* __restrict__ lops, const cx<R>* __restrict__ pool) {
@@ -515,8 +632,8 @@ __global__ void __launch_bounds__(1 << TB)
       // both layouts share the wave bits (and no folded op targets one), every
       // wavefront reads back only what it wrote, and LDS operations of one
       // wavefront complete in order: no workgroup barrier is needed
-      const bool xw = Sn->xwave != 0;
-      if (Sn->xwave == 2) __syncthreads();
+      const bool xw = (Sn->xwave & 1) != 0;
+      if (Sn->xwave & 2) __syncthreads();
       {
         const LdsMap<R, RB, TB> mo(Sn->put_reg, Sn->put_tcol, Sn->put_tcst, tau);
 #pragma unroll
@@ -529,8 +646,10 @@ __global__ void __launch_bounds__(1 << TB)
 #pragma unroll
         for (int i = 0; i < NR; ++i) v[i] = mn.get(smem, i);
       }
-      if (xw) __syncthreads();
-      else wave_sync();
+      // a cross-wave re-map's closing barrier waits for the next LDS write
+      // (marked on the next re-map; ops through LDS always wait first), so
+      // the segment's register ops overlap the wavefronts' skew
+      if (!xw) wave_sync();
     }
     S = Sn;
     // ops alternate between the register arrays v and w (one op reads one and

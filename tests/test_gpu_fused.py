@@ -216,13 +216,17 @@ def test_commuting_diagonal_blocks_run_ahead(dt):
         assert np.max(np.abs(got - ref)) <= AMP_TOL[dt], (kw, info)
 
 
+@pytest.mark.parametrize("layers", ["1", "0"])
 @pytest.mark.parametrize("mfma", ["1", "0"])
 @pytest.mark.parametrize("tb,tile", [("8", 0), ("9", 13), ("8", 13), ("7", 11)])
-def test_one_qubit_ops_matrix_cores_and_vector_alu(mfma, tb, tile, monkeypatch):
+def test_one_qubit_ops_matrix_cores_and_vector_alu(layers, mfma, tb, tile, monkeypatch):
     # complex64 register tiles run uncontrolled dense one-qubit ops on the
-    # matrix cores by default (QSV_TILE_MFMA=0: vector ALU); Haar gates on
-    # every qubit (every register bit of every segment) with CZ and CNOT
-    # layers between them, both forms against the oracle
+    # matrix cores by default (QSV_TILE_MFMA=0: vector ALU), grouped into
+    # layer ops of up to four register bits (QSV_TILE_LAYERS=0: one op per
+    # dispatch); Haar gates on every qubit (every register bit of every
+    # segment) with CZ and CNOT layers between them, every form against the
+    # oracle
+    monkeypatch.setenv("QSV_TILE_LAYERS", layers)
     monkeypatch.setenv("QSV_TILE_MFMA", mfma)
     monkeypatch.setenv("QSV_TILE_THREAD_BITS", tb)
     n = 16
