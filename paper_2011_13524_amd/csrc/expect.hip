@@ -4,8 +4,9 @@
 // from any tile of the state whose local qubits include every qubit of F: both
 // members of each pair are then in the same tile. The host groups the
 // observable's flip masks into passes: a pass fixes L local qubits (always the
-// low b ones, for contiguous HBM runs) and greedily packs the flip masks that
-// need the fewest extra local qubits until the set is full. Each pass reads the
+// low b ones, for contiguous HBM runs) chosen to hold as many flip masks as it
+// can (pick_pass_local below); a mask with more flip qubits than a tile holds
+// is evaluated on its own, its pairs read straight from the state. Each pass reads the
 // state once into LDS, tile by tile, and evaluates every group of the pass on
 // it. Workgroups are persistent and prefetch their next tile while computing
 // on the current one; each sums its tiles in a fixed order into one FP64
@@ -89,13 +90,24 @@ uint64_t exp_grid_max() {
   return kExpGrid;
 }
 
+// A group whose flip mask has more qubits than a tile holds (with the low
+// ones): its terms are wide_terms[term_begin, term_begin + term_count), with
+// zg the whole sign mask.
+struct ExpWide {
+  uint64_t flip;
+  int hbit;  // highest bit of flip
+  int term_begin, term_count;
+};
+
 struct ExpPlan {
   int n = 0, L = 0, b = 0;
   std::vector<ExpPassDev> passes;
   std::vector<ExpGroupDev> groups;
   std::vector<ExpTermDev> terms;
-  void* dev = nullptr;  // passes | groups | terms
-  size_t off_groups = 0, off_terms = 0;
+  std::vector<ExpWide> wide;
+  std::vector<ExpTermDev> wide_terms;
+  void* dev = nullptr;  // passes | groups | terms | wide_terms
+  size_t off_groups = 0, off_terms = 0, off_wide = 0;
   int device = -1;
 };
 
@@ -533,6 +545,74 @@ __global__ void __launch_bounds__(kExpThreads)
   }
 }
 
+// Groups whose flip mask F has more qubits than a tile holds: the pairs
+// (x, x ^ F), x with the highest bit h of F clear, are read straight from the
+// state (both members of a pair in one thread; consecutive threads read
+// consecutive x). Each workgroup walks the pair indices in a fixed
+// grid-stride order and adds its FP64 sum to partial[blockIdx.x], the
+// partials of the tiled passes (same grid), so the value stays bitwise
+// reproducible.
+template <typename R>
+__global__ void __launch_bounds__(kExpThreadsE)
+    k_expect_wide(const R* __restrict__ psi, uint64_t flip, int hbit, const ExpTermDev* __restrict__ terms,
+                  int nt, uint64_t pairs, double* __restrict__ partial, int accumulate) {
+  __shared__ double red[kExpThreadsE / 64];
+  const uint64_t stride = uint64_t(gridDim.x) * kExpThreadsE;
+  const uint64_t lowm = (uint64_t(1) << hbit) - 1;
+  double acc = 0.0;
+  for (uint64_t i = uint64_t(blockIdx.x) * kExpThreadsE + threadIdx.x; i < pairs; i += stride) {
+    const uint64_t x = ((i & ~lowm) << 1) | (i & lowm);
+    const cx<R> a = load1(psi, x), bb = load1(psi, x ^ flip);
+    // w = conj(psi[y]) psi[x]
+    const double wr = double(bb.re) * a.re + double(bb.im) * a.im;
+    const double wi = double(bb.re) * a.im - double(bb.im) * a.re;
+    double cr = 0.0, ci = 0.0;
+    for (int k = 0; k < nt; ++k) {
+      const ExpTermDev T = terms[k];
+      const bool neg = __popcll(x & T.zg) & 1;
+      cr += neg ? -T.re : T.re;
+      ci += neg ? -T.im : T.im;
+    }
+    acc += 2.0 * (wr * cr - wi * ci);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < kExpThreadsE / 64; ++w) r += red[w];
+    partial[blockIdx.x] = accumulate ? partial[blockIdx.x] + r : r;
+  }
+}
+
+// lambda_y (+)= c(x) psi_x, x = y ^ F, for one group whose flip mask F has
+// more qubits than a tile holds (c(x) as in the tiled passes, in FP64; the
+// sum is stored in the amplitude precision).
+template <typename R>
+__global__ void __launch_bounds__(kExpThreads)
+    k_apply_obs_wide(const R* __restrict__ psi, R* __restrict__ lam, uint64_t flip,
+                     const ExpTermDev* __restrict__ terms, int nt, uint64_t N, int accumulate) {
+  const uint64_t stride = uint64_t(gridDim.x) * kExpThreads;
+  for (uint64_t y = uint64_t(blockIdx.x) * kExpThreads + threadIdx.x; y < N; y += stride) {
+    const uint64_t x = y ^ flip;
+    const cx<R> v = load1(psi, x);
+    double cr = 0.0, ci = 0.0;
+    for (int k = 0; k < nt; ++k) {
+      const ExpTermDev T = terms[k];
+      const bool neg = __popcll(x & T.zg) & 1;
+      cr += neg ? -T.re : T.re;
+      ci += neg ? -T.im : T.im;
+    }
+    cx<R> r{R(cr * double(v.re) - ci * double(v.im)), R(cr * double(v.im) + ci * double(v.re))};
+    if (accumulate) {
+      const cx<R> old = load1(lam, y);
+      r = {old.re + r.re, old.im + r.im};
+    }
+    store1(lam, y, r);
+  }
+}
+
 __global__ void __launch_bounds__(kExpThreads)
     k_exp_sum(const double* __restrict__ partial, uint64_t count, double* __restrict__ out) {
   __shared__ double red[kExpThreads / 64];
@@ -553,8 +633,66 @@ namespace {
 
 int popc64(uint64_t x) { return __builtin_popcountll(x); }
 
-// Pack flip masks into passes (greedy: repeatedly add the mask needing the
-// fewest extra local qubits while the local set stays within L).
+// Local qubit set of the next pass, given the flip masks hi (low qubits
+// removed) of the groups not yet evaluated; low: the always-local low qubits.
+// The set is grown from a seed mask by adding, one at a time, the mask that
+// needs the fewest new local qubits (ties: the one after which most masks lie
+// inside the set), up to L qubits; of the sets grown from up to kPackSeeds
+// seeds (spread over the list), the one holding the most masks is kept. On
+// random weight-4 strings at 30 qubits this takes 21 passes where adding
+// masks to one set in list order takes 26.
+constexpr int kPackSeeds = 64, kPackTies = 8;
+
+uint64_t pick_pass_local(const std::vector<uint64_t>& hi, uint64_t low, int L) {
+  const size_t nm = hi.size();
+  auto inside = [&](uint64_t loc) {
+    int c = 0;
+    for (uint64_t g : hi) c += (g & ~loc) == 0;
+    return c;
+  };
+  uint64_t best = low;
+  int best_cov = -1;
+  const size_t ns = std::min<size_t>(nm, kPackSeeds);
+  std::vector<uint64_t> ties;
+  for (size_t si = 0; si < ns; ++si) {
+    uint64_t local = low | hi[si * nm / ns];
+    while (true) {
+      int mn = 65;
+      ties.clear();
+      for (uint64_t f : hi) {
+        const uint64_t nf = f & ~local;
+        if (!nf || popc64(local | f) > L) continue;
+        const int need = popc64(nf);
+        if (need < mn) {
+          mn = need;
+          ties.assign(1, f);
+        } else if (need == mn && int(ties.size()) < kPackTies) {
+          ties.push_back(f);
+        }
+      }
+      if (ties.empty()) break;
+      uint64_t pick = ties[0];
+      if (ties.size() > 1) {
+        int pc = -1;
+        for (uint64_t f : ties) {
+          const int c = inside(local | f);
+          if (c > pc) {
+            pc = c;
+            pick = f;
+          }
+        }
+      }
+      local |= pick;
+    }
+    const int c = inside(local);
+    if (c > best_cov) {
+      best_cov = c;
+      best = local;
+    }
+  }
+  return best;
+}
+
 ExpPlan* build_exp_plan(const qsv_observable* o, qsv_dtype dt) {
   std::vector<Group> groups;
   std::vector<GTerm> terms;
@@ -573,27 +711,28 @@ ExpPlan* build_exp_plan(const qsv_observable* o, qsv_dtype dt) {
   p->b = std::min(p->L, bdef);
   const int L = p->L, b = p->b;
   const uint64_t low = (uint64_t(1) << b) - 1;
-  std::vector<int> rem(groups.size());
-  for (size_t i = 0; i < groups.size(); ++i) rem[i] = int(i);
-  while (!rem.empty()) {
-    uint64_t local = low;
-    std::vector<int> chosen;
-    while (true) {
-      int best = -1, bc = 1 << 30;
-      for (size_t r = 0; r < rem.size(); ++r) {
-        const uint64_t f = groups[rem[r]].flip;
-        if (popc64(local | f) > L) continue;
-        const int need = popc64(f & ~local);
-        if (need < bc) {
-          bc = need;
-          best = int(r);
-        }
-      }
-      if (best < 0) break;
-      local |= groups[rem[best]].flip;
-      chosen.push_back(rem[best]);
-      rem.erase(rem.begin() + best);
+  std::vector<int> rem;
+  for (size_t i = 0; i < groups.size(); ++i) {
+    if (popc64(groups[i].flip | low) <= L) {
+      rem.push_back(int(i));
+      continue;
     }
+    // more flip qubits than a tile holds: evaluated on its own, pairs read
+    // straight from the state
+    const Group& G = groups[i];
+    ExpWide w{G.flip, 63 - __builtin_clzll(G.flip), int(p->wide_terms.size()), G.count};
+    for (int k = G.begin; k < G.begin + G.count; ++k)
+      p->wide_terms.push_back(ExpTermDev{terms[k].re, terms[k].im, terms[k].z, 0u, 0u});
+    p->wide.push_back(w);
+  }
+  while (!rem.empty()) {
+    std::vector<uint64_t> hi;
+    for (int r : rem) hi.push_back(groups[r].flip & ~low);
+    const uint64_t local0 = pick_pass_local(hi, low, L);
+    std::vector<int> chosen, rest;
+    for (int r : rem) ((groups[r].flip & ~local0) == 0 ? chosen : rest).push_back(r);
+    rem.swap(rest);
+    uint64_t local = local0;
     for (int q = 0; q < n && popc64(local) < L; ++q) local |= uint64_t(1) << q;
     std::vector<int> lpos(64, -1), loc;
     for (int q = 0; q < 64; ++q)
@@ -664,13 +803,17 @@ int upload_exp_plan(ExpPlan* p, int device) {
   p->off_groups = (a + 255) / 256 * 256;
   const size_t bsz = p->groups.size() * sizeof(ExpGroupDev);
   p->off_terms = (p->off_groups + bsz + 255) / 256 * 256;
-  const size_t total = p->off_terms + std::max<size_t>(1, p->terms.size()) * sizeof(ExpTermDev);
+  p->off_wide = (p->off_terms + p->terms.size() * sizeof(ExpTermDev) + 255) / 256 * 256;
+  const size_t total = p->off_wide + std::max<size_t>(1, p->wide_terms.size()) * sizeof(ExpTermDev);
   if (hipMalloc(&p->dev, total) != hipSuccess) return fail(QSV_ENOMEM, "observable plan allocation failed");
   char* d = static_cast<char*>(p->dev);
-  QSV_HIP_CHECK(hipMemcpy(d, p->passes.data(), a, hipMemcpyHostToDevice));
+  if (a) QSV_HIP_CHECK(hipMemcpy(d, p->passes.data(), a, hipMemcpyHostToDevice));
   if (bsz) QSV_HIP_CHECK(hipMemcpy(d + p->off_groups, p->groups.data(), bsz, hipMemcpyHostToDevice));
   if (!p->terms.empty())
     QSV_HIP_CHECK(hipMemcpy(d + p->off_terms, p->terms.data(), p->terms.size() * sizeof(ExpTermDev),
+                            hipMemcpyHostToDevice));
+  if (!p->wide_terms.empty())
+    QSV_HIP_CHECK(hipMemcpy(d + p->off_wide, p->wide_terms.data(), p->wide_terms.size() * sizeof(ExpTermDev),
                             hipMemcpyHostToDevice));
   p->device = device;
   return QSV_OK;
@@ -680,7 +823,7 @@ template <typename R>
 int expect_tiled_t(qsv_state* s, qsv_observable* o, double* out) {
   ExpPlan*& pl = o->exp_plan[s->dtype];
   if (!pl) pl = build_exp_plan(o, s->dtype);
-  if (pl->passes.empty()) {
+  if (pl->passes.empty() && pl->wide.empty()) {
     *out = 0.0;
     return QSV_OK;
   }
@@ -715,6 +858,15 @@ int expect_tiled_t(qsv_state* s, qsv_observable* o, double* out) {
                          pd, int(pi), gd, td, s->red, pi > 0 ? 1 : 0, tiles);
     QSV_HIP_CHECK(hipGetLastError());
   }
+  const auto* wt = reinterpret_cast<const ExpTermDev*>(d + pl->off_wide);
+  for (size_t wi = 0; wi < pl->wide.size(); ++wi) {
+    ProfScope ps("expect_wide", double(sizeof(cx<R>)) * double(dim(s->n)), s->stream);
+    const ExpWide& w = pl->wide[wi];
+    hipLaunchKernelGGL((k_expect_wide<R>), dim3(unsigned(grid)), dim3(kExpThreadsE), 0, s->stream,
+                       static_cast<const R*>(s->ptr), w.flip, w.hbit, wt + w.term_begin, w.term_count,
+                       dim(s->n - 1), s->red, pl->passes.empty() && wi == 0 ? 0 : 1);
+    QSV_HIP_CHECK(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_exp_sum, dim3(1), dim3(kExpThreads), 0, s->stream, s->red, grid, s->red + grid);
   QSV_HIP_CHECK(hipGetLastError());
   QSV_HIP_CHECK(hipMemcpyAsync(s->red_host, s->red + grid, sizeof(double), hipMemcpyDeviceToHost,
@@ -729,7 +881,7 @@ int apply_obs_tiled_t(const qsv_state* in, qsv_observable* o, qsv_state* out) {
   ExpPlan*& pl = o->exp_plan[in->dtype];
   if (!pl) pl = build_exp_plan(o, in->dtype);
   const uint64_t N = dim(in->n);
-  if (pl->passes.empty()) {  // no terms: lambda = 0
+  if (pl->passes.empty() && pl->wide.empty()) {  // no terms: lambda = 0
     const uint64_t blocks = std::min<uint64_t>((N + kExpThreads - 1) / kExpThreads, 65536);
     hipLaunchKernelGGL((k_zero_amps<R>), dim3(unsigned(blocks)), dim3(kExpThreads), 0, in->stream,
                        static_cast<R*>(out->ptr), N);
@@ -760,6 +912,17 @@ int apply_obs_tiled_t(const qsv_state* in, qsv_observable* o, qsv_state* out) {
       hipLaunchKernelGGL((k_apply_obs_tile<R, false>), grid, dim3(kExpThreads), lds, in->stream,
                          static_cast<const R*>(in->ptr), static_cast<R*>(out->ptr), pd, int(pi), gd, td,
                          pi > 0 ? 1 : 0, tiles);
+    QSV_HIP_CHECK(hipGetLastError());
+  }
+  const auto* wt = reinterpret_cast<const ExpTermDev*>(d + pl->off_wide);
+  for (size_t wi = 0; wi < pl->wide.size(); ++wi) {
+    const bool acc = !pl->passes.empty() || wi > 0;
+    ProfScope ps("apply_obs_wide", double(sizeof(cx<R>)) * double(N) * (acc ? 3.0 : 2.0), in->stream);
+    const ExpWide& w = pl->wide[wi];
+    const unsigned blocks = unsigned(std::min<uint64_t>((N + kExpThreads - 1) / kExpThreads, 8192));
+    hipLaunchKernelGGL((k_apply_obs_wide<R>), dim3(blocks), dim3(kExpThreads), 0, in->stream,
+                       static_cast<const R*>(in->ptr), static_cast<R*>(out->ptr), w.flip, wt + w.term_begin,
+                       w.term_count, N, acc ? 1 : 0);
     QSV_HIP_CHECK(hipGetLastError());
   }
   return QSV_OK;
@@ -805,7 +968,7 @@ template <typename R>
 int expect_noalloc_t(qsv_state* s, qsv_observable* o, double* out) {
   ExpPlan*& pl = o->exp_plan[s->dtype];
   if (!pl) pl = build_exp_plan(o, s->dtype);  // host tables only
-  if (pl->passes.empty()) {
+  if (pl->passes.empty() && pl->wide.empty()) {
     *out = 0.0;
     return QSV_OK;
   }
@@ -816,7 +979,8 @@ int expect_noalloc_t(qsv_state* s, qsv_observable* o, double* out) {
   const size_t o_pass = al((size_t(grid) + 1) * sizeof(double));
   const size_t o_grp = o_pass + al(pl->passes.size() * sizeof(ExpPassDev));
   const size_t o_term = o_grp + al(pl->groups.size() * sizeof(ExpGroupDev));
-  const size_t need = o_term + al(pl->terms.size() * sizeof(ExpTermDev));
+  const size_t o_wide = o_term + al(pl->terms.size() * sizeof(ExpTermDev));
+  const size_t need = o_wide + al(pl->wide_terms.size() * sizeof(ExpTermDev));
   if (need > kNoAllocBytes)
     return fail(QSV_ERANGE, "observable needs %zu bytes of device scratch; the no-allocation limit is %zu",
                 need, kNoAllocBytes);
@@ -824,13 +988,17 @@ int expect_noalloc_t(qsv_state* s, qsv_observable* o, double* out) {
   int rc = noalloc_scratch(s->device, &d);
   if (rc) return rc;
   hipStream_t st = s->stream;
-  QSV_HIP_CHECK(hipMemcpyAsync(d + o_pass, pl->passes.data(), pl->passes.size() * sizeof(ExpPassDev),
-                               hipMemcpyHostToDevice, st));
+  if (!pl->passes.empty())
+    QSV_HIP_CHECK(hipMemcpyAsync(d + o_pass, pl->passes.data(), pl->passes.size() * sizeof(ExpPassDev),
+                                 hipMemcpyHostToDevice, st));
   if (!pl->groups.empty())
     QSV_HIP_CHECK(hipMemcpyAsync(d + o_grp, pl->groups.data(), pl->groups.size() * sizeof(ExpGroupDev),
                                  hipMemcpyHostToDevice, st));
   if (!pl->terms.empty())
     QSV_HIP_CHECK(hipMemcpyAsync(d + o_term, pl->terms.data(), pl->terms.size() * sizeof(ExpTermDev),
+                                 hipMemcpyHostToDevice, st));
+  if (!pl->wide_terms.empty())
+    QSV_HIP_CHECK(hipMemcpyAsync(d + o_wide, pl->wide_terms.data(), pl->wide_terms.size() * sizeof(ExpTermDev),
                                  hipMemcpyHostToDevice, st));
   double* part = reinterpret_cast<double*>(d);
   const auto* pd = reinterpret_cast<const ExpPassDev*>(d + o_pass);
@@ -855,6 +1023,14 @@ int expect_noalloc_t(qsv_state* s, qsv_observable* o, double* out) {
     else
       hipLaunchKernelGGL((k_expect_tile<R, 0>), dim3(unsigned(grid)), dim3(kExpThreadsE), lds, st, psi, pd,
                          int(pi), gd, td, part, pi > 0 ? 1 : 0, tiles);
+    QSV_HIP_CHECK(hipGetLastError());
+  }
+  const auto* wt = reinterpret_cast<const ExpTermDev*>(d + o_wide);
+  for (size_t wi = 0; wi < pl->wide.size(); ++wi) {
+    const ExpWide& w = pl->wide[wi];
+    hipLaunchKernelGGL((k_expect_wide<R>), dim3(unsigned(grid)), dim3(kExpThreadsE), 0, st, psi, w.flip, w.hbit,
+                       wt + w.term_begin, w.term_count, dim(s->n - 1), part,
+                       pl->passes.empty() && wi == 0 ? 0 : 1);
     QSV_HIP_CHECK(hipGetLastError());
   }
   hipLaunchKernelGGL(k_exp_sum, dim3(1), dim3(kExpThreads), 0, st, part, grid, part + grid);
@@ -888,7 +1064,7 @@ int expectation_passes(const qsv_observable* o, qsv_dtype dt) {
   qsv_observable* mo = const_cast<qsv_observable*>(o);
   ExpPlan*& pl = mo->exp_plan[dt];
   if (!pl) pl = build_exp_plan(mo, dt);
-  return int(pl->passes.size());
+  return int(pl->passes.size() + pl->wide.size());
 }
 
 }  // namespace qsv

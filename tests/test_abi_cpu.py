@@ -146,9 +146,19 @@ def test_observable_pass_packing_on_host():
     o = Q.Observable(30, W.random_pauli_observable(30, 200, 4, seed_key=(2, 1)))
     n, terms, groups = o.info()
     assert (n, terms, groups) == (30, 200, 186)
-    assert o.passes("c64") <= 30 and o.passes("c128") <= 32
+    assert o.passes("c64") <= 21 and o.passes("c128") <= 22
     assert Q.Observable(4, [(1.0, [(0, 3)])]).passes("c64") == 1  # pure Z: one pass
     assert Q.Observable(4, []).passes("c64") == 0
+    # masks that share qubits land in one pass: X on every pair of 8 high
+    # qubits (28 masks) fits one 2^12 tile with the 4 low qubits
+    pairs = [(1.0, [(a, 1), (b, 1)]) for a in range(20, 28) for b in range(a + 1, 28)]
+    assert Q.Observable(30, pairs).passes("c64") == 1
+    # a mask with more flip qubits than a tile holds (with the low ones) is
+    # evaluated on its own: one more state read, and packing terminates
+    wide = [(1.0, [(q, 1) for q in range(10, 22)])]
+    assert Q.Observable(30, wide).passes("c64") == 1
+    assert Q.Observable(30, wide + pairs).passes("c64") == 2
+    assert Q.Observable(30, wide + pairs).passes("c128") == 2
 
 
 def test_merge_never_raises_arithmetic():

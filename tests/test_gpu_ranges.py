@@ -151,3 +151,61 @@ def test_adjoint_24q_vs_oracle(dt):
     assert abs(e - e_ref) <= GRAD_TOL[dt] * scale, dt
     err = np.max(np.abs(g[slots] - g_ref))
     assert err <= GRAD_TOL[dt] * scale, (dt, err)
+
+
+def wide_observable(n, seed):
+    """Strings whose X/Y factors cover more qubits than a tile holds beside
+    the low ones (9 and 10 flip qubits above qubit 3), one of them twice with
+    other Z/Y signs (a multi-term group), mixed with ordinary strings."""
+    rng = np.random.default_rng(seed)
+    hi = list(range(4, n))
+    obs = W.random_pauli_observable(n, 8, (1, 4), seed_key=(25, n, seed))
+    for w in (9, 10):
+        qs = [int(q) for q in rng.choice(hi, size=w, replace=False)]
+        ps = [int(p) for p in rng.integers(1, 3, size=w)]
+        obs.append((float(rng.standard_normal()), list(zip(qs, ps)) + [(0, 3)]))
+    flips = obs[-1][1][:-1]  # the same flip mask, X and Y swapped, other Z factors
+    obs.append((0.45, [(q, 2 if p == 1 else 1) for q, p in flips] + [(1, 3), (2, 3)]))
+    return obs
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("grid", ["0", "3"])
+def test_wide_flip_masks(dt, grid, monkeypatch):
+    # flip masks with more qubits than a tile holds are evaluated on their
+    # own, pairs read straight from the state, after the tiled passes (the
+    # same persistent partials): expectation, the no-allocation expectation,
+    # lambda = O psi and the adjoint, against the oracle; also an observable
+    # with wide masks only (no tiled pass: the first wide group writes)
+    from paper_2011_13524_amd.binding import expectation_noalloc
+    if grid != "0":
+        monkeypatch.setenv("QSV_EXPECT_GRID", grid)
+    rng = np.random.default_rng(140)
+    for n in (14, 16):
+        psi = rand_state(rng, n)
+        ref_in = as_loaded(psi, dt)
+        full = wide_observable(n, n)
+        for obs_t in (full, full[-3:]):
+            obs = Observable(n, obs_t)
+            assert obs.passes(dt) >= 2
+            scale = sum(abs(c) for c, _ in obs_t)
+            s, out = State(n, dt), State(n, dt)
+            s.load(psi)
+            e_ref = O.expectation(ref_in, obs_t)
+            assert abs(expectation(s, obs) - e_ref) <= E_LOADED[dt] * scale, (n, dt, len(obs_t))
+            assert abs(expectation_noalloc(s, obs) - e_ref) <= E_LOADED[dt] * scale, (n, dt, len(obs_t))
+            apply_observable(s, obs, out)
+            err = np.max(np.abs(out.store() - O.apply_observable(ref_in, obs_t)))
+            assert err <= LAM_TOL[dt] * scale, (n, dt, len(obs_t), err)
+    n = 14
+    gates, npar = W.ry_rz_cnot_ring(n, 1)
+    theta = W.uniform_angles(npar, (26, n))
+    obs_t = wide_observable(n, 3)
+    c = Circuit.from_records(n, gates)
+    psi, lam = State(n, dt), State(n, dt)
+    e, g = adjoint_gradient(c, theta, Observable(n, obs_t), psi, lam, Plan(c, dt, max_k=2))
+    scale = sum(abs(cf) for cf, _ in obs_t)
+    slots = [0, npar // 2, npar - 1]
+    assert abs(e - O.energy(n, gates, theta, obs_t)) <= GRAD_TOL[dt] * scale
+    err = np.max(np.abs(g[slots] - O.param_shift_grad(n, gates, theta, obs_t, slots=slots)))
+    assert err <= GRAD_TOL[dt] * scale, err
