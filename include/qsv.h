@@ -336,8 +336,13 @@ int qsv_transition_amplitude(const qsv_state* bra, const qsv_observable* o, cons
 int qsv_observable_passes(const qsv_observable* o, qsv_dtype dtype, int* passes);
 
 /* <psi|O|psi> accumulated in double (section 4.5, get_expectation_value). The
- * state is not normalised first (basic gates need not be unitary). Synchronises
- * the state's stream. */
+ * state is not normalised first (basic gates need not be unitary). Flip masks
+ * are packed into passes that each read the state once (a mask with more flip
+ * qubits than a tile holds gets a pass of its own). complex64: a single-term
+ * string's pair products, and each thread's sum of 8 of them per tile, are
+ * formed in FP32 (|error| <= 9 x 2^-24 x sum|alpha| x <psi|psi> beyond the
+ * stored amplitudes), every other sum in double. Synchronises the state's
+ * stream. */
 int qsv_expectation(const qsv_state* s, const qsv_observable* o, double* out);
 
 /* qsv_expectation for callers that cannot allocate device memory (code under

@@ -141,6 +141,9 @@ __device__ __forceinline__ double flip_sign(double v, uint32_t s) {
 __device__ __forceinline__ double xor_sign(double v, uint32_t m) {
   return __hiloint2double(__double2hiint(v) ^ int(m), __double2loint(v));
 }
+__device__ __forceinline__ float xor_sign(float v, uint32_t m) {
+  return __uint_as_float(__float_as_uint(v) ^ m);
+}
 
 __device__ __forceinline__ uint32_t ins0(uint32_t i, int hb) {
   return ((i >> hb) << (hb + 1)) | (i & ((1u << hb) - 1));
@@ -266,8 +269,8 @@ __host__ __device__ constexpr int exp_tile_bits() {
   return sizeof(R) == 4 ? 12 : 11;
 }
 
-// Re (REAL) or Im of conj(b) a. complex64: formed in FP32 (one rounding,
-// relative error <= 2^-23 of |a||b|; the caller accumulates in FP64), which
+// Re (REAL) or Im of conj(b) a. complex64: formed in FP32 (relative error
+// <= 2^-23 of |a||b|; see exp_pairs for the sums), which
 // halves the vector instructions per pair against converting all four
 // components first; complex128: FP64.
 template <typename R, bool REAL>
@@ -277,7 +280,12 @@ __device__ __forceinline__ R pair_product(const cx<R>& a, const cx<R>& b) {
 
 // One single-term group with flip mask lf != 0 over a tile: the sum over the
 // pairs (x, x ^ lf), x with bit hb clear, of Re (REAL) or Im of
-// conj(psi_y) psi_x with the term's local Z/Y sign, in FP64. x is the thread
+// conj(psi_y) psi_x with the term's local Z/Y sign. A thread's NP pair
+// products are summed in the amplitude precision (complex64: FP32, one
+// conversion to FP64 per group and thread instead of one per pair; with the
+// products' own rounding the error is at most 9 x 2^-24 of the sum of
+// |psi_x||psi_y| over the pairs, i.e. of <psi|psi>/2) and the sums over
+// threads and tiles in FP64. x is the thread
 // part xt (tx = t + xt) OR-ed with a workgroup-uniform step part xs (disjoint
 // bits); likewise y = (xt ^ (lf & thread bits)) | (xs ^ (lf outside them)),
 // so each step adds a uniform offset to two per-thread LDS pointers. The sign
@@ -286,24 +294,24 @@ __device__ __forceinline__ R pair_product(const cx<R>& a, const cx<R>& b) {
 template <typename R, bool REAL, bool FULL, int NP, int NT>
 __device__ __forceinline__ double exp_pairs(const cx<R>* tx, const cx<R>* ty, const ExpGroupDev& D, uint32_t pt,
                                             uint32_t TS, uint32_t tid) {
-  double sw = 0.0;
+  R sw = R(0);
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
     const uint32_t i0 = uint32_t(k) * NT;
     if (i0 >= TS / 2) break;
     if (FULL || i0 + tid < TS / 2) {
       const cx<R> a = tx[D.offx[k]], b = ty[D.offy[k]];
-      sw += xor_sign(double(pair_product<R, REAL>(a, b)), D.sgn[k]);
+      sw += xor_sign(pair_product<R, REAL>(a, b), D.sgn[k]);
     }
   }
-  return xor_sign(sw, pt);  // the thread's part of the sign, common to every step
+  return xor_sign(double(sw), pt);  // the thread's part of the sign, common to every step
 }
 
-// <psi|O|psi> over the tiles of one pass. Sums are FP64; the products of the
-// single-term groups are formed in the amplitude precision (for complex64 one
-// FP32 rounding per product, relative error <= 2^-23, so |dE| <= 2^-23 sum
-// |alpha| <psi|psi> beyond the stored amplitudes), those of multi-term groups
-// in FP64. Each workgroup sums its
+// <psi|O|psi> over the tiles of one pass. Sums over threads and tiles are
+// FP64; single-term groups form their products in the amplitude precision,
+// and a flip group also sums each thread's 8 pairs per tile in it
+// (complex64: |dE| <= 9 x 2^-24 sum |alpha| <psi|psi> beyond the stored
+// amplitudes, see exp_pairs); multi-term groups work in FP64. Each workgroup sums its
 // tiles in a fixed order into partial[blockIdx.x] (added to the value of
 // earlier passes when accumulate is set). MODE 0: any tile size (per-lane
 // guards); 1: the tile has at least two amplitudes per thread, so every loop
