@@ -236,6 +236,12 @@ constexpr int kAdjMaxRows = 64;  // gradient rows per pass (LDS slots)
 
 // X/Y rotation on register bit P: share of -Im<lambda|P|psi>, then
 // psi, lambda <- u psi, u lambda (u = exp(-i t P/2)); writes every slot of os, ol.
+// u = c I - i s' P has a real diagonal c and off-diagonals s' (Y: real, -s'
+// below the diagonal) or i s' (X), so each output takes two real products
+// per component instead of a complex 2x2 product. The gradient share is
+// summed in the amplitude precision over the thread's pairs (complex64:
+// FP32 products and 8-term sums, relative error <= 11 x 2^-24 of
+// sum |lambda_x||psi_y| <= |lambda||psi|; the caller sums in FP64).
 template <typename R, int NR, int P>
 __device__ __forceinline__ double grad_xy(const cx<R>* s, const cx<R>* l, cx<R>* os, cx<R>* ol, bool ypauli,
                                           const cx<R>* __restrict__ u) {
@@ -244,27 +250,33 @@ __device__ __forceinline__ double grad_xy(const cx<R>* s, const cx<R>* l, cx<R>*
     reg_copy<R, NR>(l, ol);
     return 0.0;
   }
-  const cx<R> u00 = u[0], u01 = u[1], u10 = u[2], u11 = u[3];
-  double acc = 0.0;
+  const R c = u[0].re, sn = ypauli ? u[1].re : u[1].im;
+  R acc = R(0);
 #pragma unroll
   for (int g = 0; g < NR / 2; ++g) {
     const int i = ins1<P>(g), j = i | (1 << P);
     const cx<R> a0 = s[i], a1 = s[j], l0 = l[i], l1 = l[j];
-    const double a0r = a0.re, a0i = a0.im, a1r = a1.re, a1i = a1.im;
-    const double l0r = l0.re, l0i = l0.im, l1r = l1.re, l1i = l1.im;
-    const double im = ypauli ? -(l0r * a1r + l0i * a1i) + (l1r * a0r + l1i * a0i)
-                             : (l0r * a1i - l0i * a1r) + (l1r * a0i - l1i * a0r);
+    const R im = ypauli ? fma(l1.re, a0.re, l1.im * a0.im) - fma(l0.re, a1.re, l0.im * a1.im)
+                        : fma(l0.re, a1.im, -(l0.im * a1.re)) + fma(l1.re, a0.im, -(l1.im * a0.re));
     acc -= im;
-    os[i] = cfma(u00, a0, u01 * a1);
-    os[j] = cfma(u10, a0, u11 * a1);
-    ol[i] = cfma(u00, l0, u01 * l1);
-    ol[j] = cfma(u10, l0, u11 * l1);
+    if (ypauli) {  // u = [[c, s'], [-s', c]]
+      os[i] = {fma(c, a0.re, sn * a1.re), fma(c, a0.im, sn * a1.im)};
+      os[j] = {fma(c, a1.re, -(sn * a0.re)), fma(c, a1.im, -(sn * a0.im))};
+      ol[i] = {fma(c, l0.re, sn * l1.re), fma(c, l0.im, sn * l1.im)};
+      ol[j] = {fma(c, l1.re, -(sn * l0.re)), fma(c, l1.im, -(sn * l0.im))};
+    } else {  // u = [[c, i s'], [i s', c]]
+      os[i] = {fma(c, a0.re, -(sn * a1.im)), fma(c, a0.im, sn * a1.re)};
+      os[j] = {fma(c, a1.re, -(sn * a0.im)), fma(c, a1.im, sn * a0.re)};
+      ol[i] = {fma(c, l0.re, -(sn * l1.im)), fma(c, l0.im, sn * l1.re)};
+      ol[j] = {fma(c, l1.re, -(sn * l0.im)), fma(c, l1.im, sn * l0.re)};
+    }
   }
-  return acc;
+  return double(acc);
 }
 
 // Z rotation: the bit of the target is register bit P (P >= 0) or `fixed`;
-// share of -Im<lambda|Z|psi>, then the diagonal u on both states.
+// share of -Im<lambda|Z|psi> (summed in the amplitude precision over the
+// thread's elements, as for grad_xy), then the diagonal u on both states.
 template <typename R, int NR, int P>
 __device__ __forceinline__ double grad_z(const cx<R>* s, const cx<R>* l, cx<R>* os, cx<R>* ol, int fixed,
                                          const cx<R>* __restrict__ u) {
@@ -274,18 +286,18 @@ __device__ __forceinline__ double grad_z(const cx<R>* s, const cx<R>* l, cx<R>* 
     return 0.0;
   }
   const cx<R> f0 = u[0], f1 = u[3];
-  double acc = 0.0;
+  R acc = R(0);
 #pragma unroll
   for (int i = 0; i < NR; ++i) {
     const int bit = P >= 0 ? (i >> P) & 1 : fixed;
     const cx<R> a = s[i], c = l[i];
-    const double im = double(c.re) * a.im - double(c.im) * a.re;
+    const R im = fma(c.re, a.im, -(c.im * a.re));
     acc -= bit ? -im : im;
     const cx<R> f = csel(bit != 0, f1, f0);
     os[i] = f * a;
     ol[i] = f * c;
   }
-  return acc;
+  return double(acc);
 }
 
 // Gradient op: share of the gradient from (s, l), the rotation applied into
