@@ -18,6 +18,7 @@
 #include "plan.h"
 #include "prof.h"
 #include "tile_reg.h"
+#include "wave_sum.h"
 
 namespace qsv {
 
@@ -405,17 +406,13 @@ __device__ __forceinline__ void adj_step(const RegOpDev& opr, const cx<R>* s, co
       ol[i] = c;
     }
     __syncthreads();  // every read done before the LDS tile is written again
-    double acc = neg_im_phase(sr, si, op.pph);
-#pragma unroll
-    for (int sft = 32; sft > 0; sft >>= 1) acc += __shfl_xor(acc, sft, 64);
-    if ((tau & 63) == 0) wslot[op.aux * (1 << (TB - 6))] += acc;
+    const double acc = wave_sum_to_last(neg_im_phase(sr, si, op.pph));
+    if ((tau & 63) == 63) wslot[op.aux * (1 << (TB - 6))] += acc;
     return;
   }
   if (op.kind == 5 || op.kind == 6) {
-    double acc = grad_apply<R, NR>(s, l, os, ol, op, tau, base, m);
-#pragma unroll
-    for (int sft = 32; sft > 0; sft >>= 1) acc += __shfl_xor(acc, sft, 64);
-    if ((tau & 63) == 0) wslot[op.aux * (1 << (TB - 6))] += acc;
+    const double acc = wave_sum_to_last(grad_apply<R, NR>(s, l, os, ol, op, tau, base, m));
+    if ((tau & 63) == 63) wslot[op.aux * (1 << (TB - 6))] += acc;
     return;
   }
   if (op.kind == 3) {

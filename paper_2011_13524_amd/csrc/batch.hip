@@ -21,6 +21,7 @@
 #include "dev_common.h"
 #include "observable.h"
 #include "prof.h"
+#include "wave_sum.h"
 
 namespace qsv {
 
@@ -98,11 +99,10 @@ struct BatchArgs {
 };
 
 __device__ __forceinline__ double wg_sum(double v, double* red) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v = wave_sum_to_last(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();  // red[] may still be read from the previous reduction
-  if (lane == 0) red[w] = v;
+  if (lane == 63) red[w] = v;
   __syncthreads();
   double r = 0.0;
   for (int i = 0; i < int(blockDim.x >> 6); ++i) r += red[i];  // same order in every thread
@@ -440,9 +440,8 @@ __device__ void bt_reverse(const BatchArgs& a, const BatchItem& I, cx<R>* psi, c
         const double t = op.kind == BO_PAULI ? op_angle(a.ops[I.op_begin + op.bop], theta, a.pool) : 0.0;
         double acc = bt_rev(ts, tl, op, mats, TS, base, t);
         if (op.row >= 0) {
-#pragma unroll
-          for (int sft = 32; sft > 0; sft >>= 1) acc += __shfl_xor(acc, sft, 64);
-          if ((threadIdx.x & 63) == 0) slot[op.row * NW + wave] += acc;
+          acc = wave_sum_to_last(acc);
+          if ((threadIdx.x & 63) == 63) slot[op.row * NW + wave] += acc;
         }
         __syncthreads();
       }
