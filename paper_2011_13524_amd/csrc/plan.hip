@@ -39,9 +39,6 @@
 // barrier between them, and streams the tile back. Each pass therefore reads
 // and writes the state once however many gates it applies.
 #include <algorithm>
-#include <mutex>
-#include <map>
-#include <array>
 #include <cmath>
 #include <cstdlib>
 
@@ -436,107 +433,6 @@ bool tile_mfma_default() {
   return !(e && e[0] == '0');
 }
 
-// LDS layout of one register re-map: local index j at element
-// j ^ (XOR of acol[b] over the set bits b of j >> SB), a bijection linear
-// over XOR (only the low SB bits change).
-struct LdsSwz {
-  int SB = 5;
-  uint32_t acol[16] = {};
-  uint32_t operator()(uint32_t j) const {
-    uint32_t x = j;
-    for (int b = 0; b < 16; ++b)
-      if (j >> (SB + b) & 1) x ^= acol[b];
-    return x;
-  }
-  // j ^ ((j >> SB) & m) ^ ((j >> 2 SB) & m): the layout the kernels' own LDS
-  // addressing (Swz) uses
-  static LdsSwz standard(int sb) {
-    LdsSwz s;
-    s.SB = sb;
-    for (int b = 0; b < 2 * sb && b < 16; ++b) s.acol[b] = 1u << (b % sb);
-    return s;
-  }
-};
-
-// Bank cost of one re-map under a layout: the lanes' elements (lane bit k
-// contributes lane[k] to the local index) for the write (old layout through
-// the folded map) and the read (new layout), split into the groups of lanes
-// an LDS access serves at once, each costing the largest number of lanes
-// that share a bank slot. Summed over three bank models (64 banks: slots of
-// one element over 32 or 16 lanes for complex64, 16 or 8 for complex128; 32
-// banks: half as many slots), since which the hardware uses is not assumed.
-int remap_cost(const LdsSwz& sw, const uint32_t* put_lane, const uint32_t* get_lane) {
-  const int slots = 1 << sw.SB;  // element slots per 256 bytes
-  const int models[3][2] = {{slots, slots}, {slots, slots / 2}, {slots / 2, slots / 2}};
-  int cost = 0;
-  for (const uint32_t* lv : {put_lane, get_lane}) {
-    uint32_t slot[64];
-    for (int l = 0; l < 64; ++l) {
-      uint32_t x = 0;
-      for (int k = 0; k < 6; ++k)
-        if (l >> k & 1) x ^= lv[k];
-      slot[l] = sw(x);
-    }
-    for (const auto& m : models) {
-      const uint32_t mask = uint32_t(m[0]) - 1;
-      for (int g0 = 0; g0 < 64; g0 += m[1]) {
-        int cnt[64] = {}, mx = 0;
-        for (int l = g0; l < g0 + m[1]; ++l) mx = std::max(mx, ++cnt[slot[l] & mask]);
-        cost += mx;
-      }
-    }
-  }
-  return cost;
-}
-
-// Layout of a re-map: the standard one when its lanes already meet no bank
-// conflicts, else the cheapest of up to 256 candidates drawn from a fixed
-// generator (each a random choice of acol); chosen once per (lanes, SB, L)
-// and remembered (the reverse sweep plans on every call). QSV_TILE_SWIZZLE=0
-// keeps the standard layout.
-LdsSwz remap_swizzle(int SB, int L, const uint32_t* put_lane, const uint32_t* get_lane) {
-  const char* env = std::getenv("QSV_TILE_SWIZZLE");  // "0": the standard layout everywhere (comparison)
-  if (env && env[0] == '0') return LdsSwz::standard(SB);
-  static std::mutex mu;
-  static std::map<std::array<uint32_t, 14>, LdsSwz> memo;
-  std::array<uint32_t, 14> key{};
-  for (int k = 0; k < 6; ++k) {
-    key[size_t(k)] = put_lane[k];
-    key[size_t(6 + k)] = get_lane[k];
-  }
-  key[12] = uint32_t(SB);
-  key[13] = uint32_t(L);
-  {
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = memo.find(key);
-    if (it != memo.end()) return it->second;
-  }
-  const int slots = 1 << SB;
-  const int ideal = 2 * (64 / slots + 2 * (64 / (slots / 2)));
-  LdsSwz best = LdsSwz::standard(SB);
-  int best_cost = remap_cost(best, put_lane, get_lane);
-  uint64_t r = 0x9e3779b97f4a7c15ull;
-  for (const uint32_t v : key) r = (r ^ v) * 0xbf58476d1ce4e5b9ull;
-  for (int t = 0; t < 256 && best_cost > ideal; ++t) {
-    LdsSwz c;
-    c.SB = SB;
-    for (int b = 0; b < L - SB && b < 16; ++b) {
-      r ^= r << 13;
-      r ^= r >> 7;
-      r ^= r << 17;
-      c.acol[b] = uint32_t(r >> 20) & uint32_t(slots - 1);
-    }
-    const int cst = remap_cost(c, put_lane, get_lane);
-    if (cst < best_cost) {
-      best_cost = cst;
-      best = c;
-    }
-  }
-  std::lock_guard<std::mutex> lk(mu);
-  memo.emplace(key, best);
-  return best;
-}
-
 int build_reg_segments(const SegCfg& cfg, const std::vector<TileOpDev>& ho, TilePassDev& d,
                        std::vector<RegSegDev>& out_segs, std::vector<RegOpDev>& out_rops) {
   const int RB = cfg.reg_bits, TB = cfg.thread_bits, L = d.L;
@@ -897,51 +793,37 @@ int build_reg_segments(const SegCfg& cfg, const std::vector<TileOpDev>& ho, Tile
     out_segs.push_back(sd);
     d.seg_count++;
   }
-  // LDS address tables of the pass's segments. A re-map's layout puts local
-  // index j at LDS element swz(j) = j ^ A (j >> SB), linear over XOR, so the
-  // byte offset splits into a per-thread part (XOR of per-bit columns) and a
-  // per-element part. Segments whose ops stage the tile in LDS themselves
-  // (kinds 3 and 8, which address it with the standard fold of bits SB..
-  // 2 SB - 1 and 2 SB.. onto the low ones) and the first segment keep the
-  // standard A; every other re-map takes an A under which the lanes of each
-  // of its LDS writes and reads fall in distinct banks (remap_swizzle).
+  // LDS address tables of the pass's segments: the tile's LDS index is
+  // swizzled by j ^ (j >> SB) ^ (j >> 2 SB) (low SB bits of each), linear over
+  // XOR, so the byte offset splits into a per-thread part (XOR of per-bit
+  // columns) and a per-element part
   const int SB = c64 ? 5 : 4;
   const uint32_t esz = c64 ? 8u : 16u;
-  const LdsSwz std_sw = LdsSwz::standard(SB);
+  auto swz = [SB](uint32_t j) {
+    const uint32_t m = (1u << SB) - 1;
+    return j ^ ((j >> SB) & m) ^ ((j >> (2 * SB)) & m);
+  };
   auto gbit = [&](int p) { return uint64_t(1) << (p < d.b ? p : d.hq[p - d.b]); };
   for (int si = d.seg_begin; si < d.seg_begin + d.seg_count; ++si) {
     RegSegDev& S = out_segs[size_t(si)];
-    LdsSwz sw = std_sw;
-    bool staged = false;
-    for (int oi = S.op_begin; oi < S.op_begin + S.op_count; ++oi)
-      staged = staged || out_rops[size_t(oi)].kind == 3 || out_rops[size_t(oi)].kind == 8;
-    if (si != d.seg_begin && !staged) {
-      const RegSegDev& O = out_segs[size_t(si) - 1];
-      uint32_t put_lane[6], get_lane[6];
-      for (int k = 0; k < 6; ++k) {
-        put_lane[k] = S.mcol[O.thr[k]];
-        get_lane[k] = 1u << S.thr[k];
-      }
-      sw = remap_swizzle(SB, L, put_lane, get_lane);
-    }
     for (int k = 0; k < TB; ++k) S.gcol_t[k] = gbit(S.thr[k]);
     for (int k = 0; k < RB; ++k) S.gcol_r[k] = gbit(S.reg[k]);
-    for (int k = 0; k < TB; ++k) S.get_tcol[k] = sw(1u << S.thr[k]) * esz;
+    for (int k = 0; k < TB; ++k) S.get_tcol[k] = swz(1u << S.thr[k]) * esz;
     for (int i = 0; i < (1 << RB); ++i) {
       uint32_t x = 0;
       for (int k = 0; k < RB; ++k)
         if (i >> k & 1) x |= 1u << S.reg[k];
-      S.get_reg[i] = sw(x) * esz;
+      S.get_reg[i] = swz(x) * esz;
     }
     if (si == d.seg_begin) continue;
     const RegSegDev& O = out_segs[size_t(si) - 1];  // written through S's map
-    S.put_tcst = sw(S.mcst) * esz;
-    for (int k = 0; k < TB; ++k) S.put_tcol[k] = sw(S.mcol[O.thr[k]]) * esz;
+    S.put_tcst = swz(S.mcst) * esz;
+    for (int k = 0; k < TB; ++k) S.put_tcol[k] = swz(S.mcol[O.thr[k]]) * esz;
     for (int i = 0; i < (1 << RB); ++i) {
       uint32_t x = 0;
       for (int k = 0; k < RB; ++k)
         if (i >> k & 1) x ^= S.mcol[O.reg[k]];
-      S.put_reg[i] = sw(x) * esz;
+      S.put_reg[i] = swz(x) * esz;
     }
   }
   return QSV_OK;
