@@ -27,11 +27,17 @@
 namespace qsv {
 
 constexpr int kExpThreads = 512;
-// loads per thread for a whole tile: 2^12 complex64 (16-byte pairs) or 2^11
-// complex128 amplitudes over 512 threads
-constexpr int kExpTileMax = 4096;  // largest tile: 2^12 amplitudes
-constexpr int kExpThreadsE = 256;  // expectation workgroups (more work per wave: the
-                                   // per-group setup is scalar and repeats per wave)
+// largest tiles: expectation passes 2^13 amplitudes (64 KiB of complex64),
+// lambda passes 2^12 (32 KiB)
+constexpr int kExpTileMax = 8192;
+constexpr int kObsTileMax = 4096;
+// expectation workgroups: 512 threads over a 2^13-amplitude tile, so a
+// single-term group gives each thread 8 pairs per tile (the group's scalar
+// setup repeats per wave) and two workgroups (64 KiB of LDS each) keep 16
+// waves on a compute unit; measured at 30 qubits complex64 against 256
+// threads over 2^12 tiles (21 passes: 52.7 ms) and 256 over 2^13 (18
+// passes but 8 waves per compute unit: 62.4 ms): 18 passes, 50.9 ms
+constexpr int kExpThreadsE = 512;
 constexpr int kExpMaxHigh = 16;
 constexpr int kExpMaxGlobal = 40;
 
@@ -77,9 +83,10 @@ struct ExpTermLds {
   uint32_t zl;
 };
 constexpr int kExpLdsTerms = 128;
-// persistent workgroups per observable pass: 8 per compute unit, 4 of them
-// resident at a time (LDS); measured at 30 qubits complex64: 2048 beats 1024
-// by 3.5% (shorter ranges even out the tail); QSV_EXPECT_GRID overrides
+// persistent workgroups per observable pass: 8 per compute unit (2 resident
+// at a time for the 64 KiB expectation tiles, 4 for the 32 KiB lambda
+// tiles); measured at 30 qubits complex64: 2048 beats 1024 (shorter ranges
+// even out the tail); QSV_EXPECT_GRID overrides
 constexpr int kExpGrid = 2048;
 
 // Persistent grid of the expectation and lambda passes: kExpGrid, or the
@@ -168,10 +175,10 @@ __device__ __forceinline__ uint64_t uni(uint64_t v) {
 // tile's base is the current one carried within the non-local qubit mask), so
 // its partial sum has a fixed order; the loads of its next tile are issued
 // before it computes on the current one.
-template <typename R, int NT, int LT = 0>
+template <typename R, int NT, int LT = 0, int TMAX = kExpTileMax>
 struct ExpTileStream {
   static constexpr int V = sizeof(R) == 4 ? 2 : 1;
-  static constexpr int NL = kExpTileMax / 2 / NT;  // at most 2048 loads (16-byte pairs or complex128)
+  static constexpr int NL = TMAX / 2 / NT;  // loads per thread (16-byte pairs or complex128)
   uint64_t xt;          // per-thread part of the element addresses
   uint64_t xk[NL];      // workgroup-uniform parts
   cx<R> buf[NL * V];
@@ -263,9 +270,14 @@ __device__ __forceinline__ void exp_term(const ExpTermDev* __restrict__ terms, c
   }
 }
 
-// Tile qubits of the fixed-size expectation kernel variant (32 KiB tiles).
+// Tile qubits of the fixed-size expectation kernel variant (64 KiB tiles)
+// and of the lambda passes (32 KiB tiles).
 template <typename R>
 __host__ __device__ constexpr int exp_tile_bits() {
+  return sizeof(R) == 4 ? 13 : 12;
+}
+template <typename R>
+__host__ __device__ constexpr int obs_tile_bits() {
   return sizeof(R) == 4 ? 12 : 11;
 }
 
@@ -280,12 +292,12 @@ __device__ __forceinline__ R pair_product(const cx<R>& a, const cx<R>& b) {
 
 // One single-term group with flip mask lf != 0 over a tile: the sum over the
 // pairs (x, x ^ lf), x with bit hb clear, of Re (REAL) or Im of
-// conj(psi_y) psi_x with the term's local Z/Y sign. A thread's NP pair
-// products are summed in the amplitude precision (complex64: FP32, one
-// conversion to FP64 per group and thread instead of one per pair; with the
+// conj(psi_y) psi_x with the term's local Z/Y sign. A thread's pair products
+// are summed in the amplitude precision in chunks of at most 8 (complex64:
+// FP32, one conversion to FP64 per chunk instead of one per pair; with the
 // products' own rounding the error is at most 9 x 2^-24 of the sum of
-// |psi_x||psi_y| over the pairs, i.e. of <psi|psi>/2) and the sums over
-// threads and tiles in FP64. x is the thread
+// |psi_x||psi_y| over the pairs, i.e. of <psi|psi>/2) and the chunks, threads
+// and tiles in FP64. x is the thread
 // part xt (tx = t + xt) OR-ed with a workgroup-uniform step part xs (disjoint
 // bits); likewise y = (xt ^ (lf & thread bits)) | (xs ^ (lf outside them)),
 // so each step adds a uniform offset to two per-thread LDS pointers. The sign
@@ -294,6 +306,7 @@ __device__ __forceinline__ R pair_product(const cx<R>& a, const cx<R>& b) {
 template <typename R, bool REAL, bool FULL, int NP, int NT>
 __device__ __forceinline__ double exp_pairs(const cx<R>* tx, const cx<R>* ty, const ExpGroupDev& D, uint32_t pt,
                                             uint32_t TS, uint32_t tid) {
+  double sd = 0.0;
   R sw = R(0);
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
@@ -303,8 +316,13 @@ __device__ __forceinline__ double exp_pairs(const cx<R>* tx, const cx<R>* ty, co
       const cx<R> a = tx[D.offx[k]], b = ty[D.offy[k]];
       sw += xor_sign(pair_product<R, REAL>(a, b), D.sgn[k]);
     }
+    if ((k & 7) == 7) {  // sums of at most 8 products in the amplitude precision
+      sd += double(sw);
+      sw = R(0);
+    }
   }
-  return xor_sign(double(sw), pt);  // the thread's part of the sign, common to every step
+  sd += double(sw);  // (the loop may end early on small tiles)
+  return xor_sign(sd, pt);  // the thread's part of the sign, common to every step
 }
 
 // <psi|O|psi> over the tiles of one pass. Sums over threads and tiles are
@@ -467,8 +485,8 @@ __device__ __forceinline__ void obs_single(const cx<R>* t, uint32_t tid, uint32_
   }
 }
 
-// FIXED: the tile has exp_tile_bits<R>() qubits and every thread's outputs
-// exist (complex64: 2^12 = 8 x 512).
+// FIXED: the tile has obs_tile_bits<R>() qubits and every thread's outputs
+// exist (complex64: 2^12 = 8 x 512). Tiles of at most kObsTileMax amplitudes.
 template <typename R, bool FIXED>
 __global__ void __launch_bounds__(kExpThreads)
     k_apply_obs_tile(const R* __restrict__ psi, R* __restrict__ lam, const ExpPassDev* __restrict__ passes,
@@ -478,9 +496,9 @@ __global__ void __launch_bounds__(kExpThreads)
   __shared__ ExpTermLds et[kExpLdsTerms];
   cx<R>* t = reinterpret_cast<cx<R>*>(smem);
   const ExpPassDev& P = passes[pass_idx];
-  const uint32_t TS = FIXED ? (1u << exp_tile_bits<R>()) : (1u << P.L);
+  const uint32_t TS = FIXED ? (1u << obs_tile_bits<R>()) : (1u << P.L);
   const uint32_t tid = threadIdx.x;
-  ExpTileStream<R, kExpThreads> io(P);
+  ExpTileStream<R, kExpThreads, 0, kObsTileMax> io(P);
   const uint64_t yt = exp_place(P, tid);
   uint64_t yk[kObsOut];
 #pragma unroll
@@ -701,17 +719,18 @@ uint64_t pick_pass_local(const std::vector<uint64_t>& hi, uint64_t low, int L) {
   return best;
 }
 
-ExpPlan* build_exp_plan(const qsv_observable* o, qsv_dtype dt) {
+ExpPlan* build_exp_plan(const qsv_observable* o, qsv_dtype dt, bool lambda) {
   std::vector<Group> groups;
   std::vector<GTerm> terms;
   build_groups(o, groups, terms);
   ExpPlan* p = new ExpPlan();
   const int n = o->n;
   p->n = n;
-  // tile: 2^L amplitudes, 32 KiB (measured on MI355X at 30 qubits: 32 KiB
-  // tiles under 512-thread workgroups beat 64 KiB and 16 KiB ones);
-  // QSV_EXPECT_TILE overrides L, for tuning
-  int Ldef = dt == QSV_C64 ? 12 : 11;
+  // tile: 2^L amplitudes; expectation passes 64 KiB (2^13 complex64, 2^12
+  // complex128: more flip masks fit a pass, 18 passes instead of 21 for the
+  // 200-term 30-qubit observable), lambda passes 32 KiB (their kernel keeps 8
+  // outputs per thread in registers); QSV_EXPECT_TILE lowers L, for tuning
+  int Ldef = lambda ? (dt == QSV_C64 ? 12 : 11) : (dt == QSV_C64 ? 13 : 12);
   if (const char* e = std::getenv("QSV_EXPECT_TILE")) Ldef = std::max(6, std::min(Ldef, std::atoi(e)));
   p->L = std::min(n, Ldef);
   int bdef = dt == QSV_C64 ? 4 : 3;  // 128-byte contiguous runs
@@ -830,7 +849,7 @@ int upload_exp_plan(ExpPlan* p, int device) {
 template <typename R>
 int expect_tiled_t(qsv_state* s, qsv_observable* o, double* out) {
   ExpPlan*& pl = o->exp_plan[s->dtype];
-  if (!pl) pl = build_exp_plan(o, s->dtype);
+  if (!pl) pl = build_exp_plan(o, s->dtype, false);
   if (pl->passes.empty() && pl->wide.empty()) {
     *out = 0.0;
     return QSV_OK;
@@ -886,8 +905,8 @@ int expect_tiled_t(qsv_state* s, qsv_observable* o, double* out) {
 
 template <typename R>
 int apply_obs_tiled_t(const qsv_state* in, qsv_observable* o, qsv_state* out) {
-  ExpPlan*& pl = o->exp_plan[in->dtype];
-  if (!pl) pl = build_exp_plan(o, in->dtype);
+  ExpPlan*& pl = o->obs_plan[in->dtype];
+  if (!pl) pl = build_exp_plan(o, in->dtype, true);
   const uint64_t N = dim(in->n);
   if (pl->passes.empty() && pl->wide.empty()) {  // no terms: lambda = 0
     const uint64_t blocks = std::min<uint64_t>((N + kExpThreads - 1) / kExpThreads, 65536);
@@ -901,7 +920,7 @@ int apply_obs_tiled_t(const qsv_state* in, qsv_observable* o, qsv_state* out) {
   const uint64_t tiles = dim(in->n - pl->L);
   const size_t lds = (size_t(1) << pl->L) * sizeof(cx<R>);
   // compile-time output count when every thread has kObsOut outputs
-  const bool fixed = pl->L == exp_tile_bits<R>() && (size_t(1) << pl->L) == size_t(kObsOut) * kExpThreads;
+  const bool fixed = pl->L == obs_tile_bits<R>() && (size_t(1) << pl->L) == size_t(kObsOut) * kExpThreads;
   QSV_HIP_CHECK(hipFuncSetAttribute(fixed ? reinterpret_cast<const void*>(&k_apply_obs_tile<R, true>)
                                           : reinterpret_cast<const void*>(&k_apply_obs_tile<R, false>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
@@ -975,7 +994,7 @@ int noalloc_scratch(int device, char** out) {
 template <typename R>
 int expect_noalloc_t(qsv_state* s, qsv_observable* o, double* out) {
   ExpPlan*& pl = o->exp_plan[s->dtype];
-  if (!pl) pl = build_exp_plan(o, s->dtype);  // host tables only
+  if (!pl) pl = build_exp_plan(o, s->dtype, false);  // host tables only
   if (pl->passes.empty() && pl->wide.empty()) {
     *out = 0.0;
     return QSV_OK;
@@ -1071,7 +1090,7 @@ int apply_observable_tiled(const qsv_state* in, const qsv_observable* o, qsv_sta
 int expectation_passes(const qsv_observable* o, qsv_dtype dt) {
   qsv_observable* mo = const_cast<qsv_observable*>(o);
   ExpPlan*& pl = mo->exp_plan[dt];
-  if (!pl) pl = build_exp_plan(mo, dt);
+  if (!pl) pl = build_exp_plan(mo, dt, false);
   return int(pl->passes.size() + pl->wide.size());
 }
 

@@ -157,12 +157,13 @@ def test_adjoint_24q_vs_oracle(dt):
 
 def wide_observable(n, seed):
     """Strings whose X/Y factors cover more qubits than a tile holds beside
-    the low ones (9 and 10 flip qubits above qubit 3), one of them twice with
+    the low ones (10 and 11 flip qubits above qubit 3; an expectation tile
+    holds 9 more for both dtypes, a lambda tile 8), one of them twice with
     other Z/Y signs (a multi-term group), mixed with ordinary strings."""
     rng = np.random.default_rng(seed)
     hi = list(range(4, n))
     obs = W.random_pauli_observable(n, 8, (1, 4), seed_key=(25, n, seed))
-    for w in (9, 10):
+    for w in (10, 11):
         qs = [int(q) for q in rng.choice(hi, size=w, replace=False)]
         ps = [int(p) for p in rng.integers(1, 3, size=w)]
         obs.append((float(rng.standard_normal()), list(zip(qs, ps)) + [(0, 3)]))
@@ -183,7 +184,7 @@ def test_wide_flip_masks(dt, grid, monkeypatch):
     if grid != "0":
         monkeypatch.setenv("QSV_EXPECT_GRID", grid)
     rng = np.random.default_rng(140)
-    for n in (14, 16):
+    for n in (15, 17):
         psi = rand_state(rng, n)
         ref_in = as_loaded(psi, dt)
         full = wide_observable(n, n)
@@ -199,7 +200,7 @@ def test_wide_flip_masks(dt, grid, monkeypatch):
             apply_observable(s, obs, out)
             err = np.max(np.abs(out.store() - O.apply_observable(ref_in, obs_t)))
             assert err <= LAM_TOL[dt] * scale, (n, dt, len(obs_t), err)
-    n = 14
+    n = 15
     gates, npar = W.ry_rz_cnot_ring(n, 1)
     theta = W.uniform_angles(npar, (26, n))
     obs_t = wide_observable(n, 3)
