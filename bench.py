@@ -599,8 +599,8 @@ def autotune_leg(Q, W, n=30):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
-                                   "design note, not an implementation", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the state-vector path runs on one GPU; sharding across GPUs "
+                                   "is described, not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import paper_2011_13524_amd as Q
