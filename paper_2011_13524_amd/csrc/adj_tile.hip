@@ -232,7 +232,6 @@ __global__ void __launch_bounds__(kAdjTileThreads)
 // uncompute. Per gradient op, each wavefront sums its share (fixed order) into
 // its own LDS slot; workgroups are persistent over a contiguous range of tiles
 // and write one FP64 partial per (row, workgroup) at the end of the pass.
-constexpr int kAdjRegGrid = 1024;
 constexpr int kAdjMaxRows = 64;  // gradient rows per pass (LDS slots)
 
 // X/Y rotation on register bit P: share of -Im<lambda|P|psi>, then
@@ -835,9 +834,27 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
   }
   const int nrows = int(row_slot.size());
   const uint64_t tiles = dim(n - L);
-  // persistent grid; QSV_ADJOINT_GRID overrides it (tuning, and tests that give
-  // every workgroup a ragged range of several tiles at small sizes)
-  uint64_t gmax = reg ? kAdjRegGrid : kAdjTileGrid;
+  // register-resident passes: tile + gradient slots in LDS
+  const size_t reg_lds = (size_t(1) << L) * sizeof(cx<R>) + size_t(kAdjMaxRows) * (256 / 64) * sizeof(double);
+  constexpr int RBs = sizeof(R) == 4 ? 4 : 3;
+  const void* reg_fn = kmax <= 2   ? reinterpret_cast<const void*>(&k_adj_reg<R, RBs, 2, 8>)
+                       : kmax <= 3 ? reinterpret_cast<const void*>(&k_adj_reg<R, RBs, 3, 8>)
+                                   : reinterpret_cast<const void*>(&k_adj_reg<R, RBs, 5, 8>);
+  // persistent grid: for the register sweep, four rounds of the workgroups the
+  // device holds at once (the variant's occupancy times the compute units), so
+  // no round runs part-full (measured at 24 qubits complex64: 27.7 ms with a
+  // fixed 1024 against 25.3 ms with 4 x 768); QSV_ADJOINT_GRID overrides it
+  // (tuning, and tests that give every workgroup a ragged range of several
+  // tiles at small sizes)
+  uint64_t gmax = kAdjTileGrid;
+  if (reg) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reg_fn, 256, reg_lds) != hipSuccess || per_cu < 1)
+      per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, psi->device) != hipSuccess || cus < 1)
+      cus = 256;
+    gmax = uint64_t(per_cu) * uint64_t(cus) * 4;
+  }
   if (const char* e = std::getenv("QSV_ADJOINT_GRID")) gmax = uint64_t(std::max(1, std::atoi(e)));
   const int G = int(std::min<uint64_t>(tiles, gmax));
   // one device allocation: passes | ops | pool | segs | rops | prow | partial[nrows x G] | rows[nrows]
@@ -877,8 +894,7 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
   hipLaunchKernelGGL(k_zero_doubles, dim3(256), dim3(256), 0, st, part, uint64_t(nrows) * G);
   {
     if (reg) {
-      // register-resident passes: tile + gradient slots
-      const size_t lds = (size_t(1) << L) * sizeof(cx<R>) + size_t(kAdjMaxRows) * (256 / 64) * sizeof(double);
+      const size_t lds = reg_lds;
       for (size_t pi = 0; pi < hp.size(); ++pi) {
         ProfScope ps("adjoint", 4.0 * sizeof(cx<R>) * double(dim(n)), st);
 #define QSV_ADJR_LAUNCH(KM)                                                                      \

@@ -142,7 +142,7 @@ def _adjoint_24q_case():
 @pytest.mark.parametrize("dt", ["c64", "c128"])
 def test_adjoint_24q_vs_oracle(dt):
     # the 24-qubit adjoint at its default launch shape (register-resident
-    # sweep, 4 / 8 tiles per persistent workgroup), on two layers of the
+    # sweep, 2 / 4 tiles per persistent workgroup), on two layers of the
     # workload's circuit family, against the oracle's energy and exact shift
     # rule on sampled parameters
     n, gates, theta, obs_t, slots, e_ref, g_ref = _adjoint_24q_case()
