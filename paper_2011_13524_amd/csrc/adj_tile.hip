@@ -840,12 +840,13 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
   const void* reg_fn = kmax <= 2   ? reinterpret_cast<const void*>(&k_adj_reg<R, RBs, 2, 8>)
                        : kmax <= 3 ? reinterpret_cast<const void*>(&k_adj_reg<R, RBs, 3, 8>)
                                    : reinterpret_cast<const void*>(&k_adj_reg<R, RBs, 5, 8>);
-  // persistent grid: for the register sweep, four rounds of the workgroups the
-  // device holds at once (the variant's occupancy times the compute units), so
-  // no round runs part-full (measured at 24 qubits complex64: 27.7 ms with a
-  // fixed 1024 against 25.3 ms with 4 x 768); QSV_ADJOINT_GRID overrides it
-  // (tuning, and tests that give every workgroup a ragged range of several
-  // tiles at small sizes)
+  // persistent grid: for the register sweep, eight rounds of the workgroups
+  // the device holds at once (the variant's occupancy times the compute
+  // units), so no round runs part-full and the last one is short (measured:
+  // 24 qubits complex64 27.7 ms with a fixed 1024, 25.1 ms with 4 x 768, 24.7
+  // ms with 8 x 768; 32 qubits 8.10, 7.14 and 6.98 s); QSV_ADJOINT_GRID
+  // overrides it (tuning, and tests that give every workgroup a ragged range
+  // of several tiles at small sizes)
   uint64_t gmax = kAdjTileGrid;
   if (reg) {
     int per_cu = 0, cus = 0;
@@ -853,7 +854,7 @@ int adjoint_backward_tiled(const qsv_circuit* c, const double* theta, qsv_state*
       per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, psi->device) != hipSuccess || cus < 1)
       cus = 256;
-    gmax = uint64_t(per_cu) * uint64_t(cus) * 4;
+    gmax = uint64_t(per_cu) * uint64_t(cus) * 8;
   }
   if (const char* e = std::getenv("QSV_ADJOINT_GRID")) gmax = uint64_t(std::max(1, std::atoi(e)));
   const int G = int(std::min<uint64_t>(tiles, gmax));

@@ -3,9 +3,10 @@
 The expectation pass (k_expect_tile), the lambda = O psi pass
 (k_apply_obs_tile) and the register-resident reverse sweep (k_adj_reg) run on
 a bounded persistent grid: a workgroup takes a contiguous range of several
-tiles only when the state has more tiles than the grid (from 24 qubits at the
-default grids), and only then do the next-tile prefetch and the carry of the
-next tile's base across local bit positions run. Here the grids are
+tiles only when the state has more tiles than the grid (at the default grids
+from 24 or 25 qubits, depending on the pass and the dtype), and only then do
+the next-tile prefetch and the carry of the next tile's base across local bit
+positions run. Here the grids are
 overridden (QSV_EXPECT_GRID, QSV_ADJOINT_GRID) to small odd values at 14-16
 qubits, so every workgroup takes a ragged range of several tiles, with X/Y
 strings on high qubits (non-contiguous local sets: the carry skips local bit
@@ -106,8 +107,10 @@ def test_adjoint_ragged_ranges(dt, grid, monkeypatch):
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("dt", ["c64", "c128"])
 def test_expectation_and_lambda_24q_default_grid(dt):
-    # 24 qubits at the default grid: 4096 (c64) / 8192 (c128) tiles, 2 / 4 per
-    # persistent workgroup; seeded random state, strings of weight <= 6
+    # 24 qubits at the default grid of 2048 persistent workgroups: the
+    # expectation over 2048 (c64) / 4096 (c128) tiles, lambda over 4096 /
+    # 8192 (1 / 2 and 2 / 4 tiles per workgroup); seeded random state,
+    # strings of weight <= 6
     n = 24
     psi = rand_state(np.random.default_rng(24), n)
     ref_in = as_loaded(psi, dt)
@@ -142,7 +145,7 @@ def _adjoint_24q_case():
 @pytest.mark.parametrize("dt", ["c64", "c128"])
 def test_adjoint_24q_vs_oracle(dt):
     # the 24-qubit adjoint at its default launch shape (register-resident
-    # sweep, 2 / 4 tiles per persistent workgroup), on two layers of the
+    # sweep at its default persistent grid), on two layers of the
     # workload's circuit family, against the oracle's energy and exact shift
     # rule on sampled parameters
     n, gates, theta, obs_t, slots, e_ref, g_ref = _adjoint_24q_case()
