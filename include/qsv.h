@@ -330,11 +330,10 @@ int qsv_observable_info(const qsv_observable* o, int* n, int* terms, int* groups
 int qsv_transition_amplitude(const qsv_state* bra, const qsv_observable* o, const qsv_state* ket,
                              double* re, double* im);
 
-/* Number of state passes an expectation of this observable takes for states
- * of dtype `dtype`: its flip masks packed into tiles of 2^13 (complex64) or
- * 2^12 (complex128) amplitudes, plus one pass per flip mask wider than a tile
- * (qsv_apply_observable packs into tiles half that size, so it may take
- * more). Host-only. */
+/* Number of state passes an expectation (or qsv_apply_observable) of this
+ * observable takes for states of dtype `dtype`: its flip masks packed into
+ * tiles of 2^13 (complex64) or 2^12 (complex128) amplitudes, plus one pass per
+ * flip mask wider than a tile. Host-only. */
 int qsv_observable_passes(const qsv_observable* o, qsv_dtype dtype, int* passes);
 
 /* <psi|O|psi> accumulated in double (section 4.5, get_expectation_value). The

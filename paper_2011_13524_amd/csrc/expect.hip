@@ -27,10 +27,9 @@
 namespace qsv {
 
 constexpr int kExpThreads = 512;
-// largest tiles: expectation passes 2^13 amplitudes (64 KiB of complex64),
-// lambda passes 2^12 (32 KiB)
+// largest tiles (expectation and lambda passes): 2^13 amplitudes, 64 KiB of
+// complex64
 constexpr int kExpTileMax = 8192;
-constexpr int kObsTileMax = 4096;
 // expectation workgroups: 512 threads over a 2^13-amplitude tile, so a
 // single-term group gives each thread 8 pairs per tile (the group's scalar
 // setup repeats per wave) and two workgroups (64 KiB of LDS each) keep 16
@@ -178,7 +177,9 @@ __device__ __forceinline__ uint64_t uni(uint64_t v) {
 template <typename R, int NT, int LT = 0, int TMAX = kExpTileMax>
 struct ExpTileStream {
   static constexpr int V = sizeof(R) == 4 ? 2 : 1;
-  static constexpr int NL = TMAX / 2 / NT;  // loads per thread (16-byte pairs or complex128)
+  // loads per thread (16-byte pairs or complex128); TMAX: the largest tile in
+  // 8-byte units (complex64 amplitudes)
+  static constexpr int NL = TMAX / 2 / NT;
   uint64_t xt;          // per-thread part of the element addresses
   uint64_t xk[NL];      // workgroup-uniform parts
   cx<R> buf[NL * V];
@@ -270,15 +271,19 @@ __device__ __forceinline__ void exp_term(const ExpTermDev* __restrict__ terms, c
   }
 }
 
-// Tile qubits of the fixed-size expectation kernel variant (64 KiB tiles)
-// and of the lambda passes (32 KiB tiles).
+// Tile qubits of the fixed-size expectation and lambda kernel variants (64
+// KiB tiles), and the lambda workgroup size (8 outputs per thread).
 template <typename R>
 __host__ __device__ constexpr int exp_tile_bits() {
   return sizeof(R) == 4 ? 13 : 12;
 }
 template <typename R>
 __host__ __device__ constexpr int obs_tile_bits() {
-  return sizeof(R) == 4 ? 12 : 11;
+  return sizeof(R) == 4 ? 13 : 12;
+}
+template <typename R>
+__host__ __device__ constexpr int obs_threads() {
+  return sizeof(R) == 4 ? 1024 : 512;
 }
 
 // Re (REAL) or Im of conj(b) a. complex64: formed in FP32 (relative error
@@ -465,15 +470,15 @@ constexpr int kObsOut = 8;  // outputs per thread: 2^12 / 512
 // One single-term group's contribution to this thread's outputs: lambda_y +=
 // c psi_{y ^ F} (REAL) or i c psi_{y ^ F} with c = +-coefficient, the sign of
 // (-1)^|x & z| split into a per-thread bit (pt) and a per-step bit.
-template <typename R, bool REAL, bool FIXED>
+template <typename R, bool REAL, bool FIXED, int NT>
 __device__ __forceinline__ void obs_single(const cx<R>* t, uint32_t tid, uint32_t lf, uint32_t zl, uint32_t pt,
                                            R cm, uint32_t TS, R* ar, R* ai) {
 #pragma unroll
   for (int k = 0; k < kObsOut; ++k) {
-    const uint32_t y = tid + uint32_t(k) * kExpThreads;
+    const uint32_t y = tid + uint32_t(k) * NT;
     if (FIXED || y < TS) {
       const cx<R> v = t[y ^ lf];
-      const R c = (pt ^ (__popc((uint32_t(k) * kExpThreads) & zl) & 1)) ? -cm : cm;
+      const R c = (pt ^ (__popc((uint32_t(k) * NT) & zl) & 1)) ? -cm : cm;
       if constexpr (REAL) {
         ar[k] += c * v.re;
         ai[k] += c * v.im;
@@ -486,9 +491,10 @@ __device__ __forceinline__ void obs_single(const cx<R>* t, uint32_t tid, uint32_
 }
 
 // FIXED: the tile has obs_tile_bits<R>() qubits and every thread's outputs
-// exist (complex64: 2^12 = 8 x 512). Tiles of at most kObsTileMax amplitudes.
-template <typename R, bool FIXED>
-__global__ void __launch_bounds__(kExpThreads)
+// exist (complex64: 2^13 = 8 x 1024, complex128: 2^12 = 8 x 512). Tiles of
+// at most kObsOut x NT amplitudes.
+template <typename R, bool FIXED, int NT>
+__global__ void __launch_bounds__(NT)
     k_apply_obs_tile(const R* __restrict__ psi, R* __restrict__ lam, const ExpPassDev* __restrict__ passes,
                      int pass_idx, const ExpGroupDev* __restrict__ groups,
                      const ExpTermDev* __restrict__ terms, int accumulate, uint64_t ntiles) {
@@ -498,11 +504,13 @@ __global__ void __launch_bounds__(kExpThreads)
   const ExpPassDev& P = passes[pass_idx];
   const uint32_t TS = FIXED ? (1u << obs_tile_bits<R>()) : (1u << P.L);
   const uint32_t tid = threadIdx.x;
-  ExpTileStream<R, kExpThreads, 0, kObsTileMax> io(P);
+  // (the stream's maximum counts 8-byte units: a complex128 tile of 8 x NT
+  // amplitudes is 16 x NT of them)
+  ExpTileStream<R, NT, 0, kObsOut * NT * int(sizeof(R) / 4)> io(P);
   const uint64_t yt = exp_place(P, tid);
   uint64_t yk[kObsOut];
 #pragma unroll
-  for (int k = 0; k < kObsOut; ++k) yk[k] = exp_place(P, uint32_t(k) * kExpThreads);
+  for (int k = 0; k < kObsOut; ++k) yk[k] = exp_place(P, uint32_t(k) * NT);
   ExpTileRange tr(P, ntiles);
   if (tr.g < tr.end) io.fetch(psi, tr.base);
   for (; tr.g < tr.end; ++tr.g) {
@@ -531,13 +539,13 @@ __global__ void __launch_bounds__(kExpThreads)
         // alpha i^nY is real or imaginary: lambda += c psi or i c psi
         const uint32_t pt = (__popc((tid ^ lf) & G.zl) & 1);
         if (G.im == 0.0)
-          obs_single<R, true, FIXED>(t, tid, lf, G.zl, pt, R(G.re), TS, ar, ai);
+          obs_single<R, true, FIXED, NT>(t, tid, lf, G.zl, pt, R(G.re), TS, ar, ai);
         else
-          obs_single<R, false, FIXED>(t, tid, lf, G.zl, pt, R(G.im), TS, ar, ai);
+          obs_single<R, false, FIXED, NT>(t, tid, lf, G.zl, pt, R(G.im), TS, ar, ai);
       } else {
 #pragma unroll
         for (int k = 0; k < kObsOut; ++k) {
-          const uint32_t y = tid + uint32_t(k) * kExpThreads;
+          const uint32_t y = tid + uint32_t(k) * NT;
           if (y < TS) {
             const uint32_t x = y ^ lf;
             const cx<R> v = t[x];
@@ -558,7 +566,7 @@ __global__ void __launch_bounds__(kExpThreads)
     }
 #pragma unroll
     for (int k = 0; k < kObsOut; ++k) {
-      if (!FIXED && tid + uint32_t(k) * kExpThreads >= TS) continue;
+      if (!FIXED && tid + uint32_t(k) * NT >= TS) continue;
       cx<R> r;
       if (accumulate) {
         const cx<R> old = load1(lam, base | yt | yk[k]);
@@ -719,18 +727,17 @@ uint64_t pick_pass_local(const std::vector<uint64_t>& hi, uint64_t low, int L) {
   return best;
 }
 
-ExpPlan* build_exp_plan(const qsv_observable* o, qsv_dtype dt, bool lambda) {
+ExpPlan* build_exp_plan(const qsv_observable* o, qsv_dtype dt) {
   std::vector<Group> groups;
   std::vector<GTerm> terms;
   build_groups(o, groups, terms);
   ExpPlan* p = new ExpPlan();
   const int n = o->n;
   p->n = n;
-  // tile: 2^L amplitudes; expectation passes 64 KiB (2^13 complex64, 2^12
-  // complex128: more flip masks fit a pass, 18 passes instead of 21 for the
-  // 200-term 30-qubit observable), lambda passes 32 KiB (their kernel keeps 8
-  // outputs per thread in registers); QSV_EXPECT_TILE lowers L, for tuning
-  int Ldef = lambda ? (dt == QSV_C64 ? 12 : 11) : (dt == QSV_C64 ? 13 : 12);
+  // tile: 2^L amplitudes, 64 KiB (2^13 complex64, 2^12 complex128): more
+  // flip masks fit a pass (18 expectation passes instead of 21 for the
+  // 200-term 30-qubit observable); QSV_EXPECT_TILE lowers L, for tuning
+  int Ldef = dt == QSV_C64 ? 13 : 12;
   if (const char* e = std::getenv("QSV_EXPECT_TILE")) Ldef = std::max(6, std::min(Ldef, std::atoi(e)));
   p->L = std::min(n, Ldef);
   int bdef = dt == QSV_C64 ? 4 : 3;  // 128-byte contiguous runs
@@ -849,7 +856,7 @@ int upload_exp_plan(ExpPlan* p, int device) {
 template <typename R>
 int expect_tiled_t(qsv_state* s, qsv_observable* o, double* out) {
   ExpPlan*& pl = o->exp_plan[s->dtype];
-  if (!pl) pl = build_exp_plan(o, s->dtype, false);
+  if (!pl) pl = build_exp_plan(o, s->dtype);
   if (pl->passes.empty() && pl->wide.empty()) {
     *out = 0.0;
     return QSV_OK;
@@ -905,8 +912,8 @@ int expect_tiled_t(qsv_state* s, qsv_observable* o, double* out) {
 
 template <typename R>
 int apply_obs_tiled_t(const qsv_state* in, qsv_observable* o, qsv_state* out) {
-  ExpPlan*& pl = o->obs_plan[in->dtype];
-  if (!pl) pl = build_exp_plan(o, in->dtype, true);
+  ExpPlan*& pl = o->exp_plan[in->dtype];
+  if (!pl) pl = build_exp_plan(o, in->dtype);
   const uint64_t N = dim(in->n);
   if (pl->passes.empty() && pl->wide.empty()) {  // no terms: lambda = 0
     const uint64_t blocks = std::min<uint64_t>((N + kExpThreads - 1) / kExpThreads, 65536);
@@ -920,9 +927,10 @@ int apply_obs_tiled_t(const qsv_state* in, qsv_observable* o, qsv_state* out) {
   const uint64_t tiles = dim(in->n - pl->L);
   const size_t lds = (size_t(1) << pl->L) * sizeof(cx<R>);
   // compile-time output count when every thread has kObsOut outputs
-  const bool fixed = pl->L == obs_tile_bits<R>() && (size_t(1) << pl->L) == size_t(kObsOut) * kExpThreads;
-  QSV_HIP_CHECK(hipFuncSetAttribute(fixed ? reinterpret_cast<const void*>(&k_apply_obs_tile<R, true>)
-                                          : reinterpret_cast<const void*>(&k_apply_obs_tile<R, false>),
+  constexpr int NTo = obs_threads<R>();
+  const bool fixed = pl->L == obs_tile_bits<R>() && (size_t(1) << pl->L) == size_t(kObsOut) * NTo;
+  QSV_HIP_CHECK(hipFuncSetAttribute(fixed ? reinterpret_cast<const void*>(&k_apply_obs_tile<R, true, NTo>)
+                                          : reinterpret_cast<const void*>(&k_apply_obs_tile<R, false, NTo>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   char* d = static_cast<char*>(pl->dev);
   for (size_t pi = 0; pi < pl->passes.size(); ++pi) {
@@ -932,11 +940,11 @@ int apply_obs_tiled_t(const qsv_state* in, qsv_observable* o, qsv_state* out) {
     const auto* gd = reinterpret_cast<const ExpGroupDev*>(d + pl->off_groups);
     const auto* td = reinterpret_cast<const ExpTermDev*>(d + pl->off_terms);
     if (fixed)
-      hipLaunchKernelGGL((k_apply_obs_tile<R, true>), grid, dim3(kExpThreads), lds, in->stream,
+      hipLaunchKernelGGL((k_apply_obs_tile<R, true, NTo>), grid, dim3(NTo), lds, in->stream,
                          static_cast<const R*>(in->ptr), static_cast<R*>(out->ptr), pd, int(pi), gd, td,
                          pi > 0 ? 1 : 0, tiles);
     else
-      hipLaunchKernelGGL((k_apply_obs_tile<R, false>), grid, dim3(kExpThreads), lds, in->stream,
+      hipLaunchKernelGGL((k_apply_obs_tile<R, false, NTo>), grid, dim3(NTo), lds, in->stream,
                          static_cast<const R*>(in->ptr), static_cast<R*>(out->ptr), pd, int(pi), gd, td,
                          pi > 0 ? 1 : 0, tiles);
     QSV_HIP_CHECK(hipGetLastError());
@@ -994,7 +1002,7 @@ int noalloc_scratch(int device, char** out) {
 template <typename R>
 int expect_noalloc_t(qsv_state* s, qsv_observable* o, double* out) {
   ExpPlan*& pl = o->exp_plan[s->dtype];
-  if (!pl) pl = build_exp_plan(o, s->dtype, false);  // host tables only
+  if (!pl) pl = build_exp_plan(o, s->dtype);  // host tables only
   if (pl->passes.empty() && pl->wide.empty()) {
     *out = 0.0;
     return QSV_OK;
@@ -1090,7 +1098,7 @@ int apply_observable_tiled(const qsv_state* in, const qsv_observable* o, qsv_sta
 int expectation_passes(const qsv_observable* o, qsv_dtype dt) {
   qsv_observable* mo = const_cast<qsv_observable*>(o);
   ExpPlan*& pl = mo->exp_plan[dt];
-  if (!pl) pl = build_exp_plan(mo, dt, false);
+  if (!pl) pl = build_exp_plan(mo, dt);
   return int(pl->passes.size() + pl->wide.size());
 }
 

@@ -19,10 +19,8 @@ struct qsv_observable {
     int ny;
   };
   std::vector<Term> terms;
-  // tiled evaluation plans per dtype (built on first use, dropped on change):
-  // the expectation's passes and lambda = O psi's (smaller tiles)
+  // tiled evaluation plans per dtype (built on first use, dropped on change)
   qsv::ExpPlan* exp_plan[3] = {nullptr, nullptr, nullptr};
-  qsv::ExpPlan* obs_plan[3] = {nullptr, nullptr, nullptr};
 
   qsv_observable() = default;
   qsv_observable(const qsv_observable& o) : n(o.n), terms(o.terms) {}
@@ -37,10 +35,6 @@ struct qsv_observable {
   ~qsv_observable() { drop_plans(); }
   void drop_plans() {
     for (auto*& p : exp_plan) {
-      if (p) qsv::free_exp_plan(p);
-      p = nullptr;
-    }
-    for (auto*& p : obs_plan) {
       if (p) qsv::free_exp_plan(p);
       p = nullptr;
     }

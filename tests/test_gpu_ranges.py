@@ -107,9 +107,8 @@ def test_adjoint_ragged_ranges(dt, grid, monkeypatch):
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("dt", ["c64", "c128"])
 def test_expectation_and_lambda_24q_default_grid(dt):
-    # 24 qubits at the default grid of 2048 persistent workgroups: the
-    # expectation over 2048 (c64) / 4096 (c128) tiles, lambda over 4096 /
-    # 8192 (1 / 2 and 2 / 4 tiles per workgroup); seeded random state,
+    # 24 qubits at the default grid of 2048 persistent workgroups: 2048
+    # (c64) / 4096 (c128) tiles, 1 / 2 per workgroup; seeded random state,
     # strings of weight <= 6
     n = 24
     psi = rand_state(np.random.default_rng(24), n)
@@ -160,8 +159,8 @@ def test_adjoint_24q_vs_oracle(dt):
 
 def wide_observable(n, seed):
     """Strings whose X/Y factors cover more qubits than a tile holds beside
-    the low ones (10 and 11 flip qubits above qubit 3; an expectation tile
-    holds 9 more for both dtypes, a lambda tile 8), one of them twice with
+    the low ones (10 and 11 flip qubits above qubit 3; a tile holds 9 more
+    for both dtypes), one of them twice with
     other Z/Y signs (a multi-term group), mixed with ordinary strings."""
     rng = np.random.default_rng(seed)
     hi = list(range(4, n))
