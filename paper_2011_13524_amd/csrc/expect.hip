@@ -82,6 +82,11 @@ struct ExpTermLds {
   uint32_t zl;
 };
 constexpr int kExpLdsTerms = 128;
+// Flip-mask groups of at most this many terms are split into single-term
+// records: the single-term loop costs about a sixth of the multi-term one (FP64
+// sign sums per pair, terms staged in LDS) at 30 qubits complex64, so up to
+// four passes of it win; larger groups share the pair products.
+constexpr int kExpSplitTerms = 4;
 // persistent workgroups per observable pass: 8 per compute unit (2 resident
 // at a time for the 64 KiB expectation tiles, 4 for the 32 KiB lambda
 // tiles); measured at 30 qubits complex64: 2048 beats 1024 (shorter ranges
@@ -233,16 +238,26 @@ struct ExpGroup {
   const ExpGroupDev* d;
 };
 
-__device__ __forceinline__ ExpGroup exp_group(const ExpPassDev& P, const ExpGroupDev* __restrict__ groups,
-                                              uint64_t base, int gi) {
-  const ExpGroupDev& G = groups[P.grp_begin + gi];
-  ExpGroup r{G.re, G.im, G.lf, G.zl, G.hbit, G.term_begin, G.term_count, &G};
-  if (__popcll(base & G.zg) & 1) {
-    r.re = -r.re;
-    r.im = -r.im;
+// The leading fields of a group record, read one group ahead so that their
+// scalar loads overlap the current group's work; fold() gives the group with
+// its first term's sign for the tile at base folded in.
+struct ExpGroupHead {
+  double re, im;
+  uint64_t zg;
+  uint32_t lf, zl;
+  int hbit, term_begin, term_count;
+  __device__ __forceinline__ explicit ExpGroupHead(const ExpGroupDev& G)
+      : re(G.re), im(G.im), zg(G.zg), lf(G.lf), zl(G.zl), hbit(G.hbit), term_begin(G.term_begin),
+        term_count(G.term_count) {}
+  __device__ __forceinline__ ExpGroup fold(uint64_t base, const ExpGroupDev* d) const {
+    ExpGroup r{re, im, lf, zl, hbit, term_begin, term_count, d};
+    if (__popcll(base & zg) & 1) {
+      r.re = -r.re;
+      r.im = -r.im;
+    }
+    return r;
   }
-  return r;
-}
+};
 
 // Stages the terms of a multi-term group for the tile at base (sign folded in).
 __device__ __forceinline__ void exp_stage_terms(const ExpTermDev* __restrict__ terms, const ExpGroup& G,
@@ -311,16 +326,25 @@ __device__ __forceinline__ R pair_product(const cx<R>& a, const cx<R>& b) {
 template <typename R, bool REAL, bool FULL, int NP, int NT>
 __device__ __forceinline__ double exp_pairs(const cx<R>* tx, const cx<R>* ty, const ExpGroupDev& D, uint32_t pt,
                                             uint32_t TS, uint32_t tid) {
+  // every LDS read of the group is issued before its arithmetic (one wait
+  // instead of one per few pairs)
+  cx<R> a[NP], b[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const uint32_t i0 = uint32_t(k) * NT;
+    if (i0 < TS / 2 && (FULL || i0 + tid < TS / 2)) {
+      a[k] = tx[D.offx[k]];
+      b[k] = ty[D.offy[k]];
+    } else {
+      a[k] = b[k] = cx<R>{R(0), R(0)};  // zero product
+    }
+  }
   double sd = 0.0;
   R sw = R(0);
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
-    const uint32_t i0 = uint32_t(k) * NT;
-    if (i0 >= TS / 2) break;
-    if (FULL || i0 + tid < TS / 2) {
-      const cx<R> a = tx[D.offx[k]], b = ty[D.offy[k]];
-      sw += xor_sign(pair_product<R, REAL>(a, b), D.sgn[k]);
-    }
+    if (uint32_t(k) * NT >= TS / 2) break;
+    sw += xor_sign(pair_product<R, REAL>(a[k], b[k]), D.sgn[k]);
     if ((k & 7) == 7) {  // sums of at most 8 products in the amplitude precision
       sd += double(sw);
       sw = R(0);
@@ -368,9 +392,12 @@ __global__ void __launch_bounds__(kExpThreadsE)
       tr.base = tr.next_base();
       io.fetch(psi, tr.base);
     }
+    const ExpGroupDev* gd = groups + P.grp_begin;
+    ExpGroupHead head(gd[0]);
     __syncthreads();  // tile (and, first time, the group table) in LDS
     for (int gi = 0; gi < P.grp_count; ++gi) {
-      const ExpGroup G = exp_group(P, groups, base, gi);
+      const ExpGroup G = head.fold(base, gd + gi);
+      head = ExpGroupHead(gd[gi + 1 < P.grp_count ? gi + 1 : gi]);
       const int nt = G.term_count;
       if (nt > 1) {
         __syncthreads();
@@ -525,9 +552,12 @@ __global__ void __launch_bounds__(NT)
     R ar[kObsOut], ai[kObsOut];
 #pragma unroll
     for (int k = 0; k < kObsOut; ++k) ar[k] = ai[k] = R(0);
+    const ExpGroupDev* gd = groups + P.grp_begin;
+    ExpGroupHead head(gd[0]);
     __syncthreads();  // tile (and, first time, the group table) in LDS
     for (int gi = 0; gi < P.grp_count; ++gi) {
-      const ExpGroup G = exp_group(P, groups, base, gi);
+      const ExpGroup G = head.fold(base, gd + gi);
+      head = ExpGroupHead(gd[gi + 1 < P.grp_count ? gi + 1 : gi]);
       const int nt = G.term_count;
       if (nt > 1) {
         __syncthreads();
@@ -783,47 +813,53 @@ ExpPlan* build_exp_plan(const qsv_observable* o, qsv_dtype dt) {
     for (int q = 0; q < n; ++q)
       if (!(local >> q & 1)) d.gpos[d.ng++] = q;
     d.grp_begin = int(p->groups.size());
-    d.grp_count = int(chosen.size());
     for (int gi : chosen) {
       const Group& G = groups[gi];
-      ExpGroupDev gd{};
       uint32_t lf = 0;
       for (int q = 0; q < n; ++q)
         if (G.flip >> q & 1) lf |= 1u << lpos[q];
-      gd.lf = lf;
-      gd.hbit = lf ? 31 - __builtin_clz(lf) : 0;
-      gd.term_begin = int(p->terms.size());
-      gd.term_count = G.count;
-      for (int k = G.begin; k < G.begin + G.count; ++k) {
-        ExpTermDev td{};
-        td.re = terms[k].re;
-        td.im = terms[k].im;
-        for (int q = 0; q < n; ++q) {
-          if (!(terms[k].z >> q & 1)) continue;
-          if (lpos[q] >= 0) td.zl |= 1u << lpos[q];
-          else td.zg |= uint64_t(1) << q;
+      // a few terms on one flip mask run as that many single-term records
+      // (the single-term loop, once per term); more share one record
+      const int nrec = G.count <= kExpSplitTerms ? G.count : 1;
+      for (int r = 0; r < nrec; ++r) {
+        ExpGroupDev gd{};
+        gd.lf = lf;
+        gd.hbit = lf ? 31 - __builtin_clz(lf) : 0;
+        gd.term_begin = int(p->terms.size());
+        gd.term_count = nrec > 1 ? 1 : G.count;
+        const int k0 = G.begin + (nrec > 1 ? r : 0);
+        for (int k = k0; k < k0 + gd.term_count; ++k) {
+          ExpTermDev td{};
+          td.re = terms[k].re;
+          td.im = terms[k].im;
+          for (int q = 0; q < n; ++q) {
+            if (!(terms[k].z >> q & 1)) continue;
+            if (lpos[q] >= 0) td.zl |= 1u << lpos[q];
+            else td.zg |= uint64_t(1) << q;
+          }
+          if (k == k0) {
+            gd.re = td.re;
+            gd.im = td.im;
+            gd.zg = td.zg;
+            gd.zl = td.zl;
+          }
+          p->terms.push_back(td);
         }
-        if (k == G.begin) {
-          gd.re = td.re;
-          gd.im = td.im;
-          gd.zg = td.zg;
-          gd.zl = td.zl;
+        // uniform step parts for kExpThreadsE-thread workgroups
+        auto ins0h = [](uint32_t i, int hb) { return ((i >> hb) << (hb + 1)) | (i & ((1u << hb) - 1)); };
+        const uint32_t mt = ins0h(kExpThreadsE - 1, gd.hbit);
+        for (int k = 0; k < kExpSteps; ++k) {
+          const uint32_t xs = lf ? ins0h(uint32_t(k) * kExpThreadsE, gd.hbit) : uint32_t(k) * kExpThreadsE;
+          if (lf && k < kExpSteps / 2) {
+            gd.offx[k] = xs;
+            gd.offy[k] = xs ^ (lf & ~mt);
+          }
+          if (!lf || k < kExpSteps / 2) gd.sgn[k] = uint32_t(__builtin_popcount(xs & gd.zl) & 1) << 31;
         }
-        p->terms.push_back(td);
+        p->groups.push_back(gd);
       }
-      // uniform step parts for kExpThreadsE-thread workgroups
-      auto ins0h = [](uint32_t i, int hb) { return ((i >> hb) << (hb + 1)) | (i & ((1u << hb) - 1)); };
-      const uint32_t mt = ins0h(kExpThreadsE - 1, gd.hbit);
-      for (int k = 0; k < kExpSteps; ++k) {
-        const uint32_t xs = lf ? ins0h(uint32_t(k) * kExpThreadsE, gd.hbit) : uint32_t(k) * kExpThreadsE;
-        if (lf && k < kExpSteps / 2) {
-          gd.offx[k] = xs;
-          gd.offy[k] = xs ^ (lf & ~mt);
-        }
-        if (!lf || k < kExpSteps / 2) gd.sgn[k] = uint32_t(__builtin_popcount(xs & gd.zl) & 1) << 31;
-      }
-      p->groups.push_back(gd);
     }
+    d.grp_count = int(p->groups.size()) - d.grp_begin;
     p->passes.push_back(d);
   }
   return p;
