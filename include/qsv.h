@@ -339,11 +339,12 @@ int qsv_observable_passes(const qsv_observable* o, qsv_dtype dtype, int* passes)
 /* <psi|O|psi> accumulated in double (section 4.5, get_expectation_value). The
  * state is not normalised first (basic gates need not be unitary). Flip masks
  * are packed into passes that each read the state once (a mask with more flip
- * qubits than a tile holds gets a pass of its own). complex64: a single-term
- * string's pair products, and each thread's sum of 8 of them per tile, are
- * formed in FP32 (|error| <= 9 x 2^-24 x sum|alpha| x <psi|psi> beyond the
- * stored amplitudes), every other sum in double. Synchronises the state's
- * stream. */
+ * qubits than a tile holds gets a pass of its own); the terms of a flip mask
+ * shared by at most four strings are evaluated one by one, larger sets
+ * together. complex64: a single-term evaluation's pair products, and each
+ * thread's sum of 8 of them per tile, are formed in FP32 (|error| <= 9 x
+ * 2^-24 x sum|alpha| x <psi|psi> beyond the stored amplitudes), every other
+ * sum in double. Synchronises the state's stream. */
 int qsv_expectation(const qsv_state* s, const qsv_observable* o, double* out);
 
 /* qsv_expectation for callers that cannot allocate device memory (code under
@@ -355,8 +356,9 @@ int qsv_expectation(const qsv_state* s, const qsv_observable* o, double* out);
  * until the process ends; the call makes no hipMalloc, hipFree or pinned-
  * memory allocation (host-side plan tables are built and cached on the
  * observable as for qsv_expectation). The tables of one pass cost about
- * 250 bytes, of one flip-mask group about 180 and of one term 32, plus 16 KiB
- * of partials: some 5000 single-term strings fit. Calls that overlap on one
+ * 250 bytes, of one flip-mask record about 180 (one per term for a mask
+ * shared by at most four strings, else one per mask) and of one term 32, plus
+ * 16 KiB of partials: some 5000 strings with distinct flip masks fit. Calls that overlap on one
  * GPU share the array and race; calls in order on one stream do not (the
  * array keeps the last call's contents, and each call rewrites what it
  * reads). Synchronises the state's stream.
