@@ -214,3 +214,45 @@ def test_wide_flip_masks(dt, grid, monkeypatch):
     assert abs(e - O.energy(n, gates, theta, obs_t)) <= GRAD_TOL[dt] * scale
     err = np.max(np.abs(g[slots] - O.param_shift_grad(n, gates, theta, obs_t, slots=slots)))
     assert err <= GRAD_TOL[dt] * scale, err
+
+
+def shared_mask_observable(n, seed):
+    """Flip masks shared by 2, 3, 4, 5 and 9 strings (the X/Y pattern fixed,
+    the Z qubits varied): masks of at most four strings run as single-term
+    records, larger sets as one shared record; with 60 more random strings
+    the planner takes several passes and moves groups between them."""
+    rng = np.random.default_rng(seed)
+    obs = W.random_pauli_observable(n, 60, (2, 5), seed_key=(23, n, seed))
+    for count in (2, 3, 4, 5, 9):
+        flips = rng.choice(n, size=int(rng.integers(1, 4)), replace=False)
+        xy = [(int(q), int(rng.integers(1, 3))) for q in flips]
+        others = [q for q in range(n) if q not in set(int(f) for f in flips)]
+        for _ in range(count):
+            zs = rng.choice(others, size=int(rng.integers(0, 4)), replace=False)
+            obs.append((float(rng.standard_normal()), xy + [(int(q), 3) for q in zs]))
+    # the pure-Z mask shared by several strings too
+    for k in range(3):
+        obs.append((0.2 * (k + 1), [(k, 3), (n - 1 - k, 3)]))
+    return obs
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("grid", [0, 5])
+def test_shared_flip_masks_vs_oracle(dt, grid, monkeypatch):
+    if grid:
+        monkeypatch.setenv("QSV_EXPECT_GRID", str(grid))
+    rng = np.random.default_rng(300 + grid)
+    for n in (14, 16):
+        psi = rand_state(rng, n)
+        ref_in = as_loaded(psi, dt)
+        obs_t = shared_mask_observable(n, 7 + n)
+        obs = Observable(n, obs_t)
+        assert obs.passes(dt) >= 2
+        scale = sum(abs(c) for c, _ in obs_t)
+        s, out = State(n, dt), State(n, dt)
+        s.load(psi)
+        e = expectation(s, obs)
+        assert abs(e - O.expectation(ref_in, obs_t)) <= E_LOADED[dt] * scale, (n, dt, grid)
+        apply_observable(s, obs, out)
+        err = np.max(np.abs(out.store() - O.apply_observable(ref_in, obs_t)))
+        assert err <= LAM_TOL[dt] * scale, (n, dt, grid, err)
