@@ -88,9 +88,10 @@ constexpr int kExpLdsTerms = 128;
 // four passes of it win; larger groups share the pair products.
 constexpr int kExpSplitTerms = 4;
 // persistent workgroups per observable pass: 8 per compute unit (2 resident
-// at a time for the 64 KiB expectation tiles, 4 for the 32 KiB lambda
-// tiles); measured at 30 qubits complex64: 2048 beats 1024 (shorter ranges
-// even out the tail); QSV_EXPECT_GRID overrides
+// at a time for the 512-thread expectation workgroups over 64 KiB tiles, 1
+// for the lambda workgroups, which their registers limit); measured at 30
+// qubits complex64: 2048 beats 1024 (shorter ranges even out the tail);
+// QSV_EXPECT_GRID overrides
 constexpr int kExpGrid = 2048;
 
 // Persistent grid of the expectation and lambda passes: kExpGrid, or the
@@ -287,7 +288,9 @@ __device__ __forceinline__ void exp_term(const ExpTermDev* __restrict__ terms, c
 }
 
 // Tile qubits of the fixed-size expectation and lambda kernel variants (64
-// KiB tiles), and the lambda workgroup size (8 outputs per thread).
+// KiB tiles), and the lambda workgroup size and outputs per thread (1024
+// threads: 8 complex64 or 4 complex128 outputs each; 512 threads with 8
+// complex128 outputs took 181 VGPRs, two wavefronts per SIMD).
 template <typename R>
 __host__ __device__ constexpr int exp_tile_bits() {
   return sizeof(R) == 4 ? 13 : 12;
@@ -298,7 +301,11 @@ __host__ __device__ constexpr int obs_tile_bits() {
 }
 template <typename R>
 __host__ __device__ constexpr int obs_threads() {
-  return sizeof(R) == 4 ? 1024 : 512;
+  return 1024;
+}
+template <typename R>
+__host__ __device__ constexpr int obs_out() {
+  return (1 << obs_tile_bits<R>()) / obs_threads<R>();
 }
 
 // Re (REAL) or Im of conj(b) a. complex64: formed in FP32 (relative error
@@ -492,7 +499,6 @@ __global__ void __launch_bounds__(kExpThreads) k_zero_amps(R* __restrict__ a, ui
 // with c(x) = sum over the group's terms of alpha i^nY (-1)^|x & z| (in FP64),
 // summed per pass in the amplitude precision (that of lambda itself); the
 // first pass writes lambda, later passes add to it.
-constexpr int kObsOut = 8;  // outputs per thread: 2^12 / 512
 
 // One single-term group's contribution to this thread's outputs: lambda_y +=
 // c psi_{y ^ F} (REAL) or i c psi_{y ^ F} with c = +-coefficient, the sign of
@@ -500,8 +506,9 @@ constexpr int kObsOut = 8;  // outputs per thread: 2^12 / 512
 template <typename R, bool REAL, bool FIXED, int NT>
 __device__ __forceinline__ void obs_single(const cx<R>* t, uint32_t tid, uint32_t lf, uint32_t zl, uint32_t pt,
                                            R cm, uint32_t TS, R* ar, R* ai) {
+  constexpr int KO = obs_out<R>();
 #pragma unroll
-  for (int k = 0; k < kObsOut; ++k) {
+  for (int k = 0; k < KO; ++k) {
     const uint32_t y = tid + uint32_t(k) * NT;
     if (FIXED || y < TS) {
       const cx<R> v = t[y ^ lf];
@@ -518,26 +525,27 @@ __device__ __forceinline__ void obs_single(const cx<R>* t, uint32_t tid, uint32_
 }
 
 // FIXED: the tile has obs_tile_bits<R>() qubits and every thread's outputs
-// exist (complex64: 2^13 = 8 x 1024, complex128: 2^12 = 8 x 512). Tiles of
-// at most kObsOut x NT amplitudes.
+// exist (complex64: 2^13 = 8 x 1024, complex128: 2^12 = 4 x 1024). Tiles of
+// at most obs_out<R>() x NT amplitudes.
 template <typename R, bool FIXED, int NT>
 __global__ void __launch_bounds__(NT)
     k_apply_obs_tile(const R* __restrict__ psi, R* __restrict__ lam, const ExpPassDev* __restrict__ passes,
                      int pass_idx, const ExpGroupDev* __restrict__ groups,
                      const ExpTermDev* __restrict__ terms, int accumulate, uint64_t ntiles) {
+  constexpr int KO = obs_out<R>();
   extern __shared__ __align__(16) char smem[];
   __shared__ ExpTermLds et[kExpLdsTerms];
   cx<R>* t = reinterpret_cast<cx<R>*>(smem);
   const ExpPassDev& P = passes[pass_idx];
   const uint32_t TS = FIXED ? (1u << obs_tile_bits<R>()) : (1u << P.L);
   const uint32_t tid = threadIdx.x;
-  // (the stream's maximum counts 8-byte units: a complex128 tile of 8 x NT
-  // amplitudes is 16 x NT of them)
-  ExpTileStream<R, NT, 0, kObsOut * NT * int(sizeof(R) / 4)> io(P);
+  // (the stream's maximum counts 8-byte units: a complex128 tile of 4 x NT
+  // amplitudes is 8 x NT of them)
+  ExpTileStream<R, NT, 0, obs_out<R>() * NT * int(sizeof(R) / 4)> io(P);
   const uint64_t yt = exp_place(P, tid);
-  uint64_t yk[kObsOut];
+  uint64_t yk[KO];
 #pragma unroll
-  for (int k = 0; k < kObsOut; ++k) yk[k] = exp_place(P, uint32_t(k) * NT);
+  for (int k = 0; k < KO; ++k) yk[k] = exp_place(P, uint32_t(k) * NT);
   ExpTileRange tr(P, ntiles);
   if (tr.g < tr.end) io.fetch(psi, tr.base);
   for (; tr.g < tr.end; ++tr.g) {
@@ -549,9 +557,9 @@ __global__ void __launch_bounds__(NT)
       io.fetch(psi, tr.base);
     }
     // per-pass sums in the amplitude precision (lambda is stored in it)
-    R ar[kObsOut], ai[kObsOut];
+    R ar[KO], ai[KO];
 #pragma unroll
-    for (int k = 0; k < kObsOut; ++k) ar[k] = ai[k] = R(0);
+    for (int k = 0; k < KO; ++k) ar[k] = ai[k] = R(0);
     const ExpGroupDev* gd = groups + P.grp_begin;
     ExpGroupHead head(gd[0]);
     __syncthreads();  // tile (and, first time, the group table) in LDS
@@ -574,7 +582,7 @@ __global__ void __launch_bounds__(NT)
           obs_single<R, false, FIXED, NT>(t, tid, lf, G.zl, pt, R(G.im), TS, ar, ai);
       } else {
 #pragma unroll
-        for (int k = 0; k < kObsOut; ++k) {
+        for (int k = 0; k < KO; ++k) {
           const uint32_t y = tid + uint32_t(k) * NT;
           if (y < TS) {
             const uint32_t x = y ^ lf;
@@ -595,7 +603,7 @@ __global__ void __launch_bounds__(NT)
       }
     }
 #pragma unroll
-    for (int k = 0; k < kObsOut; ++k) {
+    for (int k = 0; k < KO; ++k) {
       if (!FIXED && tid + uint32_t(k) * NT >= TS) continue;
       cx<R> r;
       if (accumulate) {
@@ -1022,9 +1030,9 @@ int apply_obs_tiled_t(const qsv_state* in, qsv_observable* o, qsv_state* out) {
   if (rc) return rc;
   const uint64_t tiles = dim(in->n - pl->L);
   const size_t lds = (size_t(1) << pl->L) * sizeof(cx<R>);
-  // compile-time output count when every thread has kObsOut outputs
+  // compile-time output count when every thread has obs_out<R>() outputs
   constexpr int NTo = obs_threads<R>();
-  const bool fixed = pl->L == obs_tile_bits<R>() && (size_t(1) << pl->L) == size_t(kObsOut) * NTo;
+  const bool fixed = pl->L == obs_tile_bits<R>() && (size_t(1) << pl->L) == size_t(obs_out<R>()) * NTo;
   QSV_HIP_CHECK(hipFuncSetAttribute(fixed ? reinterpret_cast<const void*>(&k_apply_obs_tile<R, true, NTo>)
                                           : reinterpret_cast<const void*>(&k_apply_obs_tile<R, false, NTo>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
