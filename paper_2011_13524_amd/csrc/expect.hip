@@ -59,7 +59,7 @@ struct ExpGroupDev {
   uint32_t zl;     // first term: sign mask on local qubits
   int hbit;        // a set bit of lf (pairs are enumerated with it clear)
   int term_begin, term_count;
-  uint32_t pad;
+  uint32_t kind;  // ExpKind: which loop evaluates the record
   // lf != 0, step k (pair index k * kExpThreadsE + thread): the step part of
   // x = ins0(pair index, hbit) and of y = x ^ lf outside the thread's bits
   uint32_t offx[kExpSteps / 2], offy[kExpSteps / 2];
@@ -67,6 +67,11 @@ struct ExpGroupDev {
   // is k * kExpThreadsE
   uint32_t sgn[kExpSteps];
 };
+
+// Record kinds (set by the planner): one term with flip mask 0; several
+// terms with flip mask 0; one term with a flip mask and a real (REAL) or
+// imaginary (IMAG) coefficient alpha i^nY; several terms with a flip mask.
+enum ExpKind : uint32_t { kExpZ1 = 0, kExpZN = 1, kExpFlipRe = 2, kExpFlipIm = 3, kExpFlipN = 4 };
 
 struct ExpTermDev {
   double re, im;  // alpha * i^nY
@@ -247,9 +252,10 @@ struct ExpGroupHead {
   uint64_t zg;
   uint32_t lf, zl;
   int hbit, term_begin, term_count;
+  uint32_t kind;
   __device__ __forceinline__ explicit ExpGroupHead(const ExpGroupDev& G)
       : re(G.re), im(G.im), zg(G.zg), lf(G.lf), zl(G.zl), hbit(G.hbit), term_begin(G.term_begin),
-        term_count(G.term_count) {}
+        term_count(G.term_count), kind(G.kind) {}
   __device__ __forceinline__ ExpGroup fold(uint64_t base, const ExpGroupDev* d) const {
     ExpGroup r{re, im, lf, zl, hbit, term_begin, term_count, d};
     if (__popcll(base & zg) & 1) {
@@ -402,16 +408,33 @@ __global__ void __launch_bounds__(kExpThreadsE)
     const ExpGroupDev* gd = groups + P.grp_begin;
     ExpGroupHead head(gd[0]);
     __syncthreads();  // tile (and, first time, the group table) in LDS
-    for (int gi = 0; gi < P.grp_count; ++gi) {
-      const ExpGroup G = head.fold(base, gd + gi);
-      head = ExpGroupHead(gd[gi + 1 < P.grp_count ? gi + 1 : gi]);
+    for (int left = P.grp_count; left > 0; --left, ++gd) {
+      const ExpGroup G = head.fold(base, gd);
+      const uint32_t kind = head.kind;
+      head = ExpGroupHead(gd[1]);  // (after a pass's last record: the next pass's first, or the spare)
       const int nt = G.term_count;
+      if (kind == kExpFlipRe || kind == kExpFlipIm) {
+        // one term (the common case for random strings). A Hermitian term's
+        // coefficient alpha i^nY is real (nY even) or imaginary (nY odd):
+        // only Re or Im of w = conj(psi[y]) psi[x] counts
+        const int hb = G.hbit;
+        const uint32_t xt = ins0(tid, hb);
+        const uint32_t mt = ins0(NT - 1, hb);  // local bits of the thread part
+        const cx<R>* tx = t + xt;
+        const cx<R>* ty = t + (xt ^ (G.lf & mt));
+        uint32_t pt = uint32_t(__popc(xt & G.zl) & 1) << 31;
+        if (kind == kExpFlipRe)
+          acc += 2.0 * G.re * exp_pairs<R, true, FULL, NA / 2, NT>(tx, ty, *G.d, pt, TS, tid);
+        else
+          acc -= 2.0 * G.im * exp_pairs<R, false, FULL, NA / 2, NT>(tx, ty, *G.d, pt, TS, tid);
+        continue;
+      }
       if (nt > 1) {
         __syncthreads();
         exp_stage_terms(terms, G, base, et);
         __syncthreads();
       }
-      if (G.lf == 0 && nt == 1) {
+      if (kind == kExpZ1) {
         // sum of +-|psi_x|^2: thread part of the sign once, uniform part per step
         uint32_t pt = uint32_t(__popc(tid & G.zl) & 1) << 31;
         double sum = 0.0;
@@ -425,7 +448,7 @@ __global__ void __launch_bounds__(kExpThreadsE)
           }
         }
         acc += G.re * xor_sign(sum, pt);
-      } else if (G.lf == 0) {
+      } else if (kind == kExpZN) {
         for (uint32_t j = tid; j < TS; j += NT) {
           const cx<R> a = t[j];
           double c = 0.0;
@@ -437,40 +460,25 @@ __global__ void __launch_bounds__(kExpThreadsE)
           }
           acc += (double(a.re) * a.re + double(a.im) * a.im) * c;
         }
-      } else {
+      } else {  // kExpFlipN
         const int hb = G.hbit;
         const uint32_t lf = G.lf;
-        if (nt == 1) {
-          // one term (the common case for random strings). A Hermitian term's
-          // coefficient alpha i^nY is real (nY even) or imaginary (nY odd):
-          // only Re or Im of w = conj(psi[y]) psi[x] counts
-          const uint32_t xt = ins0(tid, hb);
-          const uint32_t mt = ins0(NT - 1, hb);  // local bits of the thread part
-          const cx<R>* tx = t + xt;
-          const cx<R>* ty = t + (xt ^ (lf & mt));
-          uint32_t pt = uint32_t(__popc(xt & G.zl) & 1) << 31;
-          if (G.im == 0.0)
-            acc += 2.0 * G.re * exp_pairs<R, true, FULL, NA / 2, NT>(tx, ty, *G.d, pt, TS, tid);
-          else
-            acc -= 2.0 * G.im * exp_pairs<R, false, FULL, NA / 2, NT>(tx, ty, *G.d, pt, TS, tid);
-        } else {
-          for (uint32_t i = tid; i < TS / 2; i += NT) {
-            const uint32_t x = ins0(i, hb);
-            const cx<R> a = t[x], bb = t[x ^ lf];
-            // w = conj(psi[y]) psi[x]
-            const double wr = double(bb.re) * a.re + double(bb.im) * a.im;
-            const double wi = double(bb.re) * a.im - double(bb.im) * a.re;
-            double cr = 0.0, ci = 0.0;
-            for (int k = 0; k < nt; ++k) {
-              double re, im;
-              uint32_t zl;
-              exp_term(terms, et, G, base, k, re, im, zl);
-              const bool neg = __popc(x & zl) & 1;
-              cr += neg ? -re : re;
-              ci += neg ? -im : im;
-            }
-            acc += 2.0 * (wr * cr - wi * ci);
+        for (uint32_t i = tid; i < TS / 2; i += NT) {
+          const uint32_t x = ins0(i, hb);
+          const cx<R> a = t[x], bb = t[x ^ lf];
+          // w = conj(psi[y]) psi[x]
+          const double wr = double(bb.re) * a.re + double(bb.im) * a.im;
+          const double wi = double(bb.re) * a.im - double(bb.im) * a.re;
+          double cr = 0.0, ci = 0.0;
+          for (int k = 0; k < nt; ++k) {
+            double re, im;
+            uint32_t zl;
+            exp_term(terms, et, G, base, k, re, im, zl);
+            const bool neg = __popc(x & zl) & 1;
+            cr += neg ? -re : re;
+            ci += neg ? -im : im;
           }
+          acc += 2.0 * (wr * cr - wi * ci);
         }
       }
     }
@@ -565,7 +573,7 @@ __global__ void __launch_bounds__(NT)
     __syncthreads();  // tile (and, first time, the group table) in LDS
     for (int gi = 0; gi < P.grp_count; ++gi) {
       const ExpGroup G = head.fold(base, gd + gi);
-      head = ExpGroupHead(gd[gi + 1 < P.grp_count ? gi + 1 : gi]);
+      head = ExpGroupHead(gd[gi + 1]);  // (see k_expect_tile)
       const int nt = G.term_count;
       if (nt > 1) {
         __syncthreads();
@@ -895,6 +903,9 @@ ExpPlan* build_exp_plan(const qsv_observable* o, qsv_dtype dt) {
         gd.hbit = lf ? 31 - __builtin_clz(lf) : 0;
         gd.term_begin = int(p->terms.size());
         gd.term_count = nrec > 1 ? 1 : G.count;
+        const double im0 = terms[G.begin + (nrec > 1 ? r : 0)].im;
+        gd.kind = lf == 0 ? (gd.term_count == 1 ? kExpZ1 : kExpZN)
+                          : (gd.term_count > 1 ? kExpFlipN : (im0 == 0.0 ? kExpFlipRe : kExpFlipIm));
         const int k0 = G.begin + (nrec > 1 ? r : 0);
         for (int k = k0; k < k0 + gd.term_count; ++k) {
           ExpTermDev td{};
@@ -930,6 +941,9 @@ ExpPlan* build_exp_plan(const qsv_observable* o, qsv_dtype dt) {
     d.grp_count = int(p->groups.size()) - d.grp_begin;
     p->passes.push_back(d);
   }
+  // the kernels read each record's successor ahead of use: one spare record
+  // after the last pass keeps that read inside the table
+  if (!p->passes.empty()) p->groups.push_back(ExpGroupDev{});
   return p;
 }
 
