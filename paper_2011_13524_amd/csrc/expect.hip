@@ -60,6 +60,9 @@ struct ExpGroupDev {
   int hbit;        // a set bit of lf (pairs are enumerated with it clear)
   int term_begin, term_count;
   uint32_t kind;  // ExpKind: which loop evaluates the record
+  // lf != 0, kExpThreadsE-thread workgroups: bits below hbit, and the flip
+  // bits inside the thread part of x = ins0(pair index, hbit)
+  uint32_t hmask, lft;
   // lf != 0, step k (pair index k * kExpThreadsE + thread): the step part of
   // x = ins0(pair index, hbit) and of y = x ^ lf outside the thread's bits
   uint32_t offx[kExpSteps / 2], offy[kExpSteps / 2];
@@ -241,6 +244,7 @@ struct ExpGroup {
   double re, im;
   uint32_t lf, zl;
   int hbit, term_begin, term_count;
+  uint32_t hmask, lft;
   const ExpGroupDev* d;
 };
 
@@ -252,17 +256,13 @@ struct ExpGroupHead {
   uint64_t zg;
   uint32_t lf, zl;
   int hbit, term_begin, term_count;
-  uint32_t kind;
+  uint32_t kind, hmask, lft;
   __device__ __forceinline__ explicit ExpGroupHead(const ExpGroupDev& G)
       : re(G.re), im(G.im), zg(G.zg), lf(G.lf), zl(G.zl), hbit(G.hbit), term_begin(G.term_begin),
-        term_count(G.term_count), kind(G.kind) {}
+        term_count(G.term_count), kind(G.kind), hmask(G.hmask), lft(G.lft) {}
   __device__ __forceinline__ ExpGroup fold(uint64_t base, const ExpGroupDev* d) const {
-    ExpGroup r{re, im, lf, zl, hbit, term_begin, term_count, d};
-    if (__popcll(base & zg) & 1) {
-      r.re = -r.re;
-      r.im = -r.im;
-    }
-    return r;
+    const uint32_t sg = uint32_t(__popcll(base & zg) & 1) << 31;
+    return ExpGroup{xor_sign(re, sg), xor_sign(im, sg), lf, zl, hbit, term_begin, term_count, hmask, lft, d};
   }
 };
 
@@ -417,11 +417,9 @@ __global__ void __launch_bounds__(kExpThreadsE)
         // one term (the common case for random strings). A Hermitian term's
         // coefficient alpha i^nY is real (nY even) or imaginary (nY odd):
         // only Re or Im of w = conj(psi[y]) psi[x] counts
-        const int hb = G.hbit;
-        const uint32_t xt = ins0(tid, hb);
-        const uint32_t mt = ins0(NT - 1, hb);  // local bits of the thread part
+        const uint32_t xt = ((tid & ~G.hmask) << 1) | (tid & G.hmask);  // ins0(tid, hbit)
         const cx<R>* tx = t + xt;
-        const cx<R>* ty = t + (xt ^ (G.lf & mt));
+        const cx<R>* ty = t + (xt ^ G.lft);
         uint32_t pt = uint32_t(__popc(xt & G.zl) & 1) << 31;
         if (kind == kExpFlipRe)
           acc += 2.0 * G.re * exp_pairs<R, true, FULL, NA / 2, NT>(tx, ty, *G.d, pt, TS, tid);
@@ -927,6 +925,8 @@ ExpPlan* build_exp_plan(const qsv_observable* o, qsv_dtype dt) {
         // uniform step parts for kExpThreadsE-thread workgroups
         auto ins0h = [](uint32_t i, int hb) { return ((i >> hb) << (hb + 1)) | (i & ((1u << hb) - 1)); };
         const uint32_t mt = ins0h(kExpThreadsE - 1, gd.hbit);
+        gd.hmask = (1u << gd.hbit) - 1;
+        gd.lft = lf & mt;
         for (int k = 0; k < kExpSteps; ++k) {
           const uint32_t xs = lf ? ins0h(uint32_t(k) * kExpThreadsE, gd.hbit) : uint32_t(k) * kExpThreadsE;
           if (lf && k < kExpSteps / 2) {
