@@ -66,8 +66,8 @@ struct ExpGroupDev {
   // lf != 0, step k (pair index k * kExpThreadsE + thread): the step part of
   // x = ins0(pair index, hbit) and of y = x ^ lf outside the thread's bits
   uint32_t offx[kExpSteps / 2], offy[kExpSteps / 2];
-  // bit 31: parity of (step part of x) & zl; for lf == 0 the step part of x
-  // is k * kExpThreadsE
+  // bit 31: parity of (step part of x) & zl (complex64 plans, lf != 0: as
+  // the float +-1.0); for lf == 0 the step part of x is k * kExpThreadsE
   uint32_t sgn[kExpSteps];
 };
 
@@ -357,7 +357,10 @@ __device__ __forceinline__ double exp_pairs(const cx<R>* tx, const cx<R>* ty, co
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
     if (uint32_t(k) * NT >= TS / 2) break;
-    sw += xor_sign(pair_product<R, REAL>(a[k], b[k]), D.sgn[k]);
+    if constexpr (sizeof(R) == 4)  // complex64 plans store the step sign as +-1.0f
+      sw = fmaf(__uint_as_float(D.sgn[k]), pair_product<R, REAL>(a[k], b[k]), sw);
+    else
+      sw += xor_sign(pair_product<R, REAL>(a[k], b[k]), D.sgn[k]);
     if ((k & 7) == 7) {  // sums of at most 8 products in the amplitude precision
       sd += double(sw);
       sw = R(0);
@@ -934,6 +937,10 @@ ExpPlan* build_exp_plan(const qsv_observable* o, qsv_dtype dt) {
             gd.offy[k] = xs ^ (lf & ~mt);
           }
           if (!lf || k < kExpSteps / 2) gd.sgn[k] = uint32_t(__builtin_popcount(xs & gd.zl) & 1) << 31;
+          // flip records of complex64 plans: the sign as +-1.0f, applied by
+          // one FMA into the running sum (exact: the same result as a sign
+          // flip and an add)
+          if (lf && k < kExpSteps / 2 && dt == QSV_C64) gd.sgn[k] |= 0x3f800000u;
         }
         p->groups.push_back(gd);
       }
