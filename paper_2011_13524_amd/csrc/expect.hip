@@ -777,8 +777,8 @@ uint64_t pick_pass_local(const std::vector<uint64_t>& hi, uint64_t low, int L) {
 // Moves flip-mask groups from heavily loaded passes to lighter ones whose
 // local set also holds their mask (the packing above fills the first passes
 // and leaves the last ones light). Cost of a pass in units of one
-// single-term record's work (complex64, 30 qubits: 0.165 ms each), measured:
-// max(7.6, 2.1 + records) -- at least its read of the state, and a fixed
+// single-term record's work (complex64, 30 qubits: 0.12 ms each), measured:
+// max(10.9, 4.9 + records) -- at least its read of the state, and a fixed
 // part per tile on top of its records; a shared record of more than
 // kExpSplitTerms terms costs about six. A group moves when the modelled sum
 // drops; deterministic (passes by load, groups in order).
@@ -786,7 +786,7 @@ void rebalance_passes(const std::vector<Group>& groups, const std::vector<uint64
                       std::vector<std::vector<int>>& pchosen) {
   const size_t np = plocal.size();
   auto weight = [&](int gi) { return groups[gi].count <= kExpSplitTerms ? double(groups[gi].count) : 6.0; };
-  auto cost = [](double g) { return std::max(7.6, 2.1 + g); };
+  auto cost = [](double g) { return std::max(10.9, 4.9 + g); };
   std::vector<double> load(np, 0.0);
   for (size_t pi = 0; pi < np; ++pi)
     for (int gi : pchosen[pi]) load[pi] += weight(gi);
