@@ -572,24 +572,26 @@ __global__ void __launch_bounds__(NT)
     const ExpGroupDev* gd = groups + P.grp_begin;
     ExpGroupHead head(gd[0]);
     __syncthreads();  // tile (and, first time, the group table) in LDS
-    for (int gi = 0; gi < P.grp_count; ++gi) {
-      const ExpGroup G = head.fold(base, gd + gi);
-      head = ExpGroupHead(gd[gi + 1]);  // (see k_expect_tile)
-      const int nt = G.term_count;
-      if (nt > 1) {
-        __syncthreads();
-        exp_stage_terms(terms, G, base, et);
-        __syncthreads();
-      }
+    for (int left = P.grp_count; left > 0; --left, ++gd) {
+      const ExpGroup G = head.fold(base, gd);
+      const uint32_t kind = head.kind;
+      head = ExpGroupHead(gd[1]);  // (see k_expect_tile)
       const uint32_t lf = G.lf;
-      if (nt == 1) {
-        // alpha i^nY is real or imaginary: lambda += c psi or i c psi
+      if (kind == kExpZ1 || kind == kExpFlipRe || kind == kExpFlipIm) {
+        // alpha i^nY is real or imaginary (a Z-only string's is real):
+        // lambda += c psi or i c psi
         const uint32_t pt = (__popc((tid ^ lf) & G.zl) & 1);
-        if (G.im == 0.0)
+        if (kind != kExpFlipIm)
           obs_single<R, true, FIXED, NT>(t, tid, lf, G.zl, pt, R(G.re), TS, ar, ai);
         else
           obs_single<R, false, FIXED, NT>(t, tid, lf, G.zl, pt, R(G.im), TS, ar, ai);
-      } else {
+        continue;
+      }
+      const int nt = G.term_count;
+      __syncthreads();
+      exp_stage_terms(terms, G, base, et);
+      __syncthreads();
+      {
 #pragma unroll
         for (int k = 0; k < KO; ++k) {
           const uint32_t y = tid + uint32_t(k) * NT;
