@@ -356,9 +356,9 @@ int qsv_expectation(const qsv_state* s, const qsv_observable* o, double* out);
  * until the process ends; the call makes no hipMalloc, hipFree or pinned-
  * memory allocation (host-side plan tables are built and cached on the
  * observable as for qsv_expectation). The tables of one pass cost about
- * 250 bytes, of one flip-mask record about 180 (one per term for a mask
+ * 250 bytes, of one flip-mask record about 184 (one per term for a mask
  * shared by at most four strings, else one per mask) and of one term 32, plus
- * 16 KiB of partials: some 5000 strings with distinct flip masks fit. Calls that overlap on one
+ * 16 KiB of partials: some 4700 strings with distinct flip masks fit. Calls that overlap on one
  * GPU share the array and race; calls in order on one stream do not (the
  * array keeps the last call's contents, and each call rewrites what it
  * reads). Synchronises the state's stream.

@@ -38,7 +38,7 @@ def test_noalloc_matches_expectation(dt):
 
 def test_noalloc_refuses_oversized_observable():
     # 8000 strings of weight 6 on 22 qubits: ~8000 distinct flip masks, whose
-    # group tables alone (~176 bytes each) exceed the 1 MiB scratch
+    # record tables alone (~184 bytes each) exceed the 1 MiB scratch
     n = 22
     s = State(n, "c64")
     obs = Observable(n, W.random_pauli_observable(n, 8000, 6, seed_key=(62,)))
