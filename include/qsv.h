@@ -340,7 +340,7 @@ int qsv_observable_passes(const qsv_observable* o, qsv_dtype dtype, int* passes)
  * state is not normalised first (basic gates need not be unitary). Flip masks
  * are packed into passes that each read the state once (a mask with more flip
  * qubits than a tile holds gets a pass of its own); the terms of a flip mask
- * shared by at most four strings are evaluated one by one, larger sets
+ * shared by at most eight strings are evaluated one by one, larger sets
  * together. complex64: a single-term evaluation's pair products, and each
  * thread's sum of 8 of them per tile, are formed in FP32 (|error| <= 9 x
  * 2^-24 x sum|alpha| x <psi|psi> beyond the stored amplitudes), every other
@@ -357,7 +357,7 @@ int qsv_expectation(const qsv_state* s, const qsv_observable* o, double* out);
  * memory allocation (host-side plan tables are built and cached on the
  * observable as for qsv_expectation). The tables of one pass cost about
  * 250 bytes, of one flip-mask record about 184 (one per term for a mask
- * shared by at most four strings, else one per mask) and of one term 32, plus
+ * shared by at most eight strings, else one per mask) and of one term 32, plus
  * 16 KiB of partials: some 4700 strings with distinct flip masks fit. Calls that overlap on one
  * GPU share the array and race; calls in order on one stream do not (the
  * array keeps the last call's contents, and each call rewrites what it

@@ -91,10 +91,11 @@ struct ExpTermLds {
 };
 constexpr int kExpLdsTerms = 128;
 // Flip-mask groups of at most this many terms are split into single-term
-// records: the single-term loop costs about a sixth of the multi-term one (FP64
-// sign sums per pair, terms staged in LDS) at 30 qubits complex64, so up to
-// four passes of it win; larger groups share the pair products.
-constexpr int kExpSplitTerms = 4;
+// records: a shared multi-term record (FP64 sign sums per pair, terms staged
+// in LDS) costs about six single-term ones or more; splitting masks of up to
+// eight terms (not only up to four) took the 24-qubit 500-term lambda pass
+// from 0.279 to 0.254 ms (complex64). Larger groups share the pair products.
+constexpr int kExpSplitTerms = 8;
 // persistent workgroups per observable pass: 8 per compute unit (2 resident
 // at a time for the 512-thread expectation workgroups over 64 KiB tiles, 1
 // for the lambda workgroups, which their registers limit); measured at 30

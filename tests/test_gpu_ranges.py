@@ -217,13 +217,13 @@ def test_wide_flip_masks(dt, grid, monkeypatch):
 
 
 def shared_mask_observable(n, seed):
-    """Flip masks shared by 2, 3, 4, 5 and 9 strings (the X/Y pattern fixed,
-    the Z qubits varied): masks of at most four strings run as single-term
+    """Flip masks shared by 2, 3, 4, 5, 8 and 9 strings (the X/Y pattern fixed,
+    the Z qubits varied): masks of at most eight strings run as single-term
     records, larger sets as one shared record; with 60 more random strings
     the planner takes several passes and moves groups between them."""
     rng = np.random.default_rng(seed)
     obs = W.random_pauli_observable(n, 60, (2, 5), seed_key=(23, n, seed))
-    for count in (2, 3, 4, 5, 9):
+    for count in (2, 3, 4, 5, 8, 9):
         flips = rng.choice(n, size=int(rng.integers(1, 4)), replace=False)
         xy = [(int(q), int(rng.integers(1, 3))) for q in flips]
         others = [q for q in range(n) if q not in set(int(f) for f in flips)]
